@@ -1,0 +1,233 @@
+/*
+ * pact.h -- C ABI of libpact, the MI355X (gfx950) hot path of self-supervised
+ * speed-of-sound (SOS) and image joint reconstruction for ring-array
+ * photoacoustic computed tomography, after Li, Cui, Ma, Alexander,
+ * "Coordinate-based Speed of Sound Recovery for Aberration-Corrected
+ * Photoacoustic Computed Tomography" (ICCV 2025).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units: lengths in mm, times in us, SOS in mm/us (1 mm/us = 1000 m/s),
+ * sampling rates in samples per us.
+ *
+ * Grids are centred on the origin: cell (r, c) of an ny x nx grid with
+ * spacing s has centre x = (c - (nx-1)/2) s, y = (r - (ny-1)/2) s; arrays are
+ * row-major with the row index (y) first.  Element n of the ring sits at
+ * R (cos phi_n, sin phi_n), phi_n = phi0 + 2 pi n / n_elem.
+ *
+ * Complex arrays are interleaved (re, im) float pairs, row-major.  A "full"
+ * spectrum of a P x P patch is [P][P] in FFT order (index u carries
+ * frequency u or u - P, the usual FFT layout); a "half" spectrum keeps the
+ * columns 0 .. P/2 only, [P][P/2 + 1], which is enough for the spectrum of a
+ * real patch.  The forward transform is unnormalised with kernel e^{-j k.r};
+ * k is the angular wavenumber 2 pi fftfreq(P, px) in rad/mm.
+ *
+ * Memory: every array pointer is a DEVICE pointer owned by the caller unless
+ * the argument says host.  The library allocates no device memory, frees
+ * nothing and keeps no pointer after a call returns.  Workspaces are
+ * caller-provided; their size comes from the matching *_workspace_size call.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Every call only enqueues work on that stream and returns; errors
+ * raised by a kernel surface at the caller's next synchronisation.  No call
+ * synchronises, allocates, or issues a memset, so a sequence of calls can
+ * be captured into a HIP graph.
+ *
+ * Geometry structs (pact_ring, pact_grid, pact_patches) are passed by const
+ * pointer to host memory, read during the call only.
+ *
+ * Errors: every call returns PACT_OK (0) or a negative status; argument
+ * checks happen on the host before anything is enqueued, so a failed call
+ * has no effect.  pact_last_error() returns a message for the calling
+ * thread's last failure.  No C++ exception crosses the ABI.
+ *
+ * Gradients follow PyTorch's convention for complex numbers:
+ * dL/dz = dL/dRe(z) + j dL/dIm(z).  Gradient outputs are overwritten unless a
+ * call has an `accumulate` flag.
+ */
+#ifndef PACT_H
+#define PACT_H
+
+#include <stddef.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PACT_API __attribute__((visibility("default")))
+#else
+#define PACT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PACT_OK 0
+#define PACT_EINVAL (-1)        /* invalid argument (null pointer, bad size)      */
+#define PACT_EHIP (-2)          /* HIP runtime or launch error                     */
+#define PACT_EWORKSPACE (-3)    /* workspace missing or smaller than required      */
+#define PACT_EUNSUPPORTED (-4)  /* valid but outside this build's limits           */
+
+/* Ring array: n_elem elements on a circle of radius `radius` (mm), element 0 at
+ * angle phi0 (rad), counter-clockwise. */
+typedef struct {
+    int n_elem;
+    float radius;
+    float phi0;
+} pact_ring;
+
+/* A grid of ny x nx cells of size `spacing` (mm) centred on the origin. */
+typedef struct {
+    int ny;
+    int nx;
+    float spacing;
+} pact_grid;
+
+/* Isoplanatic patches: P x P pixels, origins every `stride` pixels in both
+ * directions, Gaussian window of full width at half maximum `fwhm` (mm). */
+typedef struct {
+    int P;
+    int stride;
+    float fwhm;
+} pact_patches;
+
+/* Thread-local message describing the calling thread's last failure ("" if none). */
+PACT_API const char* pact_last_error(void);
+
+/* ABI version (incremented on any incompatible change). */
+PACT_API int pact_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Geometry helpers (host only, no GPU work)
+ * ------------------------------------------------------------------------ */
+
+/* Number of patches along y and x: (ny - P) / stride + 1 and (nx - P) / stride + 1
+ * (Supp. S1.4: patch centres on a Cartesian grid).  Patch i = a * npx + b. */
+PACT_API int pact_patch_count(const pact_grid* img, const pact_patches* pp, int* npy, int* npx);
+
+/* Patch centres, HOST array [npy * npx][2] of (x, y): the mean of each patch's
+ * pixel centres. */
+PACT_API int pact_patch_centres(const pact_grid* img, const pact_patches* pp, float* centres_host);
+
+/* ---------------------------------------------------------------------------
+ * Once per scan
+ * ------------------------------------------------------------------------ */
+
+/* Delay-and-sum stack, Eq. DAS (Sec. 3.1), one image per extra delay (Sec. 3.2):
+ *   stack[j][r][c] = sum_n S(t = (|p_rc - r_n| - d[j]) / v0, n)
+ * S [n_elem][n_t]: channel n sampled at times t0 + m / fs, read by linear
+ * interpolation, zero outside the record.  d [M] extra delays (mm).
+ * stack [M][img.ny][img.nx].  Distances and sample positions are computed in
+ * FP64, the interpolation and the sum in FP32. */
+PACT_API int pact_das_stack(const float* S, int n_t, float fs, float t0, const pact_ring* ring, float v0,
+                   const float* d, int M, const pact_grid* img, float* stack, void* stream);
+
+/* Windowed patch spectra (Eq. conv, Sec. 3.3):
+ *   Y[i][j] = FFT2(g * stack[j][patch i]),  g[u][v] = exp(-((u-(P-1)/2)^2 + (v-(P-1)/2)^2) px^2 / (2 sigma^2)),
+ * sigma = fwhm / (2 sqrt(2 ln 2)), px = img.spacing.  Y is complex,
+ * [N][M][P][P/2+1] when half != 0, [N][M][P][P] otherwise, N = npy * npx.
+ * P <= 96. */
+PACT_API int pact_patch_fft(const float* stack, int M, const pact_grid* img, const pact_patches* pp, int half,
+                   float* Y, void* stream);
+
+/* Real part of the normalised inverse 2-D transform of B full P x P spectra:
+ * x[b] = Re(IFFT2(X[b])), X complex [B][P][P], x [B][P][P].  Used for the
+ * PSF h = Re(IFFT2 H) and the deconvolved patch x_hat = Re(IFFT2 X_hat). P <= 96. */
+PACT_API int pact_ifft2_real(const float* X, int B, int P, float* x, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Per optimisation step: SOS -> wavefront -> transfer function -> deconvolution -> loss
+ * ------------------------------------------------------------------------ */
+
+/* Wavefront error per (patch, element) ray, Eq. TOF and Eq. wf (Sec. 3.1):
+ *   w[i][n] = sum_{s < n_samples} dl (1 - v0 / v(c_i + (s + 1/2) dl u_in)),  dl = L_in / n_samples,
+ * u_in the unit vector from centre c_i to element n, L_in the distance at which
+ * that ray leaves the box |x|, |y| < (G + 1) spacing / 2 outside which the SOS is
+ * v0 (or the element distance, if shorter).  v is the bilinear interpolation
+ * of the node grid sos [sosg.ny][sosg.nx] (node centres placed like pixel
+ * centres), every node outside the grid being v0 (interpolated pixel grid,
+ * Sec. 3.3).  centres [N][2] (x, y) must lie inside that box.  w [N][n_elem].
+ * (sosg.ny + 2) * (sosg.nx + 2) * 4 bytes must fit in 160 KiB of LDS. */
+PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
+                       const pact_ring* ring, int n_samples, float* w, void* stream);
+
+/* Adjoint of pact_sos_to_delays: dL_dsos[a][b] = scale * sum_{i,n} dL_dw[i][n] dw[i][n]/dsos[a][b],
+ * with dw/dv = dl v0 / v^2 at every sample spread by the bilinear weights.
+ * scale: optional DEVICE scalar (NULL = 1).  accumulate != 0 adds to dL_dsos.
+ * ws: workspace of pact_sos_to_delays_adjoint_workspace_size() bytes.  The
+ * result does not depend on the order of the floating-point sums across
+ * workgroups (fixed-order reduction). */
+PACT_API size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg, int N, const pact_ring* ring);
+PACT_API int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
+                               const pact_ring* ring, int n_samples, const float* dL_dw, const float* scale,
+                               float* dL_dsos, int accumulate, void* ws, size_t ws_bytes, void* stream);
+
+/* Transfer functions, Eq. TF (Sec. 3.1), under the e^{-j k.r} forward transform:
+ *   H[i][j](k) = 1/2 (e^{+j|k|(d_j - W_i(th))} + e^{-j|k|(d_j - W_i(th + pi))}),  th = atan2(k_y, k_x),
+ * W_i(th) the wavefront of patch i at angle th: the ray from c_i at angle th
+ * meets the ring at fractional element index f; W is linear between elements
+ * floor(f) and floor(f)+1 (cyclic) of w[i].  H full spectrum [N][M][P][P].
+ * h_opt (may be NULL): the PSFs Re(IFFT2 H), [N][M][P][P].  P <= 96. */
+PACT_API int pact_delays_to_psf(const float* w, const float* centres, int N, const pact_ring* ring, const float* d, int M,
+                       int P, float px, float* H, float* h_opt, void* stream);
+
+/* Adjoint of pact_delays_to_psf (H only): dL_dw [N][n_elem] from dL_dH [N][M][P][P]. */
+PACT_API int pact_delays_to_psf_adjoint(const float* w, const float* centres, int N, const pact_ring* ring, const float* d,
+                               int M, int P, float px, const float* dL_dH, float* dL_dw, void* stream);
+
+/* Multichannel deconvolution, Eq. fm_fourier and Eq. multi-deconv (Sec. 3.2), with
+ * the conjugate transpose and a Tikhonov eps:
+ *   X[i](k) = sum_j conj(H[i][j](k)) Y[i][j](k) / (sum_j |H[i][j](k)|^2 + eps).
+ * Y, H full spectra [N][M][P][P]; X [N][P][P]. */
+PACT_API int pact_multichannel_deconv(const float* Y, const float* H, int N, int M, int P, float eps, float* X,
+                             void* stream);
+
+/* Adjoint of pact_multichannel_deconv with respect to H:
+ *   dL_dH[i][j] = (conj(g) Y_j - 2 Re(conj(g) X) H_j) / (sum |H|^2 + eps),  g = dL_dX[i]. */
+PACT_API int pact_multichannel_deconv_adjoint(const float* Y, const float* H, int N, int M, int P, float eps,
+                                     const float* dL_dX, float* dL_dH, void* stream);
+
+/* Data term of Eq. jr for given H and X (modular path):
+ *   loss = sum_i sum_k |k| sum_j |Y[i][j](k) - H[i][j](k) X[i](k)|^2  (DEVICE scalar, overwritten),
+ * and, if not NULL, its partial derivatives at fixed X and at fixed H:
+ *   dL_dH[i][j] = -2 |k| r_ij conj(X_i),   dL_dX[i] = -2 |k| sum_j r_ij conj(H_ij),  r = Y - H X.
+ * ws: pact_residual_loss_workspace_size() bytes. */
+PACT_API size_t pact_residual_loss_workspace_size(int N, int P);
+PACT_API int pact_residual_loss(const float* Y, const float* H, const float* X, int N, int M, int P, float px,
+                       float* loss, float* dL_dH, float* dL_dX, void* ws, size_t ws_bytes, void* stream);
+
+/* The fused step: Eq. TF + Eq. multi-deconv + data term of Eq. jr and its
+ * gradient with respect to the wavefront table, in one pass over the half
+ * spectra Y_half [N][M][P][P/2+1] (the spectra of real patches), without
+ * storing any transfer function:
+ *   loss  (DEVICE scalar, overwritten) = sum over all P x P bins as in pact_residual_loss
+ *         with H from w and X the deconvolution of Y by H,
+ *   dL_dw [N][n_elem] (overwritten; may be NULL),
+ *   X_opt (may be NULL): the deconvolved full spectra [N][P][P].
+ * ws: pact_loss_and_grad_workspace_size() bytes, zero-filled once when it is
+ * allocated; every call leaves its counters at zero again, so the same
+ * workspace can be reused (but not by two calls in flight at once).
+ * Sums across workgroups are taken in a fixed order (deterministic).  M <= 16. */
+PACT_API size_t pact_loss_and_grad_workspace_size(int N, int M, int P, int n_elem);
+PACT_API int pact_loss_and_grad(const float* Y_half, const float* w, const float* centres, int N, const pact_ring* ring,
+                       const float* d, int M, int P, float px, float eps, float* loss, float* dL_dw,
+                       float* X_opt, void* ws, size_t ws_bytes, void* stream);
+
+/* Total-variation term of Eq. jr (reading: anisotropic, over node pairs with at
+ * least one free node, subgradient sign(0) = 0):
+ *   loss += lambda * TV(sos),  grad += lambda * dTV/dsos  (grad over all nodes).
+ * mask [G] uint8, nonzero = free node.  loss: DEVICE scalar (read-modify-write). */
+PACT_API int pact_tv_grad(const float* sos, const unsigned char* mask, const pact_grid* sosg, float lambda, float* grad,
+                 float* loss, void* stream);
+
+/* Adam step (Sec. 3.3) on the free nodes of sos (size n), PyTorch's update rule:
+ *   t += 1; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ *   sos -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ * fixed nodes untouched.  t: DEVICE int step counter (so that the step can be
+ * replayed from a HIP graph). */
+PACT_API int pact_adam_step(float* sos, float* m, float* v, int* t, const unsigned char* mask, int n, const float* grad,
+                   float lr, float b1, float b2, float eps, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PACT_H */

@@ -1,0 +1,99 @@
+// Total-variation term of Eq. jr and the Adam update of the pixel-grid SOS (Sec. 3.3).
+//
+// Both are single-workgroup kernels: the SOS grid is small (19,600 nodes at the
+// paper scale), a single workgroup gives a fixed summation order for the TV
+// value, and it lets the Adam kernel advance the device-side step counter after
+// every node has read it, so that a captured step can be replayed.
+#include "common.h"
+
+namespace pact {
+namespace {
+
+constexpr int kThreads = 1024;
+
+__device__ __forceinline__ float sgn(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
+
+__global__ __launch_bounds__(kThreads) void tv_kernel(const float* __restrict__ v,
+                                                      const unsigned char* __restrict__ mask, int Gy, int Gx,
+                                                      float lambda, float* __restrict__ grad,
+                                                      float* __restrict__ loss) {
+    __shared__ float red[kThreads / 64];
+    float tv = 0.0f;
+    for (int idx = threadIdx.x; idx < Gy * Gx; idx += kThreads) {
+        const int a = idx / Gx, b = idx % Gx;
+        const float x = v[idx];
+        const bool m = mask[idx] != 0;
+        float g = 0.0f;
+        // pair (a, b)-(a+1, b) and (a, b)-(a, b+1): counted once, by their first node
+        if (a + 1 < Gy && (m || mask[idx + Gx])) {
+            const float dv = v[idx + Gx] - x;
+            tv += fabsf(dv);
+            g -= sgn(dv);
+        }
+        if (b + 1 < Gx && (m || mask[idx + 1])) {
+            const float dv = v[idx + 1] - x;
+            tv += fabsf(dv);
+            g -= sgn(dv);
+        }
+        // the same pairs seen from their second node
+        if (a > 0 && (m || mask[idx - Gx])) g += sgn(x - v[idx - Gx]);
+        if (b > 0 && (m || mask[idx - 1])) g += sgn(x - v[idx - 1]);
+        grad[idx] = fmaf(lambda, g, grad[idx]);
+    }
+    tv = block_sum(tv, red);
+    if (threadIdx.x == 0) *loss += lambda * tv;
+}
+
+__global__ __launch_bounds__(kThreads) void adam_kernel(float* __restrict__ p, float* __restrict__ m,
+                                                        float* __restrict__ v, int* __restrict__ t,
+                                                        const unsigned char* __restrict__ mask, int n,
+                                                        const float* __restrict__ grad, float lr, float b1, float b2,
+                                                        float eps) {
+    const int step = *t + 1;
+    const float bc1 = 1.0f - powf(b1, static_cast<float>(step));
+    const float bc2 = 1.0f - powf(b2, static_cast<float>(step));
+    const float step_size = lr / bc1;
+    const float inv_sqrt_bc2 = 1.0f / sqrtf(bc2);
+    for (int idx = threadIdx.x; idx < n; idx += kThreads) {
+        if (!mask[idx]) continue;
+        const float g = grad[idx];
+        const float mm = fmaf(b1, m[idx], (1.0f - b1) * g);
+        const float vv = fmaf(b2, v[idx], (1.0f - b2) * g * g);
+        m[idx] = mm;
+        v[idx] = vv;
+        p[idx] -= step_size * mm / fmaf(sqrtf(vv), inv_sqrt_bc2, eps);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *t = step;
+}
+
+}  // namespace
+}  // namespace pact
+
+extern "C" int pact_tv_grad(const float* sos, const unsigned char* mask, const pact_grid* sosg_, float lambda, float* grad,
+                            float* loss, void* stream) {
+    if (!sosg_) {
+        pact::set_error("pact_tv_grad: null geometry pointer");
+        return PACT_EINVAL;
+    }
+    const pact_grid sosg = *sosg_;
+    using namespace pact;
+    clear_error();
+    PACT_CHECK_ARG(sos && mask && grad && loss, "pact_tv_grad: null pointer");
+    if (int s = check_grid(sosg, "pact_tv_grad")) return s;
+    PACT_CHECK_ARG(std::isfinite(lambda), "pact_tv_grad: lambda must be finite");
+    tv_kernel<<<1, kThreads, 0, as_stream(stream)>>>(sos, mask, sosg.ny, sosg.nx, lambda, grad, loss);
+    return launch_status("pact_tv_grad");
+}
+
+extern "C" int pact_adam_step(float* sos, float* m, float* v, int* t, const unsigned char* mask, int n,
+                              const float* grad, float lr, float b1, float b2, float eps, void* stream) {
+    using namespace pact;
+    clear_error();
+    PACT_CHECK_ARG(sos && m && v && t && mask && grad, "pact_adam_step: null pointer");
+    PACT_CHECK_ARG(n > 0, "pact_adam_step: n must be positive");
+    PACT_CHECK_ARG(b1 >= 0.0f && b1 < 1.0f && b2 >= 0.0f && b2 < 1.0f, "pact_adam_step: betas must be in [0, 1)");
+    PACT_CHECK_ARG(eps > 0.0f && std::isfinite(lr), "pact_adam_step: eps must be positive and lr finite");
+    adam_kernel<<<1, kThreads, 0, as_stream(stream)>>>(sos, m, v, t, mask, n, grad, lr, b1, b2, eps);
+    return launch_status("pact_adam_step");
+}

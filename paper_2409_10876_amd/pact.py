@@ -1,0 +1,321 @@
+"""Thin ctypes binding of libpact (see include/pact.h for every call's contract).
+
+Argument marshalling only: each function checks tensor devices, dtypes,
+shapes and contiguity, passes raw device pointers and torch's current HIP
+stream, and raises PactError on a negative status.  All arithmetic runs in
+the library's HIP kernels.  torch is imported first so that the library binds
+to the same HIP runtime as torch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpact.so")
+
+
+class PactError(RuntimeError):
+    pass
+
+
+class Ring(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int), ("radius", ctypes.c_float), ("phi0", ctypes.c_float)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int), ("nx", ctypes.c_int), ("spacing", ctypes.c_float)]
+
+
+class Patches(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int), ("stride", ctypes.c_int), ("fwhm", ctypes.c_float)]
+
+
+_P = ctypes.c_void_p
+# geometry structs are passed by pointer (passing small float-bearing structs by value through libffi is not
+# reliable); ctypes applies byref() to a struct instance given for a POINTER argument
+_PRING = ctypes.POINTER(Ring)
+_PGRID = ctypes.POINTER(Grid)
+_PPATCH = ctypes.POINTER(Patches)
+_I = ctypes.c_int
+_F = ctypes.c_float
+_Z = ctypes.c_size_t
+
+_SIGS = {
+    "pact_last_error": (ctypes.c_char_p, []),
+    "pact_version": (_I, []),
+    "pact_patch_count": (_I, [_PGRID, _PPATCH, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "pact_patch_centres": (_I, [_PGRID, _PPATCH, _P]),
+    "pact_das_stack": (_I, [_P, _I, _F, _F, _PRING, _F, _P, _I, _PGRID, _P, _P]),
+    "pact_patch_fft": (_I, [_P, _I, _PGRID, _PPATCH, _I, _P, _P]),
+    "pact_ifft2_real": (_I, [_P, _I, _I, _P, _P]),
+    "pact_sos_to_delays": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _P, _P]),
+    "pact_sos_to_delays_adjoint_workspace_size": (_Z, [_PGRID, _I, _PRING]),
+    "pact_sos_to_delays_adjoint": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _P, _P, _P, _I, _P, _Z, _P]),
+    "pact_delays_to_psf": (_I, [_P, _P, _I, _PRING, _P, _I, _I, _F, _P, _P, _P]),
+    "pact_delays_to_psf_adjoint": (_I, [_P, _P, _I, _PRING, _P, _I, _I, _F, _P, _P, _P]),
+    "pact_multichannel_deconv": (_I, [_P, _P, _I, _I, _I, _F, _P, _P]),
+    "pact_multichannel_deconv_adjoint": (_I, [_P, _P, _I, _I, _I, _F, _P, _P, _P]),
+    "pact_residual_loss_workspace_size": (_Z, [_I, _I]),
+    "pact_residual_loss": (_I, [_P, _P, _P, _I, _I, _I, _F, _P, _P, _P, _P, _Z, _P]),
+    "pact_loss_and_grad_workspace_size": (_Z, [_I, _I, _I, _I]),
+    "pact_loss_and_grad": (_I, [_P, _P, _P, _I, _PRING, _P, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
+    "pact_tv_grad": (_I, [_P, _P, _PGRID, _F, _P, _P, _P]),
+    "pact_adam_step": (_I, [_P, _P, _P, _P, _P, _I, _P, _F, _F, _F, _F, _P]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libpact.so (built in-tree by paper_2409_10876_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise PactError(f"{path} is missing: build it with `python -m paper_2409_10876_amd.build` "
+                        "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = load().pact_last_error().decode(errors="replace")
+        raise PactError(f"{what} failed with status {status}: {msg}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, name="tensor", numel=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+F32, C64, U8, I32 = torch.float32, torch.complex64, torch.uint8, torch.int32
+
+
+@dataclass(frozen=True)
+class Geometry:
+    """Scan geometry in the units of the C ABI (mm, us, mm/us)."""
+    n_elem: int
+    radius: float
+    phi0: float
+    ny: int
+    nx: int
+    px: float
+    P: int
+    stride: int
+    fwhm: float
+    sos_ny: int
+    sos_nx: int
+    sos_spacing: float
+
+    @property
+    def ring(self) -> Ring:
+        return Ring(self.n_elem, self.radius, self.phi0)
+
+    @property
+    def img(self) -> Grid:
+        return Grid(self.ny, self.nx, self.px)
+
+    @property
+    def sosg(self) -> Grid:
+        return Grid(self.sos_ny, self.sos_nx, self.sos_spacing)
+
+    @property
+    def patches(self) -> Patches:
+        return Patches(self.P, self.stride, self.fwhm)
+
+    @property
+    def n_patches(self) -> int:
+        a, b = patch_count(self)
+        return a * b
+
+
+def patch_count(g: Geometry):
+    npy, npx = ctypes.c_int(), ctypes.c_int()
+    _check(load().pact_patch_count(g.img, g.patches, ctypes.byref(npy), ctypes.byref(npx)), "pact_patch_count")
+    return npy.value, npx.value
+
+
+def patch_centres(g: Geometry, device="cuda") -> torch.Tensor:
+    N = g.n_patches
+    host = (ctypes.c_float * (2 * N))()
+    _check(load().pact_patch_centres(g.img, g.patches, ctypes.cast(host, ctypes.c_void_p)), "pact_patch_centres")
+    return torch.tensor(list(host), dtype=F32).view(N, 2).to(device)
+
+
+def das_stack(S, fs, t0, g: Geometry, v0, d, out=None):
+    n_elem, n_t = S.shape
+    assert n_elem == g.n_elem, "S rows must match the ring"
+    M = d.numel()
+    out = torch.empty(M, g.ny, g.nx, dtype=F32, device=S.device) if out is None else out
+    _check(load().pact_das_stack(_ptr(S, F32, "S"), n_t, fs, t0, g.ring, v0, _ptr(d, F32, "d"), M, g.img,
+                                 _ptr(out, F32, "stack", M * g.ny * g.nx), _stream()), "pact_das_stack")
+    return out
+
+
+def patch_fft(stack, g: Geometry, half=True, out=None):
+    M = stack.shape[0]
+    N = g.n_patches
+    W = g.P // 2 + 1 if half else g.P
+    out = torch.empty(N, M, g.P, W, dtype=C64, device=stack.device) if out is None else out
+    _check(load().pact_patch_fft(_ptr(stack, F32, "stack", M * g.ny * g.nx), M, g.img, g.patches, int(half),
+                                 _ptr(out, C64, "Y", N * M * g.P * W), _stream()), "pact_patch_fft")
+    return out
+
+
+def ifft2_real(X, out=None):
+    P = X.shape[-1]
+    B = X.numel() // (P * P)
+    out = torch.empty(X.shape, dtype=F32, device=X.device) if out is None else out
+    _check(load().pact_ifft2_real(_ptr(X, C64, "X"), B, P, _ptr(out, F32, "x", B * P * P), _stream()),
+           "pact_ifft2_real")
+    return out
+
+
+def sos_to_delays(sos, g: Geometry, v0, centres, n_samples, out=None):
+    N = centres.shape[0]
+    out = torch.empty(N, g.n_elem, dtype=F32, device=sos.device) if out is None else out
+    _check(load().pact_sos_to_delays(_ptr(sos, F32, "sos", g.sos_ny * g.sos_nx), g.sosg, v0,
+                                     _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples,
+                                     _ptr(out, F32, "w", N * g.n_elem), _stream()), "pact_sos_to_delays")
+    return out
+
+
+def sos_to_delays_adjoint_workspace_size(g: Geometry, N: int) -> int:
+    return load().pact_sos_to_delays_adjoint_workspace_size(g.sosg, N, g.ring)
+
+
+def sos_to_delays_adjoint(sos, g: Geometry, v0, centres, n_samples, dL_dw, out=None, scale=None, accumulate=False,
+                          ws=None):
+    N = centres.shape[0]
+    out = torch.empty(g.sos_ny, g.sos_nx, dtype=F32, device=sos.device) if out is None else out
+    need = sos_to_delays_adjoint_workspace_size(g, N)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=sos.device) if ws is None else ws
+    _check(load().pact_sos_to_delays_adjoint(
+        _ptr(sos, F32, "sos", g.sos_ny * g.sos_nx), g.sosg, v0, _ptr(centres, F32, "centres", 2 * N), N, g.ring,
+        n_samples, _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), _ptr(scale, F32, "scale", 1),
+        _ptr(out, F32, "dL_dsos", g.sos_ny * g.sos_nx), int(accumulate), _ptr(ws, name="ws"), ws.numel(),
+        _stream()), "pact_sos_to_delays_adjoint")
+    return out
+
+
+def delays_to_psf(w, centres, g: Geometry, d, with_psf=False, H=None, h=None):
+    N = w.shape[0]
+    M = d.numel()
+    P = g.P
+    H = torch.empty(N, M, P, P, dtype=C64, device=w.device) if H is None else H
+    if with_psf and h is None:
+        h = torch.empty(N, M, P, P, dtype=F32, device=w.device)
+    _check(load().pact_delays_to_psf(_ptr(w, F32, "w", N * g.n_elem), _ptr(centres, F32, "centres", 2 * N), N,
+                                     g.ring, _ptr(d, F32, "d", M), M, P, g.px, _ptr(H, C64, "H", N * M * P * P),
+                                     _ptr(h, F32, "h", N * M * P * P) if with_psf else None, _stream()),
+           "pact_delays_to_psf")
+    return (H, h) if with_psf else H
+
+
+def delays_to_psf_adjoint(w, centres, g: Geometry, d, dL_dH, out=None):
+    N = w.shape[0]
+    M = d.numel()
+    out = torch.empty(N, g.n_elem, dtype=F32, device=w.device) if out is None else out
+    _check(load().pact_delays_to_psf_adjoint(_ptr(w, F32, "w", N * g.n_elem), _ptr(centres, F32, "centres", 2 * N),
+                                             N, g.ring, _ptr(d, F32, "d", M), M, g.P, g.px,
+                                             _ptr(dL_dH, C64, "dL_dH", N * M * g.P * g.P),
+                                             _ptr(out, F32, "dL_dw", N * g.n_elem), _stream()),
+           "pact_delays_to_psf_adjoint")
+    return out
+
+
+def multichannel_deconv(Y, H, eps, out=None):
+    N, M, P, _ = Y.shape
+    out = torch.empty(N, P, P, dtype=C64, device=Y.device) if out is None else out
+    _check(load().pact_multichannel_deconv(_ptr(Y, C64, "Y"), _ptr(H, C64, "H", Y.numel()), N, M, P, eps,
+                                           _ptr(out, C64, "X", N * P * P), _stream()), "pact_multichannel_deconv")
+    return out
+
+
+def multichannel_deconv_adjoint(Y, H, eps, dL_dX, out=None):
+    N, M, P, _ = Y.shape
+    out = torch.empty_like(H) if out is None else out
+    _check(load().pact_multichannel_deconv_adjoint(_ptr(Y, C64, "Y"), _ptr(H, C64, "H", Y.numel()), N, M, P, eps,
+                                                   _ptr(dL_dX, C64, "dL_dX", N * P * P),
+                                                   _ptr(out, C64, "dL_dH", Y.numel()), _stream()),
+           "pact_multichannel_deconv_adjoint")
+    return out
+
+
+def residual_loss(Y, H, X, px, with_grads=True):
+    N, M, P, _ = Y.shape
+    loss = torch.empty(1, dtype=F32, device=Y.device)
+    gH = torch.empty_like(H) if with_grads else None
+    gX = torch.empty_like(X) if with_grads else None
+    need = load().pact_residual_loss_workspace_size(N, P)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=Y.device)
+    _check(load().pact_residual_loss(_ptr(Y, C64, "Y"), _ptr(H, C64, "H", Y.numel()), _ptr(X, C64, "X", N * P * P),
+                                     N, M, P, px, _ptr(loss, F32, "loss"), _ptr(gH, C64, "dL_dH"),
+                                     _ptr(gX, C64, "dL_dX"), _ptr(ws, name="ws"), ws.numel(), _stream()),
+           "pact_residual_loss")
+    return loss, gH, gX
+
+
+def loss_and_grad_workspace_size(N, M, P, n_elem) -> int:
+    return load().pact_loss_and_grad_workspace_size(N, M, P, n_elem)
+
+
+def loss_and_grad(Y_half, w, centres, g: Geometry, d, eps, loss=None, dL_dw=None, want_grad=True, X=None,
+                  ws=None):
+    N, M, P, Wh = Y_half.shape
+    assert Wh == P // 2 + 1 and P == g.P
+    dev = Y_half.device
+    loss = torch.empty(1, dtype=F32, device=dev) if loss is None else loss
+    if want_grad and dL_dw is None:
+        dL_dw = torch.empty(N, g.n_elem, dtype=F32, device=dev)
+    need = loss_and_grad_workspace_size(N, M, P, g.n_elem)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev) if ws is None else ws
+    _check(load().pact_loss_and_grad(_ptr(Y_half, C64, "Y_half"), _ptr(w, F32, "w", N * g.n_elem),
+                                     _ptr(centres, F32, "centres", 2 * N), N, g.ring, _ptr(d, F32, "d", M), M, P,
+                                     g.px, eps, _ptr(loss, F32, "loss", 1),
+                                     _ptr(dL_dw, F32, "dL_dw", N * g.n_elem) if want_grad else None,
+                                     _ptr(X, C64, "X", N * P * P), _ptr(ws, name="ws"), ws.numel(), _stream()),
+           "pact_loss_and_grad")
+    return loss, dL_dw
+
+
+def tv_grad(sos, mask, g: Geometry, lam, grad, loss):
+    n = g.sos_ny * g.sos_nx
+    _check(load().pact_tv_grad(_ptr(sos, F32, "sos", n), _ptr(mask, U8, "mask", n), g.sosg, lam,
+                               _ptr(grad, F32, "grad", n), _ptr(loss, F32, "loss", 1), _stream()), "pact_tv_grad")
+
+
+def adam_step(sos, m, v, t, mask, grad, lr, b1=0.9, b2=0.999, eps=1e-8):
+    n = sos.numel()
+    _check(load().pact_adam_step(_ptr(sos, F32, "sos"), _ptr(m, F32, "m", n), _ptr(v, F32, "v", n),
+                                 _ptr(t, I32, "t", 1), _ptr(mask, U8, "mask", n), n, _ptr(grad, F32, "grad", n),
+                                 lr, b1, b2, eps, _stream()), "pact_adam_step")

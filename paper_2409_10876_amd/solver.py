@@ -1,0 +1,162 @@
+"""Optimisation of the pixel-grid SOS (Sec. 3.3) on top of the libpact calls.
+
+* ``prepare_scan``: channel data -> DAS stack -> windowed half spectra Y, once
+  per scan (Eq. DAS, Eq. conv), resident in HBM for every step.
+* ``PixelGridSolver``: one step = sos_to_delays -> loss_and_grad (fused
+  Eq. TF + Eq. multi-deconv + Eq. jr and dL/dw) -> sos_to_delays_adjoint ->
+  tv_grad -> adam_step, all on torch's current stream with preallocated
+  buffers, so that a run of steps can be captured once into a HIP graph and
+  replayed.
+* ``SosLoss``: the data term of Eq. jr as a torch.autograd.Function whose
+  backward is the library's hand-written adjoint (dL/dw is produced by the
+  forward pass, which recomputes the transfer functions instead of storing
+  them).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import pact
+from .pact import Geometry, F32
+
+
+def geometry_from(cfg) -> Geometry:
+    """Geometry from any object with the workload attributes (n_elem, radius, phi0, ny, nx, px, P, stride,
+    fwhm, sos_n, sos_spacing)."""
+    return Geometry(n_elem=cfg.n_elem, radius=float(cfg.radius), phi0=float(cfg.phi0), ny=cfg.ny, nx=cfg.nx,
+                    px=float(cfg.px), P=cfg.P, stride=cfg.stride, fwhm=float(cfg.fwhm), sos_ny=cfg.sos_n,
+                    sos_nx=cfg.sos_n, sos_spacing=float(cfg.sos_spacing))
+
+
+class ScanData:
+    """Device-resident data of one scan."""
+
+    def __init__(self, geom: Geometry, S: torch.Tensor, delays: torch.Tensor, fs: float, t0: float, v0: float):
+        self.geom = geom
+        self.S = S
+        self.d = delays
+        self.fs, self.t0, self.v0 = fs, t0, v0
+        self.centres = pact.patch_centres(geom, device=S.device)
+        self.stack = None
+        self.Y = None
+
+    def prepare(self):
+        """DAS stack and windowed half spectra (once per scan)."""
+        self.stack = pact.das_stack(self.S, self.fs, self.t0, self.geom, self.v0, self.d, out=self.stack)
+        self.Y = pact.patch_fft(self.stack, self.geom, half=True, out=self.Y)
+        return self.Y
+
+
+def prepare_scan(cfg, S, delays, device="cuda") -> ScanData:
+    g = geometry_from(cfg)
+    S = torch.as_tensor(S, dtype=F32).to(device).contiguous()
+    d = torch.as_tensor(delays, dtype=F32).to(device).contiguous()
+    sd = ScanData(g, S, d, float(cfg.fs), float(cfg.t0), float(cfg.v0))
+    sd.prepare()
+    return sd
+
+
+class PixelGridSolver:
+    """Adam on the free nodes of the SOS grid; all state on the device."""
+
+    def __init__(self, scan: ScanData, mask, eps: float, lam: float, lr: float, n_samples: int, sos_init=None,
+                 b1=0.9, b2=0.999, adam_eps=1e-8):
+        g = scan.geom
+        dev = scan.S.device
+        self.scan, self.g = scan, g
+        self.eps, self.lam, self.lr, self.n_samples = float(eps), float(lam), float(lr), int(n_samples)
+        self.b1, self.b2, self.adam_eps = b1, b2, adam_eps
+        self.mask = torch.as_tensor(mask, dtype=torch.uint8).to(dev).contiguous()
+        v0 = scan.v0
+        if sos_init is None:
+            sos = torch.full((g.sos_ny, g.sos_nx), v0, dtype=F32, device=dev)
+        else:
+            sos = torch.as_tensor(sos_init, dtype=F32).to(dev).clone()
+        sos = torch.where(self.mask.bool(), sos, torch.full_like(sos, v0))
+        self.sos = sos.contiguous()
+        self.m = torch.zeros_like(self.sos)
+        self.v = torch.zeros_like(self.sos)
+        self.t = torch.zeros(1, dtype=torch.int32, device=dev)
+        N = scan.centres.shape[0]
+        M = scan.d.numel()
+        self.w = torch.empty(N, g.n_elem, dtype=F32, device=dev)
+        self.gw = torch.empty(N, g.n_elem, dtype=F32, device=dev)
+        self.grad = torch.empty_like(self.sos)
+        self.loss = torch.zeros(1, dtype=F32, device=dev)
+        self.ws_loss = torch.empty(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
+                                   dtype=torch.uint8, device=dev)
+        self.ws_adj = torch.empty(max(1, pact.sos_to_delays_adjoint_workspace_size(g, N)), dtype=torch.uint8,
+                                  device=dev)
+        self.graph = None
+        self.graph_steps = 0
+
+    # one optimisation step (a2 -> a8), enqueued on the current stream
+    def delays(self):
+        pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w)
+
+    def loss_grad(self):
+        pact.loss_and_grad(self.scan.Y, self.w, self.scan.centres, self.g, self.scan.d, self.eps, loss=self.loss,
+                           dL_dw=self.gw, ws=self.ws_loss)
+
+    def adjoint(self):
+        pact.sos_to_delays_adjoint(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
+                                   out=self.grad, ws=self.ws_adj)
+
+    def regularise(self):
+        if self.lam != 0.0:
+            pact.tv_grad(self.sos, self.mask, self.g, self.lam, self.grad, self.loss)
+
+    def update(self):
+        pact.adam_step(self.sos, self.m, self.v, self.t, self.mask, self.grad, self.lr, self.b1, self.b2,
+                       self.adam_eps)
+
+    def step(self):
+        self.delays()
+        self.loss_grad()
+        self.adjoint()
+        self.regularise()
+        self.update()
+
+    def capture(self, steps: int):
+        """Capture `steps` consecutive steps into one HIP graph (run one eager step first)."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(steps):
+                    self.step()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph, self.graph_steps = g, steps
+        return g
+
+    def run(self, steps: int):
+        """Advance `steps` steps, by graph replays where a captured graph divides the count."""
+        if self.graph is not None and steps % self.graph_steps == 0:
+            for _ in range(steps // self.graph_steps):
+                self.graph.replay()
+        else:
+            for _ in range(steps):
+                self.step()
+
+
+class SosLoss(torch.autograd.Function):
+    """Data term of Eq. jr as a function of the SOS node grid; backward by the library's adjoint."""
+
+    @staticmethod
+    def forward(ctx, sos, scan: ScanData, eps: float, n_samples: int):
+        g = scan.geom
+        sos = sos.contiguous()
+        w = pact.sos_to_delays(sos, g, scan.v0, scan.centres, n_samples)
+        loss, gw = pact.loss_and_grad(scan.Y, w, scan.centres, g, scan.d, eps)
+        ctx.save_for_backward(sos, gw)
+        ctx.scan, ctx.n_samples = scan, n_samples
+        return loss.view(())
+
+    @staticmethod
+    def backward(ctx, gout):
+        sos, gw = ctx.saved_tensors
+        scan = ctx.scan
+        scale = gout.reshape(1).to(F32).contiguous()
+        grad = pact.sos_to_delays_adjoint(sos, scan.geom, scan.v0, scan.centres, ctx.n_samples, gw, scale=scale)
+        return grad, None, None, None

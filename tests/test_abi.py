@@ -1,0 +1,99 @@
+"""The C ABI without a GPU: the library loads, exports every symbol include/pact.h declares, computes the
+host-side geometry, and rejects bad arguments with the documented status codes before enqueuing anything."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pact.h")
+
+FAKE = ctypes.c_void_p(0x1000)     # never dereferenced: every call below fails its host-side checks first
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2409_10876_amd as P
+    return P
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"PACT_API\s+[\w\s\*]+?\b(pact_\w+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(P):
+    names = _declared()
+    assert len(names) >= 20
+    lib = P.pact.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(P.pact.exported_symbols()) == names
+    assert lib.pact_version() == 1
+
+
+def test_patch_geometry_matches_oracle(P):
+    from oracle.geometry import patch_centres
+    for scan in (synth.TINY, synth.PAPER):
+        g = P.geometry_from(scan)
+        assert P.pact.patch_count(g) == (scan.n_patch_y, scan.n_patch_x)
+        got = P.pact.patch_centres(g, device="cpu").numpy()
+        want = patch_centres(scan.ny, scan.nx, float(np.float32(scan.px)), scan.P, scan.stride).numpy()
+        np.testing.assert_allclose(got, want, atol=1e-6)
+
+
+def _status(P, name, *args):
+    lib = P.pact.load()
+    s = getattr(lib, name)(*args)
+    return s, lib.pact_last_error().decode()
+
+
+def test_argument_errors(P):
+    pt = P.pact
+    ring = pt.Ring(256, 50.0, 0.0)
+    img = pt.Grid(128, 128, 0.2)
+    sosg = pt.Grid(32, 32, 0.8)
+    s, msg = _status(P, "pact_sos_to_delays", None, sosg, 1.5, FAKE, 49, ring, 256, FAKE, None)
+    assert s == -1 and "null" in msg
+    s, msg = _status(P, "pact_sos_to_delays", FAKE, sosg, 1.5, FAKE, 49, pt.Ring(0, 50.0, 0.0), 256, FAKE, None)
+    assert s == -1 and "n_elem" in msg
+    s, msg = _status(P, "pact_sos_to_delays", FAKE, pt.Grid(300, 300, 0.1), 1.5, FAKE, 49, ring, 256, FAKE, None)
+    assert s == -4 and "LDS" in msg
+    s, msg = _status(P, "pact_patch_fft", FAKE, 5, img, pt.Patches(120, 8, 1.0), 1, FAKE, None)
+    assert s == -4
+    s, msg = _status(P, "pact_patch_fft", FAKE, 5, img, pt.Patches(200, 8, 1.0), 1, FAKE, None)
+    assert s == -1 and "larger" in msg
+    s, msg = _status(P, "pact_loss_and_grad", FAKE, FAKE, FAKE, 49, ring, FAKE, 17, 32, 0.2, 1e-6, FAKE, FAKE, None,
+                     FAKE, 1 << 30, None)
+    assert s == -4 and "M = 17" in msg
+    s, msg = _status(P, "pact_loss_and_grad", FAKE, FAKE, FAKE, 49, ring, FAKE, 5, 32, 0.2, 1e-6, FAKE, FAKE, None,
+                     FAKE, 16, None)
+    assert s == -3 and "workspace" in msg
+    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, sosg, 1.5, FAKE, 49, ring, 256, FAKE, None, FAKE, 0,
+                     FAKE, 4, None)
+    assert s == -3
+    s, msg = _status(P, "pact_residual_loss", FAKE, FAKE, FAKE, 4, 3, 8, 0.1, FAKE, None, None, FAKE, 0, None)
+    assert s == -3
+    s, msg = _status(P, "pact_adam_step", FAKE, FAKE, FAKE, FAKE, FAKE, 10, FAKE, 1e-3, 1.0, 0.999, 1e-8, None)
+    assert s == -1 and "betas" in msg
+    s, msg = _status(P, "pact_multichannel_deconv", FAKE, FAKE, 4, 3, 8, -1.0, FAKE, None)
+    assert s == -1 and "eps" in msg
+    s, msg = _status(P, "pact_das_stack", FAKE, 100, 40.0, 0.0, ring, 0.0, FAKE, 5, img, FAKE, None)
+    assert s == -1
+
+
+def test_workspace_sizes(P):
+    pt = P.pact
+    assert pt.loss_and_grad_workspace_size(169, 11, 80, 512) == 169 * 13 * (1 + 512) * 4
+    assert P.pact.load().pact_residual_loss_workspace_size(0, 8) == 0
+
+
+def test_binding_refuses_host_tensors(P):
+    import torch
+    g = P.geometry_from(synth.TINY)
+    with pytest.raises(ValueError):
+        P.pact.sos_to_delays(torch.zeros(32, 32), g, 1.5, torch.zeros(49, 2), 256, out=torch.zeros(49, 256))
