@@ -152,9 +152,9 @@ PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v
 /* Adjoint of pact_sos_to_delays: dL_dsos[a][b] = scale * sum_{i,n} dL_dw[i][n] dw[i][n]/dsos[a][b],
  * with dw/dv = dl v0 / v^2 at every sample spread by the bilinear weights.
  * scale: optional DEVICE scalar (NULL = 1).  accumulate != 0 adds to dL_dsos.
- * ws: workspace of pact_sos_to_delays_adjoint_workspace_size() bytes.  The
- * result does not depend on the order of the floating-point sums across
- * workgroups (fixed-order reduction). */
+ * ws: workspace of pact_sos_to_delays_adjoint_workspace_size() bytes (this
+ * build needs none: the size is 0 and ws may be NULL).  Every node's sum is
+ * taken in a fixed order, so the result is deterministic. */
 PACT_API size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg, int N, const pact_ring* ring);
 PACT_API int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
                                const pact_ring* ring, int n_samples, const float* dL_dw, const float* scale,
@@ -202,10 +202,10 @@ PACT_API int pact_residual_loss(const float* Y, const float* H, const float* X, 
  *         with H from w and X the deconvolution of Y by H,
  *   dL_dw [N][n_elem] (overwritten; may be NULL),
  *   X_opt (may be NULL): the deconvolved full spectra [N][P][P].
- * ws: pact_loss_and_grad_workspace_size() bytes, zero-filled once when it is
- * allocated; every call leaves its counters at zero again, so the same
- * workspace can be reused (but not by two calls in flight at once).
- * Sums across workgroups are taken in a fixed order (deterministic).  M <= 16. */
+ * ws: pact_loss_and_grad_workspace_size() bytes of scratch for per-workgroup
+ * partial sums (not shared by two calls in flight).  Partial sums are combined
+ * in a fixed order and the gradient scatter uses exact integer arithmetic, so
+ * the result is deterministic.  M <= 16. */
 PACT_API size_t pact_loss_and_grad_workspace_size(int N, int M, int P, int n_elem);
 PACT_API int pact_loss_and_grad(const float* Y_half, const float* w, const float* centres, int N, const pact_ring* ring,
                        const float* d, int M, int P, float px, float eps, float* loss, float* dL_dw,
@@ -214,15 +214,19 @@ PACT_API int pact_loss_and_grad(const float* Y_half, const float* w, const float
 /* Total-variation term of Eq. jr (reading: anisotropic, over node pairs with at
  * least one free node, subgradient sign(0) = 0):
  *   loss += lambda * TV(sos),  grad += lambda * dTV/dsos  (grad over all nodes).
- * mask [G] uint8, nonzero = free node.  loss: DEVICE scalar (read-modify-write). */
+ * mask [G] uint8, nonzero = free node.  loss: DEVICE scalar, added to with one
+ * float atomic per workgroup (its last bits may differ between runs; grad does
+ * not). */
 PACT_API int pact_tv_grad(const float* sos, const unsigned char* mask, const pact_grid* sosg, float lambda, float* grad,
                  float* loss, void* stream);
 
 /* Adam step (Sec. 3.3) on the free nodes of sos (size n), PyTorch's update rule:
  *   t += 1; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  *   sos -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
- * fixed nodes untouched.  t: DEVICE int step counter (so that the step can be
- * replayed from a HIP graph). */
+ * fixed nodes untouched.  t: DEVICE int[2], zero-filled before the first step:
+ * t[0] counts completed steps (device-side, so that the step can be replayed
+ * from a HIP graph), t[1] is an internal arrival counter that every call
+ * leaves at zero.  Calls that overlap on the same t race. */
 PACT_API int pact_adam_step(float* sos, float* m, float* v, int* t, const unsigned char* mask, int n, const float* grad,
                    float lr, float b1, float b2, float eps, void* stream);
 

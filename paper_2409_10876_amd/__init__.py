@@ -2,13 +2,12 @@
 photoacoustic computed tomography (Li, Cui, Ma, Alexander, ICCV 2025).
 
 The computation lives in libpact.so (HIP kernels for gfx950 behind the C ABI of include/pact.h); this
-package is its ctypes binding (``pact``) and the optimisation driver (``solver``).  Importing the package
-loads the library and fails if it has not been built (``python -m paper_2409_10876_amd.build``).
+package is its ctypes binding (``pact``) and the optimisation driver (``solver``).  The library is loaded
+on first use; every call raises PactError if it has not been built (``python -m paper_2409_10876_amd.build``):
+there is no fallback implementation.
 """
 from . import pact  # noqa: F401
 from .pact import PactError, Geometry, load  # noqa: F401
-
-load()
 
 from .solver import (ScanData, PixelGridSolver, SosLoss, geometry_from, prepare_scan)  # noqa: E402,F401
 

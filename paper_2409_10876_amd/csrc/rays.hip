@@ -1,18 +1,34 @@
 // Straight-ray wavefront errors, Eq. TOF / Eq. wf (Sec. 3.1), and their adjoint.
 //
-// The node grid of SOS contrasts delta = v - v0 is staged in LDS with a one-node
-// ring of zeros (the fixed background), so that every midpoint sample inside
-// the clipped ray reads its four bilinear neighbours without a bounds test:
-// (G + 2)^2 floats, 80.6 KB at G = 140, two workgroups of 1024 threads per CU.
-// A ray (patch i, element n) is owned by a group of kLanes consecutive lanes;
-// lane l takes samples l, l + kLanes, ...; the group sums with cross-lane
-// shuffles.  The integrand is evaluated as delta / (v0 + delta) = 1 - v0 / v,
-// which keeps the contrast exact instead of cancelling 1 against v0 / v.
+// Forward.  The node grid of SOS contrasts delta = v - v0 is staged in LDS with a
+// one-node ring of zeros (the fixed background), so that every midpoint sample
+// inside the clipped ray reads its four bilinear neighbours without a bounds
+// test: (G + 2)^2 floats, 80.6 KB at G = 140, two workgroups of 1024 threads per
+// CU.  The element positions are tabulated in LDS once per workgroup.  A ray
+// (patch i, element n) is owned by kLanes consecutive lanes; lane l takes
+// samples l, l + kLanes, ... (two per iteration, so that two LDS gathers are in
+// flight), and the group sums with cross-lane shuffles.  The integrand is
+// evaluated as delta / (v0 + delta) = 1 - v0 / v, which keeps the contrast
+// exact instead of cancelling 1 against v0 / v.
 //
-// Adjoint: each workgroup privatises the gradient grid in LDS next to the SOS
-// grid (2 x 80.6 KB at G = 140, one workgroup per CU), scatters
-// dL/dw * dl * v0 / v^2 * (bilinear weight) with LDS float atomics, and writes
-// its partial grid; a second kernel sums the partials in a fixed order.
+// Adjoint (gather by tile).  dL/dv at a node collects dL/dw * dl * v0 / v^2 *
+// (bilinear weight) from every sample whose cell touches the node.  One
+// workgroup owns a kTile x kTile tile of nodes: it stages the contrast of the
+// tile and its one-node halo, and for every patch it enumerates only the
+// elements whose ray direction falls in the angular sector the tile's cell
+// region subtends from the patch centre (found by the same ring-hit mapping as
+// the wavefront interpolation); each such ray is clipped to the region.  Lane
+// t takes rays t, t + 256, ...: the lanes of a wave hold adjacent elements of
+// one patch, set up their rays together and run similar sample counts.  LDS
+// float atomics are slow on this GPU, so none are used: every
+// lane owns a private copy of the tile's accumulator (tile plus halo, so that
+// no corner needs a test), laid out node-major with the lane index fastest so
+// that a wave's read-modify-writes hit distinct banks; samples of the margin
+// that fall outside the region add zero.  The private copies of the interior
+// nodes are reduced in a fixed order and the tile is written once
+// (deterministic, no grid-sized partials).  The sample positions are computed
+// by the same code as in the forward pass, so the adjoint is the transpose of
+// the forward sum.
 #include "common.h"
 
 namespace pact {
@@ -21,155 +37,325 @@ int device_cu_count();
 
 namespace {
 
-constexpr int kLanes = 16;       // lanes per ray
-constexpr int kThreads = 1024;
+constexpr int kLanes = 16;        // lanes per ray (forward)
+constexpr int kThreads = 1024;    // forward workgroup
+#ifndef PACT_ADJ_TILE
+#define PACT_ADJ_TILE 4
+#endif
+constexpr int kTile = PACT_ADJ_TILE;  // adjoint tile side (nodes)
+constexpr int kAdjThreads = 256;      // adjoint workgroup
 
 struct RayGeo {
     float inv_ds;       // 1 / node spacing
     float off_x;        // (Gx + 1) / 2: padded node coordinate of x = 0
     float off_y;
     float hx, hy;       // half-extent of the box where v differs from v0
+    float inv_ns;       // 1 / n_samples
     int Gx, Gy, W;      // W = Gx + 2 (padded row length)
 };
 
-__device__ __forceinline__ void load_contrast(float* vs, const float* __restrict__ sos, float v0, const RayGeo& g) {
-    const int total = (g.Gy + 2) * g.W;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int a = idx / g.W - 1, b = idx % g.W - 1;
-        vs[idx] = (a >= 0 && a < g.Gy && b >= 0 && b < g.Gx) ? sos[a * g.Gx + b] - v0 : 0.0f;
+// Element positions, identical in the forward and the adjoint kernels.
+__device__ __forceinline__ void load_elements(float* ex, float* ey, int n_elem, float R, float phi0) {
+    for (int n = threadIdx.x; n < n_elem; n += blockDim.x) {
+        float sn, cs;
+        sincosf(phi0 + kTwoPi * (static_cast<float>(n) / n_elem), &sn, &cs);
+        ex[n] = R * cs;
+        ey[n] = R * sn;
     }
 }
 
-// Geometry of ray (i, n): padded node coordinates of the start point, their increment per step,
-// and the step length.
-__device__ __forceinline__ void ray_setup(const float* __restrict__ centres, int i, int n, int n_elem, float R,
-                                          float phi0, int Ns, const RayGeo& g, float& gx0, float& gy0, float& dgx,
-                                          float& dgy, float& dl) {
-    const float cx = centres[2 * i], cy = centres[2 * i + 1];
-    float sn, cs;
-    sincosf(phi0 + kTwoPi * (static_cast<float>(n) / n_elem), &sn, &cs);
-    const float dx = R * cs - cx, dy = R * sn - cy;
-    const float dist = sqrtf(dx * dx + dy * dy);
-    const float ux = dx / dist, uy = dy / dist;
-    float L = dist;
-    if (ux > 0.0f) L = fminf(L, (g.hx - cx) / ux);
-    if (ux < 0.0f) L = fminf(L, (-g.hx - cx) / ux);
-    if (uy > 0.0f) L = fminf(L, (g.hy - cy) / uy);
-    if (uy < 0.0f) L = fminf(L, (-g.hy - cy) / uy);
+// Geometry of ray (centre c, element e): padded node coordinates of the start point and their
+// increment per sample step, and the step length dl = L / n_samples.
+__device__ __forceinline__ void ray_setup(float cx, float cy, float ex, float ey, const RayGeo& g, float& gx0,
+                                          float& gy0, float& dgx, float& dgy, float& dl) {
+    const float dx = ex - cx, dy = ey - cy;
+    const float d2 = fmaf(dx, dx, dy * dy);
+    const float inv = rsqrtf(d2);
+    const float ux = dx * inv, uy = dy * inv;
+    float L = d2 * inv;
+    if (ux != 0.0f) L = fminf(L, ((ux > 0.0f ? g.hx : -g.hx) - cx) * __builtin_amdgcn_rcpf(ux));
+    if (uy != 0.0f) L = fminf(L, ((uy > 0.0f ? g.hy : -g.hy) - cy) * __builtin_amdgcn_rcpf(uy));
     L = fmaxf(L, 0.0f);
-    dl = L / Ns;
+    dl = L * g.inv_ns;
     gx0 = fmaf(cx, g.inv_ds, g.off_x);
     gy0 = fmaf(cy, g.inv_ds, g.off_y);
     dgx = dl * ux * g.inv_ds;
     dgy = dl * uy * g.inv_ds;
 }
 
-// Padded cell index and fractions of a sample (clamped so that the 2 x 2 stencil stays in the grid).
-__device__ __forceinline__ int sample_cell(float gx, float gy, const RayGeo& g, float& fx, float& fy) {
+__device__ __forceinline__ float contrast_sample(const float* vs, float sf, float gx0, float gy0, float dgx, float dgy,
+                                                 const RayGeo& g) {
+    const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
     const float bf = floorf(gx), af = floorf(gy);
-    fx = gx - bf;
-    fy = gy - af;
-    const int b0 = min(max(static_cast<int>(bf), 0), g.Gx);
-    const int a0 = min(max(static_cast<int>(af), 0), g.Gy);
-    return a0 * g.W + b0;
+    const float fx = gx - bf, fy = gy - af;
+    // clamp so that the 2 x 2 stencil stays in the padded grid whatever the input
+    const int b0 = static_cast<int>(__builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx)));
+    const int a0 = static_cast<int>(__builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy)));
+    const int c = __mul24(a0, g.W) + b0;
+    const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + g.W], v11 = vs[c + g.W + 1];
+    const float top = fmaf(fx, v01 - v00, v00);
+    const float bot = fmaf(fx, v11 - v10, v10);
+    return fmaf(fy, bot - top, top);
 }
 
 __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restrict__ sos, float v0,
                                                             const float* __restrict__ centres, int N, int n_elem,
                                                             float R, float phi0, int Ns, RayGeo g,
                                                             float* __restrict__ w) {
-    extern __shared__ float vs[];
-    load_contrast(vs, sos, v0, g);
+    extern __shared__ float lds[];
+    float* ex = lds;
+    float* ey = ex + n_elem;
+    float* vs = ey + n_elem;
+    const int total = (g.Gy + 2) * g.W;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int a = idx / g.W - 1, b = idx % g.W - 1;
+        vs[idx] = (a >= 0 && a < g.Gy && b >= 0 && b < g.Gx) ? sos[a * g.Gx + b] - v0 : 0.0f;
+    }
+    load_elements(ex, ey, n_elem, R, phi0);
     __syncthreads();
     const int lane = threadIdx.x % kLanes;
-    const long long n_rays = static_cast<long long>(N) * n_elem;
-    const long long groups = static_cast<long long>(gridDim.x) * (blockDim.x / kLanes);
-    for (long long ray = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / kLanes; ray < n_rays;
-         ray += groups) {
-        const int i = static_cast<int>(ray / n_elem), n = static_cast<int>(ray % n_elem);
+    const int n_rays = N * n_elem;
+    const int groups = gridDim.x * (blockDim.x / kLanes);
+    for (int ray = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; ray < n_rays; ray += groups) {
+        const int i = ray / n_elem, n = ray - i * n_elem;
         float gx0, gy0, dgx, dgy, dl;
-        ray_setup(centres, i, n, n_elem, R, phi0, Ns, g, gx0, gy0, dgx, dgy, dl);
-        float acc = 0.0f;
-        for (int s = lane; s < Ns; s += kLanes) {
+        ray_setup(centres[2 * i], centres[2 * i + 1], ex[n], ey[n], g, gx0, gy0, dgx, dgy, dl);
+        float acc0 = 0.0f, acc1 = 0.0f;
+        int s = lane;
+        for (; s + kLanes < Ns; s += 2 * kLanes) {
             const float sf = static_cast<float>(s) + 0.5f;
-            float fx, fy;
-            const int c = sample_cell(fmaf(sf, dgx, gx0), fmaf(sf, dgy, gy0), g, fx, fy);
-            const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + g.W], v11 = vs[c + g.W + 1];
-            const float top = fmaf(fx, v01 - v00, v00);
-            const float bot = fmaf(fx, v11 - v10, v10);
-            const float dv = fmaf(fy, bot - top, top);
-            acc = fmaf(dv, __builtin_amdgcn_rcpf(v0 + dv), acc);
+            const float d0 = contrast_sample(vs, sf, gx0, gy0, dgx, dgy, g);
+            const float d1 = contrast_sample(vs, sf + static_cast<float>(kLanes), gx0, gy0, dgx, dgy, g);
+            acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
+            acc1 = fmaf(d1, __builtin_amdgcn_rcpf(v0 + d1), acc1);
         }
+        if (s < Ns) {
+            const float d0 = contrast_sample(vs, static_cast<float>(s) + 0.5f, gx0, gy0, dgx, dgy, g);
+            acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
+        }
+        float acc = acc0 + acc1;
 #pragma unroll
         for (int off = kLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanes);
         if (lane == 0) w[ray] = acc * dl;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void rays_adj_kernel(const float* __restrict__ sos, float v0,
-                                                            const float* __restrict__ centres, int N, int n_elem,
-                                                            float R, float phi0, int Ns, RayGeo g,
-                                                            const float* __restrict__ dL_dw,
-                                                            float* __restrict__ partial) {
+// Sector of the elements whose rays from (cx, cy) can cross the rectangle [x0, x1] x [y0, y1]:
+// a first element and a count (cyclic), with one element of margin on each side.
+__device__ __forceinline__ void sector(float cx, float cy, float x0, float x1, float y0, float y1, float R,
+                                       float phi0, int n_elem, int& first, int& count) {
+    if (cx >= x0 && cx <= x1 && cy >= y0 && cy <= y1) {
+        first = 0;
+        count = n_elem;
+        return;
+    }
+    const float ref = atan2f(0.5f * (y0 + y1) - cy, 0.5f * (x0 + x1) - cx);
+    float lo = 0.0f, hi = 0.0f;
+    const float xs[4] = {x0, x1, x0, x1}, ys[4] = {y0, y0, y1, y1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float d = atan2f(ys[k] - cy, xs[k] - cx) - ref;
+        d -= kTwoPi * rintf(d * (1.0f / kTwoPi));           // wrap to [-pi, pi]
+        lo = fminf(lo, d);
+        hi = fmaxf(hi, d);
+    }
+    const float R2mc2 = R * R - (cx * cx + cy * cy);
+    const float nf = static_cast<float>(n_elem);
+    float sl, cl, sh, ch;
+    sincosf(ref + lo, &sl, &cl);
+    sincosf(ref + hi, &sh, &ch);
+    const float flo = ring_hit_index(cx, cy, cl, sl, R2mc2, phi0, nf / kTwoPi, nf);
+    float fhi = ring_hit_index(cx, cy, ch, sh, R2mc2, phi0, nf / kTwoPi, nf);
+    if (fhi < flo) fhi += nf;
+    const int a = static_cast<int>(floorf(flo)) - 1;
+    const int b = static_cast<int>(floorf(fhi)) + 2;
+    count = min(max(b - a, 0), n_elem);
+    first = ((a % n_elem) + n_elem) % n_elem;
+}
+
+// Clipped sample range [s0, s1] of a ray inside the tile region (padded node coordinates gx in
+// [b_lo, b_hi + 1), gy in [a_lo, a_hi + 1)), one sample of margin on each side; empty if s1 < s0.
+__device__ __forceinline__ void clip_samples(float gx0, float gy0, float dgx, float dgy, int a_lo, int a_hi, int b_lo,
+                                             int b_hi, int Ns, int& s0, int& s1) {
+    float slo = 0.0f, shi = static_cast<float>(Ns);
+    bool empty = false;
+    if (dgx != 0.0f) {
+        const float r = __builtin_amdgcn_rcpf(dgx);
+        const float t0 = (b_lo - gx0) * r, t1 = (b_hi + 1 - gx0) * r;
+        slo = fmaxf(slo, fminf(t0, t1));
+        shi = fminf(shi, fmaxf(t0, t1));
+    } else {
+        empty = gx0 < b_lo || gx0 >= b_hi + 1;
+    }
+    if (dgy != 0.0f) {
+        const float r = __builtin_amdgcn_rcpf(dgy);
+        const float t0 = (a_lo - gy0) * r, t1 = (a_hi + 1 - gy0) * r;
+        slo = fmaxf(slo, fminf(t0, t1));
+        shi = fminf(shi, fmaxf(t0, t1));
+    } else {
+        empty = empty || gy0 < a_lo || gy0 >= a_hi + 1;
+    }
+    if (empty || !(shi >= slo)) {
+        s0 = 0;
+        s1 = -1;
+        return;
+    }
+    s0 = max(static_cast<int>(ceilf(slo - 0.5f)) - 1, 0);
+    s1 = min(static_cast<int>(floorf(shi - 0.5f)) + 1, Ns - 1);
+}
+
+__global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
+    const float* __restrict__ sos, float v0, const float* __restrict__ centres, int N, int n_elem, float R, float phi0,
+    int Ns, RayGeo g, int tiles_x, const float* __restrict__ dL_dw, const float* __restrict__ scale, int accumulate,
+    float* __restrict__ out) {
+    constexpr int L = kTile + 2;                      // local nodes per side, including the halo
+    constexpr int NN = L * L;                         // accumulator nodes per lane
+    __shared__ float dv[NN];                          // contrast on the tile's nodes and halo
+    __shared__ int scan_a[kAdjThreads], scan_b[kAdjThreads];
     extern __shared__ float lds[];
-    float* vs = lds;
-    float* gacc = lds + (g.Gy + 2) * g.W;
-    load_contrast(vs, sos, v0, g);
-    for (int idx = threadIdx.x; idx < (g.Gy + 2) * g.W; idx += blockDim.x) gacc[idx] = 0.0f;
+    float* acc = lds;                                 // per-lane accumulators, [node][thread]
+    float* ex = acc + NN * kAdjThreads;
+    float* ey = ex + n_elem;
+    int* first = reinterpret_cast<int*>(ey + n_elem);  // [N] first element of each patch's sector
+    int* cnt = first + N;                              // [N] elements in the sector
+    int* offs = cnt + N;                               // [N + 1] exclusive prefix sum of cnt
+
+    const int tid = threadIdx.x;
+    const int ty = blockIdx.x / tiles_x, tx = blockIdx.x % tiles_x;
+    const int a_lo = ty * kTile, a_hi = min(a_lo + kTile, g.Gy);
+    const int b_lo = tx * kTile, b_hi = min(b_lo + kTile, g.Gx);
+    const int th = a_hi - a_lo, tw = b_hi - b_lo;      // interior extent (ragged at the grid edge)
+    // local node (la, lb) is grid node (a_lo - 1 + la, b_lo - 1 + lb); interior nodes have la, lb in 1..kTile
+    for (int idx = tid; idx < NN; idx += blockDim.x) {
+        const int a = a_lo - 1 + idx / L, b = b_lo - 1 + idx % L;
+        dv[idx] = (a >= 0 && a < g.Gy && b >= 0 && b < g.Gx) ? sos[a * g.Gx + b] - v0 : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < NN; ++j) acc[j * kAdjThreads + tid] = 0.0f;
+    load_elements(ex, ey, n_elem, R, phi0);
+    // Samples that touch the tile have their cell in rows a_lo-1 .. a_hi-1 and columns b_lo-1 .. b_hi-1,
+    // i.e. padded node coordinates gy in [a_lo, a_hi + 1), gx in [b_lo, b_hi + 1).
+    const float ds = 1.0f / g.inv_ds;
+    const float x0 = (b_lo - g.off_x) * ds, x1 = (b_hi + 1 - g.off_x) * ds;
+    const float y0 = (a_lo - g.off_y) * ds, y1 = (a_hi + 1 - g.off_y) * ds;
+    const float margin = 1e-3f * ds;
+    // 1. per-patch element sectors; thread t owns the contiguous run of patches t * per .. t * per + per - 1
+    const int per = (N + kAdjThreads - 1) / kAdjThreads;
+    int run = 0;
+    for (int k = 0; k < per; ++k) {
+        const int i = tid * per + k;
+        if (i < N) {
+            int f, c;
+            sector(centres[2 * i], centres[2 * i + 1], x0 - margin, x1 + margin, y0 - margin, y1 + margin, R, phi0,
+                   n_elem, f, c);
+            first[i] = f;
+            cnt[i] = c;
+            run += c;
+        }
+    }
+    // inclusive scan of per-thread values (Hillis-Steele, double-buffered); returns the inclusive prefix
+    auto block_scan = [&](int v) -> int {
+        scan_a[tid] = v;
+        __syncthreads();
+        int* src = scan_a;
+        int* dst = scan_b;
+        for (int off = 1; off < kAdjThreads; off <<= 1) {
+            dst[tid] = src[tid] + (tid >= off ? src[tid - off] : 0);
+            __syncthreads();
+            int* t = src;
+            src = dst;
+            dst = t;
+        }
+        const int r = src[tid];
+        __syncthreads();
+        return r;
+    };
+    {
+        int s0 = block_scan(run) - run;
+        for (int k = 0; k < per; ++k) {
+            const int i = tid * per + k;
+            if (i < N) {
+                offs[i] = s0;
+                s0 += cnt[i];
+            }
+        }
+        if (tid == kAdjThreads - 1) offs[N] = s0;
+    }
     __syncthreads();
-    const int lane = threadIdx.x % kLanes;
-    const long long n_rays = static_cast<long long>(N) * n_elem;
-    const long long groups = static_cast<long long>(gridDim.x) * (blockDim.x / kLanes);
-    for (long long ray = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / kLanes; ray < n_rays;
-         ray += groups) {
-        const float gw = dL_dw[ray];
-        if (gw == 0.0f) continue;
-        const int i = static_cast<int>(ray / n_elem), n = static_cast<int>(ray % n_elem);
+    const int total = offs[N];
+    const float sc = (scale ? *scale : 1.0f) * v0;
+
+    // 2. lane t takes items t, t + 256, ...: the 64 lanes of a wave hold 64 adjacent elements of one or
+    // two patches, so they set up their rays together and have similar sample counts
+    float* my = acc + tid;
+    for (int k = tid; k < total; k += kAdjThreads) {
+        int lo = 0, hi = N - 1;                        // patch of item k: the last i with offs[i] <= k
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        const int i = lo;
+        const int n = (first[i] + (k - offs[i])) % n_elem;
         float gx0, gy0, dgx, dgy, dl;
-        ray_setup(centres, i, n, n_elem, R, phi0, Ns, g, gx0, gy0, dgx, dgy, dl);
-        const float scale = gw * dl * v0;
-        for (int s = lane; s < Ns; s += kLanes) {
-            const float sf = static_cast<float>(s) + 0.5f;
-            float fx, fy;
-            const int c = sample_cell(fmaf(sf, dgx, gx0), fmaf(sf, dgy, gy0), g, fx, fy);
-            const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + g.W], v11 = vs[c + g.W + 1];
+        ray_setup(centres[2 * i], centres[2 * i + 1], ex[n], ey[n], g, gx0, gy0, dgx, dgy, dl);
+        int s0, s1;
+        clip_samples(gx0, gy0, dgx, dgy, a_lo, a_hi, b_lo, b_hi, Ns, s0, s1);
+        const float q0 = dL_dw[static_cast<size_t>(i) * n_elem + n] * dl * sc;
+        // every sample is tested: margin samples, and samples of rays grazing an edge of the region, can
+        // fall outside it; they add zero to node 0
+        float sf = static_cast<float>(s0) + 0.5f;
+        for (int s = s0; s <= s1; ++s, sf += 1.0f) {
+            const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
+            const float bf = floorf(gx), af = floorf(gy);
+            int lb = static_cast<int>(bf) - b_lo;         // local column of the cell's first node
+            int la = static_cast<int>(af) - a_lo;
+            const bool inside = static_cast<unsigned>(lb) <= static_cast<unsigned>(tw) &&
+                                static_cast<unsigned>(la) <= static_cast<unsigned>(th);
+            const float qs = inside ? q0 : 0.0f;
+            lb = inside ? lb : 0;
+            la = inside ? la : 0;
+            const int c = la * L + lb;
+            const float fx = gx - bf, fy = gy - af;
+            const float v00 = dv[c], v01 = dv[c + 1], v10 = dv[c + L], v11 = dv[c + L + 1];
             const float top = fmaf(fx, v01 - v00, v00);
             const float bot = fmaf(fx, v11 - v10, v10);
             const float r = __builtin_amdgcn_rcpf(v0 + fmaf(fy, bot - top, top));
-            const float q = scale * r * r;                      // dL/dw * dl * v0 / v^2
-            const float qy1 = q * fy, qy0 = q - qy1;
-            atomicAdd(&gacc[c], qy0 - qy0 * fx);
-            atomicAdd(&gacc[c + 1], qy0 * fx);
-            atomicAdd(&gacc[c + g.W], qy1 - qy1 * fx);
-            atomicAdd(&gacc[c + g.W + 1], qy1 * fx);
+            const float qv = qs * r * r;                  // dL/dw * dl * v0 / v^2
+            const float qy1 = qv * fy, qy0 = qv - qy1;
+            float* p = my + c * kAdjThreads;
+            p[0] += qy0 - qy0 * fx;
+            p[kAdjThreads] += qy0 * fx;
+            p[L * kAdjThreads] += qy1 - qy1 * fx;
+            p[(L + 1) * kAdjThreads] += qy1 * fx;
         }
     }
     __syncthreads();
-    float* dst = partial + static_cast<size_t>(blockIdx.x) * g.Gy * g.Gx;
-    for (int idx = threadIdx.x; idx < g.Gy * g.Gx; idx += blockDim.x) {
-        const int a = idx / g.Gx, b = idx % g.Gx;
-        dst[idx] = gacc[(a + 1) * g.W + b + 1];
+    // 3. fixed-order reduction of the interior nodes' columns: each 16-lane group sums the 256 columns of
+    // one node (16 strided columns per lane, then shuffles)
+    const int part = tid & 15;
+    for (int j = tid >> 4; j < kTile * kTile; j += kAdjThreads / 16) {
+        const int la = j / kTile, lb = j % kTile;
+        const float* col = acc + ((la + 1) * L + (lb + 1)) * kAdjThreads;
+        float sum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kAdjThreads / 16; ++q) sum += col[part + 16 * q];
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 16);
+        if (part == 0 && la < th && lb < tw) {
+            const size_t o = static_cast<size_t>(a_lo + la) * g.Gx + (b_lo + lb);
+            out[o] = accumulate ? out[o] + sum : sum;
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void sum_partials_kernel(const float* __restrict__ partial, int nparts, int n,
-                                                           const float* __restrict__ scale, int accumulate,
-                                                           float* __restrict__ out) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
-    float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += partial[static_cast<size_t>(p) * n + idx];
-    if (scale) s *= *scale;
-    out[idx] = accumulate ? out[idx] + s : s;
-}
-
-RayGeo make_geo(const pact_grid& sosg) {
+RayGeo make_geo(const pact_grid& sosg, int n_samples) {
     RayGeo g;
     g.inv_ds = 1.0f / sosg.spacing;
     g.off_x = 0.5f * (sosg.nx + 1);
     g.off_y = 0.5f * (sosg.ny + 1);
     g.hx = 0.5f * (sosg.nx + 1) * sosg.spacing;
     g.hy = 0.5f * (sosg.ny + 1) * sosg.spacing;
+    g.inv_ns = 1.0f / static_cast<float>(n_samples);
     g.Gx = sosg.nx;
     g.Gy = sosg.ny;
     g.W = sosg.nx + 2;
@@ -183,10 +369,9 @@ int check_rays(const float* sos, pact_grid sosg, float v0, const float* centres,
     PACT_CHECK_ARG(v0 > 0.0f && std::isfinite(v0), "%s: v0 must be positive", what);
     if (int s = check_ring(ring)) return s;
     if (int s = check_grid(sosg, what)) return s;
+    PACT_CHECK_SUPPORTED(static_cast<long long>(N) * ring.n_elem < (1LL << 31), "%s: too many rays", what);
     return PACT_OK;
 }
-
-int adj_blocks() { return device_cu_count(); }
 
 }  // namespace
 }  // namespace pact
@@ -203,13 +388,14 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
     clear_error();
     if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_sos_to_delays")) return s;
     PACT_CHECK_ARG(w, "pact_sos_to_delays: null output");
-    const size_t lds = static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2) * sizeof(float);
+    const size_t lds = (static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2) + 2 * static_cast<size_t>(ring.n_elem)) *
+                       sizeof(float);
     PACT_CHECK_SUPPORTED(lds <= kLdsBytes, "pact_sos_to_delays: SOS grid %d x %d does not fit in LDS", sosg.ny,
                          sosg.nx);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_fwd_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
         attr = true;
     }
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
@@ -217,24 +403,23 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
     const int blocks = static_cast<int>(std::min<long long>((n_rays + per_block - 1) / per_block,
                                                             2LL * device_cu_count()));
     rays_fwd_kernel<<<blocks, kThreads, lds, as_stream(stream)>>>(sos, v0, centres, N, ring.n_elem, ring.radius,
-                                                                 ring.phi0, n_samples, make_geo(sosg), w);
+                                                                 ring.phi0, n_samples, make_geo(sosg, n_samples), w);
     return launch_status("pact_sos_to_delays");
 }
 
 extern "C" size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg_, int N, const pact_ring* ring_) {
-    if (!sosg_ || !ring_) return 0;
-    const pact_grid sosg = *sosg_;
-    const pact_ring ring = *ring_;
+    (void)sosg_;
     (void)N;
-    (void)ring;
-    if (sosg.ny <= 0 || sosg.nx <= 0) return 0;
-    return static_cast<size_t>(pact::adj_blocks()) * sosg.ny * sosg.nx * sizeof(float);
+    (void)ring_;
+    return 0;
 }
 
-extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg_, float v0, const float* centres, int N,
-                                          const pact_ring* ring_, int n_samples, const float* dL_dw, const float* scale,
-                                          float* dL_dsos, int accumulate, void* ws, size_t ws_bytes,
-                                          void* stream) {
+extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg_, float v0, const float* centres,
+                                          int N, const pact_ring* ring_, int n_samples, const float* dL_dw,
+                                          const float* scale, float* dL_dsos, int accumulate, void* ws,
+                                          size_t ws_bytes, void* stream) {
+    (void)ws;
+    (void)ws_bytes;
     if (!sosg_ || !ring_) {
         pact::set_error("pact_sos_to_delays_adjoint: null geometry pointer");
         return PACT_EINVAL;
@@ -245,28 +430,21 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     clear_error();
     if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_sos_to_delays_adjoint")) return s;
     PACT_CHECK_ARG(dL_dw && dL_dsos, "pact_sos_to_delays_adjoint: null pointer");
-    const size_t lds = 2 * static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2) * sizeof(float);
-    PACT_CHECK_SUPPORTED(lds <= kLdsBytes, "pact_sos_to_delays_adjoint: SOS grid %d x %d does not fit in LDS",
-                         sosg.ny, sosg.nx);
-    const size_t need = pact_sos_to_delays_adjoint_workspace_size(&sosg, N, &ring);
-    if (!ws || ws_bytes < need) {
-        set_error("pact_sos_to_delays_adjoint: workspace of %zu bytes needed, %zu given", need, ws_bytes);
-        return PACT_EWORKSPACE;
-    }
+    const size_t lds = static_cast<size_t>(kTile + 2) * (kTile + 2) * kAdjThreads * sizeof(float) +
+                       2 * static_cast<size_t>(ring.n_elem) * sizeof(float) +
+                       (3 * static_cast<size_t>(N) + 1) * sizeof(int);
+    PACT_CHECK_SUPPORTED(lds + 4 * 1024 <= kLdsBytes,
+                         "pact_sos_to_delays_adjoint: %d patches x %d elements exceed the LDS work tables", N,
+                         ring.n_elem);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_tile_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes - 8 * 1024));
         attr = true;
     }
-    const int blocks = adj_blocks();
-    float* partial = static_cast<float*>(ws);
-    rays_adj_kernel<<<blocks, kThreads, lds, as_stream(stream)>>>(sos, v0, centres, N, ring.n_elem, ring.radius,
-                                                                 ring.phi0, n_samples, make_geo(sosg), dL_dw,
-                                                                 partial);
-    if (int s = launch_status("pact_sos_to_delays_adjoint")) return s;
-    const int n = sosg.ny * sosg.nx;
-    sum_partials_kernel<<<ceil_div(n, 256), 256, 0, as_stream(stream)>>>(partial, blocks, n, scale, accumulate,
-                                                                        dL_dsos);
-    return launch_status("pact_sos_to_delays_adjoint (sum)");
+    const int tiles_x = ceil_div(sosg.nx, kTile), tiles_y = ceil_div(sosg.ny, kTile);
+    rays_adj_tile_kernel<<<tiles_x * tiles_y, kAdjThreads, lds, as_stream(stream)>>>(
+        sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), tiles_x,
+        dL_dw, scale, accumulate, dL_dsos);
+    return launch_status("pact_sos_to_delays_adjoint");
 }

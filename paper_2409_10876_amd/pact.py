@@ -317,5 +317,5 @@ def tv_grad(sos, mask, g: Geometry, lam, grad, loss):
 def adam_step(sos, m, v, t, mask, grad, lr, b1=0.9, b2=0.999, eps=1e-8):
     n = sos.numel()
     _check(load().pact_adam_step(_ptr(sos, F32, "sos"), _ptr(m, F32, "m", n), _ptr(v, F32, "v", n),
-                                 _ptr(t, I32, "t", 1), _ptr(mask, U8, "mask", n), n, _ptr(grad, F32, "grad", n),
+                                 _ptr(t, I32, "t", 2), _ptr(mask, U8, "mask", n), n, _ptr(grad, F32, "grad", n),
                                  lr, b1, b2, eps, _stream()), "pact_adam_step")

@@ -76,7 +76,7 @@ class PixelGridSolver:
         self.sos = sos.contiguous()
         self.m = torch.zeros_like(self.sos)
         self.v = torch.zeros_like(self.sos)
-        self.t = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.t = torch.zeros(2, dtype=torch.int32, device=dev)
         N = scan.centres.shape[0]
         M = scan.d.numel()
         self.w = torch.empty(N, g.n_elem, dtype=F32, device=dev)

@@ -73,9 +73,12 @@ def test_argument_errors(P):
     s, msg = _status(P, "pact_loss_and_grad", FAKE, FAKE, FAKE, 49, ring, FAKE, 5, 32, 0.2, 1e-6, FAKE, FAKE, None,
                      FAKE, 16, None)
     assert s == -3 and "workspace" in msg
-    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, sosg, 1.5, FAKE, 49, ring, 256, FAKE, None, FAKE, 0,
-                     FAKE, 4, None)
-    assert s == -3
+    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, sosg, 1.5, FAKE, 49, ring, 0, FAKE, None, FAKE, 0,
+                     None, 0, None)
+    assert s == -1 and "n_samples" in msg
+    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, None, 1.5, FAKE, 49, ring, 256, FAKE, None, FAKE, 0,
+                     None, 0, None)
+    assert s == -1 and "geometry" in msg
     s, msg = _status(P, "pact_residual_loss", FAKE, FAKE, FAKE, 4, 3, 8, 0.1, FAKE, None, None, FAKE, 0, None)
     assert s == -3
     s, msg = _status(P, "pact_adam_step", FAKE, FAKE, FAKE, FAKE, FAKE, 10, FAKE, 1e-3, 1.0, 0.999, 1e-8, None)
