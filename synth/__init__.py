@@ -14,6 +14,7 @@ from .configs import Scan, TINY, PAPER, WORKLOADS, describe, uniform_delays, del
 from .phantoms import (SosPhantom, Blobs, make_sos_phantom, make_blobs, render_ip, sos_grid_truth,
                        free_node_mask, axis)
 from .channels import channel_data, travel_times, point_source_data
+from . import nf  # noqa: F401
 
 
 @dataclass
