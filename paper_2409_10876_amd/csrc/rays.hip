@@ -54,14 +54,31 @@ struct RayGeo {
     int Gx, Gy, W;      // W = Gx + 2 (padded row length)
 };
 
-// Element positions, identical in the forward and the adjoint kernels.
+// Element positions, computed by the same code in every kernel that traces rays.
+__device__ __forceinline__ void element_position(int n, int n_elem, float R, float phi0, float& ex, float& ey) {
+    float sn, cs;
+    sincosf(phi0 + kTwoPi * (static_cast<float>(n) / n_elem), &sn, &cs);
+    ex = R * cs;
+    ey = R * sn;
+}
+
 __device__ __forceinline__ void load_elements(float* ex, float* ey, int n_elem, float R, float phi0) {
-    for (int n = threadIdx.x; n < n_elem; n += blockDim.x) {
-        float sn, cs;
-        sincosf(phi0 + kTwoPi * (static_cast<float>(n) / n_elem), &sn, &cs);
-        ex[n] = R * cs;
-        ey[n] = R * sn;
-    }
+    for (int n = threadIdx.x; n < n_elem; n += blockDim.x) element_position(n, n_elem, R, phi0, ex[n], ey[n]);
+}
+
+// Block maximum (deterministic); `red` must hold blockDim.x / 64 floats.  Result valid in every thread.
+__device__ __forceinline__ float block_max(float v, float* red) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    float t = red[0];
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 1; i < nw; ++i) t = fmaxf(t, red[i]);
+    return t;
 }
 
 // Geometry of ray (centre c, element e): padded node coordinates of the start point and their
@@ -348,6 +365,122 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
     }
 }
 
+// Adjoint (scatter over the whole grid).  Used when the contrast grid and an integer accumulator of the
+// same shape both fit in one CU's LDS (G <= 141).  One 1024-thread workgroup per CU; the rays are cut
+// into K segments of consecutive samples (K chosen on the host so that the work is about one segment
+// per lane) and work item (ray, segment) goes to one lane, which walks its samples with the same
+// position formula as the forward pass.  Rays are numbered element-major, so that the lanes of a wave
+// hold parallel rays from neighbouring patch centres and rarely hit the same node at once.  Every
+// sample adds its four bilinear shares to the accumulator with integer LDS atomics, in fixed point at
+// a power-of-two scale F chosen per workgroup from a bound on any node's sum:
+//   |sum| <= sum over the workgroup's rays of |dL/dw * sc| * v0 / vmin^2 * (2 sqrt(2) ds + dl),
+// since a ray meets a node's bilinear support over at most 2 sqrt(2) ds and every weight is <= 1.
+// F = 2^30 / bound (rounded down to a power of two) keeps every partial sum inside int32 with room for
+// the truncation of each term.  Integer sums do not depend on the order of the atomics, so the result is
+// deterministic.  The interior nodes are written, scaled back, to one partial grid per workgroup, and
+// rays_adj_reduce_kernel adds the partial grids in a fixed order.
+constexpr int kGridThreads = 1024;
+
+__global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
+    const float* __restrict__ sos, float v0, const float* __restrict__ centres, int N, int n_elem, float R, float phi0,
+    int Ns, RayGeo g, int K, int n_items, int per_block, const float* __restrict__ dL_dw,
+    const float* __restrict__ scale, float* __restrict__ partial) {
+    extern __shared__ float lds[];
+    const int W = g.W;
+    const int total = (g.Gy + 2) * W;
+    float* vs = lds;                                        // contrast with a ring of zeros
+    int* acc = reinterpret_cast<int*>(vs + total);          // fixed-point sums, same layout
+    float* red = reinterpret_cast<float*>(acc + total);     // kGridThreads / 64 floats
+    const int tid = threadIdx.x;
+    float vmin = v0, nan_check = 0.0f;                     // nan_check turns NaN if any node is not finite
+    for (int idx = tid; idx < total; idx += blockDim.x) {
+        const int a = idx / W - 1, b = idx % W - 1;
+        const float d = (a >= 0 && a < g.Gy && b >= 0 && b < g.Gx) ? sos[a * g.Gx + b] - v0 : 0.0f;
+        vs[idx] = d;
+        acc[idx] = 0;
+        vmin = fminf(vmin, v0 + d);
+        nan_check += 0.0f * d;
+    }
+    vmin = -block_max(-vmin, red);
+    const int it0 = blockIdx.x * per_block;
+    const int it1 = min(it0 + per_block, n_items);
+    const float sc = (scale ? *scale : 1.0f) * v0;
+    const float ds = 1.0f / g.inv_ds;
+    // bound on any node's sum over this workgroup's rays
+    float bnd = 0.0f;
+    if (it1 > it0) {
+        for (int ray = it0 / K + tid; ray <= (it1 - 1) / K; ray += blockDim.x) {
+            const int n = ray / N, i = ray - n * N;
+            float ex, ey;
+            element_position(n, n_elem, R, phi0, ex, ey);
+            float gx0, gy0, dgx, dgy, dl;
+            ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
+            bnd += fabsf(dL_dw[static_cast<size_t>(i) * n_elem + n] * sc) * (2.8285f * ds + dl);
+        }
+    }
+    bnd = block_sum(bnd + nan_check, red) / (vmin * vmin);
+    const bool ok = vmin > 0.0f && bnd <= 3.0e38f;        // false for NaN or infinite bounds too
+    const float F = (ok && bnd > 0.0f) ? ldexpf(1.0f, min(30 - (ilogbf(bnd) + 1), 126)) : 1.0f;
+    __syncthreads();
+
+    for (int item = it0 + tid; item < it1; item += blockDim.x) {
+        const int ray = item / K, k = item - ray * K;
+        const int n = ray / N, i = ray - n * N;
+        float ex, ey;
+        element_position(n, n_elem, R, phi0, ex, ey);
+        float gx0, gy0, dgx, dgy, dl;
+        ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
+        const float q0 = ok ? dL_dw[static_cast<size_t>(i) * n_elem + n] * dl * sc * F : 0.0f;
+        const int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
+        float sf = static_cast<float>(s0) + 0.5f;
+        for (int s = s0; s < s1; ++s, sf += 1.0f) {
+            const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
+            const float bf = floorf(gx), af = floorf(gy);
+            const float fx = gx - bf, fy = gy - af;
+            const int b0 = static_cast<int>(__builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx)));
+            const int a0 = static_cast<int>(__builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy)));
+            const int c = __mul24(a0, W) + b0;
+            const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
+            const float top = fmaf(fx, v01 - v00, v00);
+            const float bot = fmaf(fx, v11 - v10, v10);
+            const float r = __builtin_amdgcn_rcpf(v0 + fmaf(fy, bot - top, top));
+            const float qv = q0 * r * r;                     // dL/dw * dl * v0 / v^2, times F
+            const float qy1 = qv * fy, qy0 = qv - qy1;
+            // truncation toward zero: at most one unit of 2^-30 of the bound per term
+            atomicAdd(acc + c, static_cast<int>(qy0 - qy0 * fx));
+            atomicAdd(acc + c + 1, static_cast<int>(qy0 * fx));
+            atomicAdd(acc + c + W, static_cast<int>(qy1 - qy1 * fx));
+            atomicAdd(acc + c + W + 1, static_cast<int>(qy1 * fx));
+        }
+    }
+    __syncthreads();
+    const float invF = 1.0f / F;
+    const float bad = __builtin_nanf("");
+    float* part = partial + static_cast<size_t>(blockIdx.x) * g.Gy * g.Gx;
+    for (int idx = tid; idx < g.Gy * g.Gx; idx += blockDim.x) {
+        const int a = idx / g.Gx, b = idx - a * g.Gx;
+        part[idx] = ok ? static_cast<float>(acc[(a + 1) * W + b + 1]) * invF : bad;
+    }
+}
+
+// out[node] (=|+=) sum over the partial grids, in a fixed order: 64 nodes per workgroup, four slices of the
+// partial grids per node, then the four slice sums in order.
+__global__ __launch_bounds__(256) void rays_adj_reduce_kernel(const float* __restrict__ partial, int n_part,
+                                                             int n_nodes, int accumulate, float* __restrict__ out) {
+    __shared__ float sl[4][64];
+    const int node = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int slice = threadIdx.x >> 6;
+    float s = 0.0f;
+    if (node < n_nodes)
+        for (int p = slice; p < n_part; p += 4) s += partial[static_cast<size_t>(p) * n_nodes + node];
+    sl[slice][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (threadIdx.x < 64 && node < n_nodes) {
+        const float t = (sl[0][threadIdx.x] + sl[1][threadIdx.x]) + (sl[2][threadIdx.x] + sl[3][threadIdx.x]);
+        out[node] = accumulate ? out[node] + t : t;
+    }
+}
+
 RayGeo make_geo(const pact_grid& sosg, int n_samples) {
     RayGeo g;
     g.inv_ds = 1.0f / sosg.spacing;
@@ -407,19 +540,48 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
     return launch_status("pact_sos_to_delays");
 }
 
+namespace pact {
+namespace {
+
+// LDS bytes of rays_adj_grid_kernel; 0 if the grid does not fit (the tile kernel is used instead).
+size_t adj_grid_lds(const pact_grid& sosg) {
+    const size_t nodes = static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2);
+    const size_t lds = 2 * nodes * sizeof(float) + (kGridThreads / 64) * sizeof(float);
+    return lds <= kLdsBytes ? lds : 0;
+}
+
+// Segments per ray for rays_adj_grid_kernel: the K that minimises the critical path of one lane, rounds of
+// items times (segment length + a ray set-up worth about two samples), with at least 8 samples a segment.
+int adj_segments(long long n_rays, int n_samples, long long lanes) {
+    int best = 1;
+    long long best_cost = -1;
+    const int kmax = std::max(1, std::min(n_samples / 8, 256));
+    for (int K = 1; K <= kmax; ++K) {
+        const long long rounds = (n_rays * K + lanes - 1) / lanes;
+        const long long cost = rounds * ((n_samples + K - 1) / K + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = K;
+        }
+    }
+    return best;
+}
+
+}  // namespace
+}  // namespace pact
+
 extern "C" size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg_, int N, const pact_ring* ring_) {
-    (void)sosg_;
     (void)N;
     (void)ring_;
-    return 0;
+    if (!sosg_ || sosg_->ny <= 0 || sosg_->nx <= 0) return 0;
+    if (!pact::adj_grid_lds(*sosg_)) return 0;
+    return static_cast<size_t>(pact::device_cu_count()) * sosg_->ny * sosg_->nx * sizeof(float);
 }
 
 extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg_, float v0, const float* centres,
                                           int N, const pact_ring* ring_, int n_samples, const float* dL_dw,
                                           const float* scale, float* dL_dsos, int accumulate, void* ws,
                                           size_t ws_bytes, void* stream) {
-    (void)ws;
-    (void)ws_bytes;
     if (!sosg_ || !ring_) {
         pact::set_error("pact_sos_to_delays_adjoint: null geometry pointer");
         return PACT_EINVAL;
@@ -430,6 +592,34 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     clear_error();
     if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_sos_to_delays_adjoint")) return s;
     PACT_CHECK_ARG(dL_dw && dL_dsos, "pact_sos_to_delays_adjoint: null pointer");
+    if (const size_t glds = adj_grid_lds(sosg)) {
+        const int blocks = device_cu_count();
+        const size_t need = static_cast<size_t>(blocks) * sosg.ny * sosg.nx * sizeof(float);
+        if (!ws || ws_bytes < need) {
+            set_error("pact_sos_to_delays_adjoint: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
+            return PACT_EWORKSPACE;
+        }
+        static bool gattr = false;
+        if (!gattr) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+            gattr = true;
+        }
+        const long long n_rays = static_cast<long long>(N) * ring.n_elem;
+        const int K = adj_segments(n_rays, n_samples, static_cast<long long>(blocks) * kGridThreads);
+        PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "pact_sos_to_delays_adjoint: too many ray segments");
+        const int n_items = static_cast<int>(n_rays * K);
+        const int per_block = ceil_div(n_items, blocks);
+        float* partial = static_cast<float*>(ws);
+        rays_adj_grid_kernel<<<blocks, kGridThreads, glds, as_stream(stream)>>>(
+            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), K,
+            n_items, per_block, dL_dw, scale, partial);
+        if (int st = launch_status("pact_sos_to_delays_adjoint")) return st;
+        const int n_nodes = sosg.ny * sosg.nx;
+        rays_adj_reduce_kernel<<<ceil_div(n_nodes, 64), 256, 0, as_stream(stream)>>>(partial, blocks, n_nodes,
+                                                                                     accumulate, dL_dsos);
+        return launch_status("pact_sos_to_delays_adjoint");
+    }
     const size_t lds = static_cast<size_t>(kTile + 2) * (kTile + 2) * kAdjThreads * sizeof(float) +
                        2 * static_cast<size_t>(ring.n_elem) * sizeof(float) +
                        (3 * static_cast<size_t>(N) + 1) * sizeof(int);

@@ -49,6 +49,9 @@ RAGGED = synth.TINY.with_(name="ragged", ny=100, nx=90, px=0.25, n_elem=200, rad
                           fwhm=synth.configs.fwhm_for_patch(24, 0.25), sos_n=23, sos_spacing=1.0, n_samples=100,
                           mask_radius=9.0, n_blobs=12, blob_radius=9.0)
 
+# An SOS grid too large for one CU's LDS as a whole (the ray adjoint then works tile by tile).
+FINEGRID = RAGGED.with_(name="finegrid", sos_n=150, sos_spacing=0.16, n_samples=120)
+
 
 class OracleView:
     """The oracle's arguments for a workload, with every scalar rounded to float32."""

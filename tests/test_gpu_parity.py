@@ -12,7 +12,7 @@ import synth
 from oracle import das as Odas, patches as Opatch, rays as Orays, psf as Opsf, deconv as Odec, loss as Oloss
 from oracle import adam as Oadam, sos as Osos
 
-from gpu_common import (RAGGED, OracleView, TOL_DAS, TOL_DECONV, TOL_DELAYS, TOL_GRAD, TOL_LOSS, TOL_PSF,
+from gpu_common import (FINEGRID, RAGGED, OracleView, TOL_DAS, TOL_DECONV, TOL_DELAYS, TOL_GRAD, TOL_LOSS, TOL_PSF,
                         TOL_SPECTRA, announce, dev32, devc64, f32, rel_l2, random_real_patches_spectra)
 
 pytestmark = pytest.mark.gpu
@@ -76,7 +76,7 @@ def _random_sos(scan, seed):
     return np.asarray(v, dtype=np.float32)
 
 
-@pytest.mark.parametrize("scan", WORKLOADS, ids=lambda s: s.name)
+@pytest.mark.parametrize("scan", WORKLOADS + [FINEGRID], ids=lambda s: s.name)
 def test_sos_to_delays(lib, scan):
     announce(f"sos_to_delays {scan.name}")
     ov = OracleView(scan)
@@ -90,7 +90,7 @@ def test_sos_to_delays(lib, scan):
     assert err < TOL_DELAYS
 
 
-@pytest.mark.parametrize("scan", WORKLOADS, ids=lambda s: s.name)
+@pytest.mark.parametrize("scan", WORKLOADS + [FINEGRID], ids=lambda s: s.name)
 def test_sos_to_delays_adjoint(lib, scan):
     announce(f"sos_to_delays_adjoint {scan.name}")
     ov = OracleView(scan)
@@ -101,6 +101,7 @@ def test_sos_to_delays_adjoint(lib, scan):
     (want,) = Oloss.vjp(fn, (torch.tensor(v, dtype=torch.float64),), torch.tensor(gw, dtype=torch.float64))
     g = _geom(lib, scan)
     got = lib.pact.sos_to_delays_adjoint(dev32(v), g, scan.v0, dev32(ov.centres), scan.n_samples, dev32(gw))
+    again = lib.pact.sos_to_delays_adjoint(dev32(v), g, scan.v0, dev32(ov.centres), scan.n_samples, dev32(gw))
     # accumulate and device-side scale
     acc = torch.ones_like(got)
     two = torch.full((1,), 2.0, device="cuda")
@@ -110,6 +111,7 @@ def test_sos_to_delays_adjoint(lib, scan):
     err = rel_l2(got, want)
     print(f"sos_to_delays_adjoint rel L2 {err:.2e}")
     assert err < TOL_GRAD
+    assert torch.equal(got, again), "the adjoint is deterministic"
     assert rel_l2(acc - 1.0, 2.0 * want) < TOL_GRAD
 
 
