@@ -25,6 +25,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32 instructions (this build disables them): 256 CUs x 64 lanes x 2 flops
+# (FMA) x 2.4 GHz.  The published 157.3 TFLOP/s counts packed FP32.
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+COPY_REF_BYTES = 256 << 20
+MFMA_BF16_PEAK_TFLOPS = 2500.0                            # dense BF16 MFMA, MI355X
+# Algorithmic FP32 operations per ray sample (FMA = 2), from the definitions of the two ray maps:
+#   forward: position 4, cell fractions 2, bilinear contrast 6, v0 + delta 1, delta / v 2, accumulate 1
+#   adjoint: position 4, cell fractions 2, bilinear contrast 6, v0 + delta 1, v0 / v^2 and the ray weight 3,
+#            four bilinear shares 6, four accumulations 4
+FLOPS_PER_SAMPLE_FWD = 16
+FLOPS_PER_SAMPLE_ADJ = 26
 METRIC = "fwd+adjoint SOS-opt steps/s (patches×delays/s); time-to-SOS-RMSE, plain vs warm"
 
 
@@ -39,7 +50,29 @@ def parse():
     ap.add_argument("--timing-steps", type=int, default=100, help="eager steps timed per stage with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed for the CPU baseline")
+    ap.add_argument("--nf-steps", type=int, default=3, help="neural-field optimisation steps timed (0: skip)")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="run one plain 256 MiB device copy kernel first (the reference for HBM counter scaling)")
     return ap.parse_args()
+
+
+def traffic_bytes(stage):
+    """HBM bytes per launch of a stage from the committed rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE,
+    scaled by the copy reference), or None when the stage's kernel source has changed since."""
+    import hashlib
+    rec = TRAFFIC.get(stage)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2409_10876_amd", "csrc", rec["source"])
+    try:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return rec["bytes"] if digest == rec["sha256_16"] else None
+
+
+# Measured HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, scaled), keyed to the kernel source it was taken on.
+TRAFFIC = {}
 
 
 def cpu_baseline(scan, inp, n_steps):
@@ -85,6 +118,14 @@ def main():
 
     scan = synth.PAPER if args.workload == "paper" else synth.TINY
     dev = torch.device("cuda:0")
+    if args.copy_ref:
+        # elementwise copy kernel: reads and writes COPY_REF_BYTES each
+        x = torch.ones(COPY_REF_BYTES // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        print(f"[bench] copy reference: {COPY_REF_BYTES} bytes read and written by one elementwise kernel", flush=True)
     t_setup = time.perf_counter()
     inp = synth.make_inputs(scan, seed=0)
     print(f"[bench] inputs ready ({time.perf_counter() - t_setup:.1f} s): {synth.describe(scan)}", flush=True)
@@ -155,34 +196,108 @@ def main():
     breakdown = {k: 1e3 * sum(a.elapsed_time(b) for a, b in v) / reps for k, v in evs.items()}
     breakdown["das_stack_once"] = 1e3 * das_ev[0].elapsed_time(das_ev[1])
     breakdown["patch_fft_once"] = 1e3 * das_ev[1].elapsed_time(das_ev[2])
-    loss_us = breakdown["loss_and_grad"]
     N, M, Pp = scan.n_patches, scan.M, scan.P
-    y_bytes = N * M * Pp * (Pp // 2 + 1) * 8                # half spectra, complex64: read once per launch
-    other = (N * scan.n_elem * 4) * 2 + 4                   # w read, dL/dw written, loss
-    alg_bytes = y_bytes + other
-    achieved = alg_bytes / (loss_us * 1e-6) / 1e9
+    G2 = scan.sos_n * scan.sos_n
+    samples = N * scan.n_elem * scan.n_samples
+    rays_io = N * scan.n_elem * 4
+    # per stage: (kernels, bound, algorithmic work per launch, unit of the work)
+    work = {
+        "sos_to_delays": ("rays_fwd_kernel", "alu", samples * FLOPS_PER_SAMPLE_FWD, "flop"),
+        "loss_and_grad": ("loss_grad_kernel + loss_finish_kernel", "hbm",
+                          N * M * Pp * (Pp // 2 + 1) * 8 + 2 * rays_io + 4, "byte"),   # Y once, w in, dL/dw out
+        "sos_to_delays_adjoint": ("rays_adj_grid_kernel + rays_adj_reduce_kernel", "alu",
+                                  samples * FLOPS_PER_SAMPLE_ADJ, "flop"),
+        "tv_grad": ("tv_kernel", "hbm", G2 * (4 + 1 + 4 + 4) + 4, "byte"),           # sos, mask, grad r+w
+        "adam_step": ("adam_kernel", "hbm", G2 * (4 * 7 + 1) + 8, "byte"),          # sos, m, v r+w, grad, mask
+    }
+    rooflines = {}
+    for k, (kern, bound, units, unit) in work.items():
+        us = breakdown[k]
+        if unit == "byte":
+            ach, peak, u = units / (us * 1e-6) / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            ach, peak, u = units / (us * 1e-6) / 1e12, ALU_PEAK_TFLOPS, "TFLOP/s"
+        rooflines[k] = {"bound": bound, "kernel": kern, "achieved": ach, "peak": peak, "unit": u, "frac": ach / peak,
+                        "traffic": traffic_bytes(k), "alg_" + unit + "s_per_launch": units, "avg_launch_us": us}
+    dominant = max(work, key=lambda k: breakdown[k])
     print("[bench] stage times (us): " + ", ".join(f"{k} {v:.1f}" for k, v in breakdown.items()), flush=True)
 
     out = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{scan.name}: {synth.describe(scan)}",
+        "config": {"workload": synth.describe(scan),
                    "bench_step": f"one job = das_stack + patch_fft once + {args.opt_steps} optimisation steps",
                    "opt_steps_per_job": args.opt_steps, "patches": N, "delays": M, "n_elem": scan.n_elem,
                    "sos_grid": scan.sos_n, "n_samples": scan.n_samples, "graph_steps": G},
         "patches_x_delays_per_s": value * N * M,
         "ms_per_opt_step": 1e3 * elapsed / opt_steps,
-        "roofline": {"bound": "hbm", "kernel": "pact_loss_and_grad (loss_grad_kernel + loss_finish_kernel)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes_per_launch": alg_bytes, "avg_launch_us": loss_us,
-                     "timing": f"HIP events around {reps} eager launches on the launch stream"},
+        "roofline": dict(rooflines[dominant], stage=dominant,
+                         timing=f"HIP events around {reps} eager launches on the launch stream"),
+        "rooflines": rooflines,
         "stage_us": breakdown,
     }
+    if args.nf_steps > 0:
+        out["neural_field"] = nf_leg(P, sd, scan, args.nf_steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, inp, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def nf_leg(P, sd, scan, steps):
+    """The neural-field workload on the same scan: Fourier features (128 frequencies) -> 4 x 128 ReLU -> SOS at
+    every ray sample, BF16 MFMA.  Times `steps` optimisation steps and each stage (HIP events on the launch
+    stream), and reports the network kernels against the dense BF16 MFMA peak."""
+    import torch
+    import synth
+    cfg = synth.nf.NF
+    net = P.pact.NfNet(cfg.n_freq, cfg.width, cfg.amp, scan.mask_radius)
+    solver = P.NeuralFieldSolver(sd, synth.nf.frequencies(cfg), synth.nf.init_params(cfg), net, lr=scan.lr,
+                                 eps=scan.eps, n_samples=scan.n_samples)
+    solver.step()
+    torch.cuda.synchronize()
+    stages = {"nf_pack": solver.pack, "nf_sos_to_delays": solver.delays, "loss_and_grad": solver.loss_grad,
+              "nf_sos_to_delays_adjoint": solver.adjoint, "adam_step": solver.update}
+    evs = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+           for k in stages}
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(2_000_000)
+    t0.record()
+    for r in range(steps):
+        for k, fn in stages.items():
+            evs[k][r][0].record()
+            fn()
+            evs[k][r][1].record()
+    t1.record()
+    torch.cuda.synchronize()
+    us = {k: 1e3 * sum(a.elapsed_time(b) for a, b in v) / steps for k, v in evs.items()}
+    step_ms = t0.elapsed_time(t1) / steps
+    H, K = cfg.width, 2 * cfg.n_freq
+    pts = scan.n_patches * scan.n_elem * scan.n_samples
+    fwd = 2 * (H * K + 3 * H * H + H)                     # MFMA/FMA flops per point, forward
+    # algorithmic backward per point: weight gradients of all layers + input gradients of layers 2-4 + head
+    bwd = 2 * (H * K + 3 * H * H) + 2 * 3 * H * H + 2 * H
+    peak = MFMA_BF16_PEAK_TFLOPS
+    roof = {
+        "nf_sos_to_delays": {"bound": "mfma", "achieved": pts * fwd / (us["nf_sos_to_delays"] * 1e-6) / 1e12,
+                             "peak": peak, "unit": "TFLOP/s", "alg_flops_per_launch": pts * fwd,
+                             "avg_launch_us": us["nf_sos_to_delays"]},
+        "nf_sos_to_delays_adjoint": {"bound": "mfma",
+                                     "achieved": pts * bwd / (us["nf_sos_to_delays_adjoint"] * 1e-6) / 1e12,
+                                     "peak": peak, "unit": "TFLOP/s", "alg_flops_per_launch": pts * bwd,
+                                     "avg_launch_us": us["nf_sos_to_delays_adjoint"],
+                                     "note": "four passes, each recomputing the forward activations"},
+    }
+    for v in roof.values():
+        v["frac"] = v["achieved"] / v["peak"]
+    print(f"[bench] neural field: {step_ms:.2f} ms/step; " + ", ".join(f"{k} {v:.0f} us" for k, v in us.items()),
+          flush=True)
+    return {"steps_per_s": 1e3 / step_ms, "ms_per_step": step_ms, "steps_timed": steps, "stage_us": us,
+            "rooflines": roof, "dtype": "bf16 MFMA, f32 accumulate",
+            "config": f"Fourier features {cfg.n_freq} (sigma {cfg.sigma} /mm) -> {cfg.depth} x {cfg.width} ReLU -> "
+                      f"SOS, {pts} ray samples per step"}
 
 
 if __name__ == "__main__":

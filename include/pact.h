@@ -152,9 +152,12 @@ PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v
 /* Adjoint of pact_sos_to_delays: dL_dsos[a][b] = scale * sum_{i,n} dL_dw[i][n] dw[i][n]/dsos[a][b],
  * with dw/dv = dl v0 / v^2 at every sample spread by the bilinear weights.
  * scale: optional DEVICE scalar (NULL = 1).  accumulate != 0 adds to dL_dsos.
- * ws: workspace of pact_sos_to_delays_adjoint_workspace_size() bytes (this
- * build needs none: the size is 0 and ws may be NULL).  Every node's sum is
- * taken in a fixed order, so the result is deterministic. */
+ * ws: DEVICE workspace of pact_sos_to_delays_adjoint_workspace_size() bytes,
+ * which depends on the current device's CU count (one partial node grid per CU
+ * when 2 (G+2)^2 floats fit in LDS, else 0 and ws may be NULL); not shared by
+ * two calls in flight.  The per-CU sums are exact integer sums at a fixed-point
+ * scale and are combined in a fixed order, so the result is deterministic; a
+ * non-finite SOS node, or one at or below zero, makes the result NaN. */
 PACT_API size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg, int N, const pact_ring* ring);
 PACT_API int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
                                const pact_ring* ring, int n_samples, const float* dL_dw, const float* scale,
@@ -223,12 +226,51 @@ PACT_API int pact_tv_grad(const float* sos, const unsigned char* mask, const pac
 /* Adam step (Sec. 3.3) on the free nodes of sos (size n), PyTorch's update rule:
  *   t += 1; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  *   sos -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
- * fixed nodes untouched.  t: DEVICE int[2], zero-filled before the first step:
+ * fixed nodes untouched (mask NULL: every entry is free, as for the neural-field
+ * parameter vector).  t: DEVICE int[2], zero-filled before the first step:
  * t[0] counts completed steps (device-side, so that the step can be replayed
  * from a HIP graph), t[1] is an internal arrival counter that every call
  * leaves at zero.  Calls that overlap on the same t race. */
 PACT_API int pact_adam_step(float* sos, float* m, float* v, int* t, const unsigned char* mask, int n, const float* grad,
                    float lr, float b1, float b2, float eps, void* stream);
+
+/* ---- Neural-field SOS (coordinate network of Sec. 3.3) queried at every ray sample ----
+ *
+ * Network (128 frequencies, width 128, 4 hidden layers; other sizes return -4):
+ *   gamma(p) = [cos(2 pi B p), sin(2 pi B p)],  B [128][2] (x, y) in cycles per mm,
+ *   h_l = relu(W_l h_{l-1} + b_l), l = 1..4,  f = w5 . h_4 + b5,
+ *   v(p) = v0 + amp tanh(f(p)) inside the mask disc |p| <= mask_radius, v0 outside.
+ * params: DEVICE float vector of pact_nf_param_count() values, row-major blocks
+ *   W1 [128][256], b1 [128], W2 [128][128], b2, W3, b3, W4, b4, w5 [128], b5 [1].
+ * packed: DEVICE BF16 copy of the weights made by pact_nf_pack (round to nearest
+ *   even): W1, W2, W3, W4, W2^T, W3^T, W4^T, w5; pact_nf_packed_count() values.
+ * The dense layers run on MFMA with BF16 operands (weights, features, hidden
+ * activations and, in the adjoint, pre-activation gradients) and FP32
+ * accumulation; biases, the head sum, tanh and the ray sum are FP32. */
+PACT_API size_t pact_nf_param_count(int n_freq, int width);
+PACT_API size_t pact_nf_packed_count(int n_freq, int width);
+PACT_API int pact_nf_pack(const float* params, int n_freq, int width, unsigned short* packed, void* stream);
+
+/* Wavefront errors through the neural field, Eq. wf: the ray from centre c_i
+ * to element n is clipped to the mask disc (which must lie inside the ring);
+ * its chord [t_a, t_b] is sampled at n_samples midpoints,
+ *   w[i][n] = dl sum_s (1 - v0 / v(c_i + (t_a + (s + 1/2) dl) u_in)),  dl = (t_b - t_a) / n_samples,
+ * and w = 0 for rays that miss the disc.  w [N][n_elem]. */
+PACT_API int pact_nf_sos_to_delays(const float* B, const float* params, const unsigned short* packed, int n_freq,
+                          int width, float amp, float mask_radius, float v0, const float* centres, int N,
+                          const pact_ring* ring, int n_samples, float* w, void* stream);
+
+/* Adjoint: dL_dparams = scale * sum_{i,n} dL_dw[i][n] dw[i][n]/dparams (same layout as params,
+ * overwritten), by backpropagation through the network at every sample of every ray with a
+ * nonzero dL_dw.  scale: optional DEVICE scalar (NULL = 1).  ws: DEVICE workspace of
+ * pact_nf_sos_to_delays_adjoint_workspace_size() bytes (one partial gradient per CU of the current
+ * device); not shared by two calls in flight.  Partial gradients are combined in a fixed order. */
+PACT_API size_t pact_nf_sos_to_delays_adjoint_workspace_size(int n_freq, int width);
+PACT_API int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, const unsigned short* packed,
+                                  int n_freq, int width, float amp, float mask_radius, float v0,
+                                  const float* centres, int N, const pact_ring* ring, int n_samples,
+                                  const float* dL_dw, const float* scale, float* dL_dparams, void* ws,
+                                  size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

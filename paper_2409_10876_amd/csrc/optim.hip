@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kThreads) void adam_kernel(float* __restrict__ p, f
                                                         float eps) {
     const int step = t[0] + 1;
     const int idx = blockIdx.x * kThreads + threadIdx.x;
-    if (idx < n && mask[idx]) {
+    if (idx < n && (!mask || mask[idx])) {
         const float bc1 = 1.0f - powf(b1, static_cast<float>(step));
         const float bc2 = 1.0f - powf(b2, static_cast<float>(step));
         const float g = grad[idx];
@@ -100,7 +100,7 @@ extern "C" int pact_adam_step(float* sos, float* m, float* v, int* t, const unsi
                               const float* grad, float lr, float b1, float b2, float eps, void* stream) {
     using namespace pact;
     clear_error();
-    PACT_CHECK_ARG(sos && m && v && t && mask && grad, "pact_adam_step: null pointer");
+    PACT_CHECK_ARG(sos && m && v && t && grad, "pact_adam_step: null pointer");
     PACT_CHECK_ARG(n > 0, "pact_adam_step: n must be positive");
     PACT_CHECK_ARG(b1 >= 0.0f && b1 < 1.0f && b2 >= 0.0f && b2 < 1.0f, "pact_adam_step: betas must be in [0, 1)");
     PACT_CHECK_ARG(eps > 0.0f && std::isfinite(lr), "pact_adam_step: eps must be positive and lr finite");

@@ -3,13 +3,16 @@
 // Forward.  The node grid of SOS contrasts delta = v - v0 is staged in LDS with a
 // one-node ring of zeros (the fixed background), so that every midpoint sample
 // inside the clipped ray reads its four bilinear neighbours without a bounds
-// test: (G + 2)^2 floats, 80.6 KB at G = 140, two workgroups of 1024 threads per
-// CU.  The element positions are tabulated in LDS once per workgroup.  A ray
-// (patch i, element n) is owned by kLanes consecutive lanes; lane l takes
-// samples l, l + kLanes, ... (two per iteration, so that two LDS gathers are in
-// flight), and the group sums with cross-lane shuffles.  The integrand is
-// evaluated as delta / (v0 + delta) = 1 - v0 / v, which keeps the contrast
-// exact instead of cancelling 1 against v0 / v.
+// test: (G + 2)^2 floats, 80.6 KB at G = 140, so that two workgroups of 1024
+// threads share a CU.  A ray (patch i, element n) is cut into K segments of
+// consecutive samples (K a power of two chosen on the host to fill the chip),
+// one per lane, so the K lanes of a ray are adjacent in a wave and combine their
+// sums with K-wide shuffles; each lane sets up its ray once (element position
+// included) and walks its samples two at a time so that two LDS gathers are in
+// flight.  Rays are numbered patch-major: the lanes of a wave fan out from one
+// centre and their gathers often hit the same words (LDS broadcasts).  The
+// integrand is evaluated as delta / (v0 + delta) = 1 - v0 / v, which keeps the
+// contrast exact instead of cancelling 1 against v0 / v.
 //
 // Adjoint (gather by tile).  dL/dv at a node collects dL/dw * dl * v0 / v^2 *
 // (bilinear weight) from every sample whose cell touches the node.  One
@@ -37,7 +40,6 @@ int device_cu_count();
 
 namespace {
 
-constexpr int kLanes = 16;        // lanes per ray (forward)
 constexpr int kThreads = 1024;    // forward workgroup
 #ifndef PACT_ADJ_TILE
 #define PACT_ADJ_TILE 4
@@ -117,43 +119,41 @@ __device__ __forceinline__ float contrast_sample(const float* vs, float sf, floa
 
 __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restrict__ sos, float v0,
                                                             const float* __restrict__ centres, int N, int n_elem,
-                                                            float R, float phi0, int Ns, RayGeo g,
-                                                            float* __restrict__ w) {
-    extern __shared__ float lds[];
-    float* ex = lds;
-    float* ey = ex + n_elem;
-    float* vs = ey + n_elem;
+                                                            float R, float phi0, int Ns, RayGeo g, int K,
+                                                            int n_items, float* __restrict__ w) {
+    extern __shared__ float vs[];
     const int total = (g.Gy + 2) * g.W;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int a = idx / g.W - 1, b = idx % g.W - 1;
         vs[idx] = (a >= 0 && a < g.Gy && b >= 0 && b < g.Gx) ? sos[a * g.Gx + b] - v0 : 0.0f;
     }
-    load_elements(ex, ey, n_elem, R, phi0);
     __syncthreads();
-    const int lane = threadIdx.x % kLanes;
-    const int n_rays = N * n_elem;
-    const int groups = gridDim.x * (blockDim.x / kLanes);
-    for (int ray = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; ray < n_rays; ray += groups) {
+    // K divides the workgroup size and n_items = rays * K, so the K lanes of a ray enter and leave the
+    // loop together
+    for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < n_items; item += gridDim.x * blockDim.x) {
+        const int ray = item / K, k = item - ray * K;
         const int i = ray / n_elem, n = ray - i * n_elem;
+        float ex, ey;
+        element_position(n, n_elem, R, phi0, ex, ey);
         float gx0, gy0, dgx, dgy, dl;
-        ray_setup(centres[2 * i], centres[2 * i + 1], ex[n], ey[n], g, gx0, gy0, dgx, dgy, dl);
+        ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
+        const int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
         float acc0 = 0.0f, acc1 = 0.0f;
-        int s = lane;
-        for (; s + kLanes < Ns; s += 2 * kLanes) {
-            const float sf = static_cast<float>(s) + 0.5f;
+        float sf = static_cast<float>(s0) + 0.5f;
+        int s = s0;
+        for (; s + 1 < s1; s += 2, sf += 2.0f) {
             const float d0 = contrast_sample(vs, sf, gx0, gy0, dgx, dgy, g);
-            const float d1 = contrast_sample(vs, sf + static_cast<float>(kLanes), gx0, gy0, dgx, dgy, g);
+            const float d1 = contrast_sample(vs, sf + 1.0f, gx0, gy0, dgx, dgy, g);
             acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
             acc1 = fmaf(d1, __builtin_amdgcn_rcpf(v0 + d1), acc1);
         }
-        if (s < Ns) {
-            const float d0 = contrast_sample(vs, static_cast<float>(s) + 0.5f, gx0, gy0, dgx, dgy, g);
+        if (s < s1) {
+            const float d0 = contrast_sample(vs, sf, gx0, gy0, dgx, dgy, g);
             acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
         }
         float acc = acc0 + acc1;
-#pragma unroll
-        for (int off = kLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanes);
-        if (lane == 0) w[ray] = acc * dl;
+        for (int off = K >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, K);
+        if (k == 0) w[ray] = acc * dl;
     }
 }
 
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
 // F = 2^30 / bound (rounded down to a power of two) keeps every partial sum inside int32 with room for
 // the truncation of each term.  Integer sums do not depend on the order of the atomics, so the result is
 // deterministic.  The interior nodes are written, scaled back, to one partial grid per workgroup, and
-// rays_adj_reduce_kernel adds the partial grids in a fixed order.
+// the two reduce kernels add the partial grids in a fixed order.
 constexpr int kGridThreads = 1024;
 
 __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
@@ -463,22 +463,43 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     }
 }
 
-// out[node] (=|+=) sum over the partial grids, in a fixed order: 64 nodes per workgroup, four slices of the
-// partial grids per node, then the four slice sums in order.
-__global__ __launch_bounds__(256) void rays_adj_reduce_kernel(const float* __restrict__ partial, int n_part,
-                                                             int n_nodes, int accumulate, float* __restrict__ out) {
-    __shared__ float sl[4][64];
-    const int node = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int slice = threadIdx.x >> 6;
+// Sum of the per-workgroup partial grids in a fixed order, in two levels so that the 20 MB of partials
+// are read by many workgroups with many loads in flight: level 1 sums, for every node, each of kSlices
+// contiguous runs of partials (in order) into part2 [kSlices][n_nodes]; level 2 sums the slices in order
+// into out (= or +=).
+constexpr int kSlices = 16;
+
+__global__ __launch_bounds__(256) void rays_adj_reduce1_kernel(const float* __restrict__ partial, int n_part,
+                                                              int n_nodes, float* __restrict__ part2) {
+    const int node = blockIdx.x * 256 + threadIdx.x;
+    const int slice = blockIdx.y;
+    if (node >= n_nodes) return;
+    const int per = (n_part + kSlices - 1) / kSlices;
+    const int p0 = slice * per, p1 = min(p0 + per, n_part);
     float s = 0.0f;
-    if (node < n_nodes)
-        for (int p = slice; p < n_part; p += 4) s += partial[static_cast<size_t>(p) * n_nodes + node];
-    sl[slice][threadIdx.x & 63] = s;
-    __syncthreads();
-    if (threadIdx.x < 64 && node < n_nodes) {
-        const float t = (sl[0][threadIdx.x] + sl[1][threadIdx.x]) + (sl[2][threadIdx.x] + sl[3][threadIdx.x]);
-        out[node] = accumulate ? out[node] + t : t;
+    int p = p0;
+    for (; p + 8 <= p1; p += 8) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = partial[static_cast<size_t>(p + k) * n_nodes + node];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
     }
+    for (; p < p1; ++p) s += partial[static_cast<size_t>(p) * n_nodes + node];
+    part2[static_cast<size_t>(slice) * n_nodes + node] = s;
+}
+
+__global__ __launch_bounds__(256) void rays_adj_reduce2_kernel(const float* __restrict__ part2, int n_nodes,
+                                                              int accumulate, float* __restrict__ out) {
+    const int node = blockIdx.x * 256 + threadIdx.x;
+    if (node >= n_nodes) return;
+    float v[kSlices];
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) v[k] = part2[static_cast<size_t>(k) * n_nodes + node];
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) s += v[k];
+    out[node] = accumulate ? out[node] + s : s;
 }
 
 RayGeo make_geo(const pact_grid& sosg, int n_samples) {
@@ -521,8 +542,7 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
     clear_error();
     if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_sos_to_delays")) return s;
     PACT_CHECK_ARG(w, "pact_sos_to_delays: null output");
-    const size_t lds = (static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2) + 2 * static_cast<size_t>(ring.n_elem)) *
-                       sizeof(float);
+    const size_t lds = static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2) * sizeof(float);
     PACT_CHECK_SUPPORTED(lds <= kLdsBytes, "pact_sos_to_delays: SOS grid %d x %d does not fit in LDS", sosg.ny,
                          sosg.nx);
     static bool attr = false;
@@ -531,12 +551,18 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
         attr = true;
     }
+    // segments per ray: the largest power of two (at most 64, at least 8 samples a segment) whose work items
+    // fit in one round of two workgroups per CU
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
-    const int per_block = kThreads / kLanes;
-    const int blocks = static_cast<int>(std::min<long long>((n_rays + per_block - 1) / per_block,
-                                                            2LL * device_cu_count()));
+    const long long lanes = 2LL * device_cu_count() * kThreads;
+    int K = 1;
+    while (K < 64 && n_rays * (2 * K) <= lanes && n_samples / (2 * K) >= 8) K *= 2;
+    PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "pact_sos_to_delays: too many rays");
+    const int n_items = static_cast<int>(n_rays * K);
+    const int blocks = static_cast<int>(std::min<long long>(ceil_div(n_items, kThreads), 2LL * device_cu_count()));
     rays_fwd_kernel<<<blocks, kThreads, lds, as_stream(stream)>>>(sos, v0, centres, N, ring.n_elem, ring.radius,
-                                                                 ring.phi0, n_samples, make_geo(sosg, n_samples), w);
+                                                                 ring.phi0, n_samples, make_geo(sosg, n_samples), K,
+                                                                 n_items, w);
     return launch_status("pact_sos_to_delays");
 }
 
@@ -575,7 +601,7 @@ extern "C" size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sos
     (void)ring_;
     if (!sosg_ || sosg_->ny <= 0 || sosg_->nx <= 0) return 0;
     if (!pact::adj_grid_lds(*sosg_)) return 0;
-    return static_cast<size_t>(pact::device_cu_count()) * sosg_->ny * sosg_->nx * sizeof(float);
+    return static_cast<size_t>(pact::device_cu_count() + pact::kSlices) * sosg_->ny * sosg_->nx * sizeof(float);
 }
 
 extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg_, float v0, const float* centres,
@@ -594,7 +620,7 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     PACT_CHECK_ARG(dL_dw && dL_dsos, "pact_sos_to_delays_adjoint: null pointer");
     if (const size_t glds = adj_grid_lds(sosg)) {
         const int blocks = device_cu_count();
-        const size_t need = static_cast<size_t>(blocks) * sosg.ny * sosg.nx * sizeof(float);
+        const size_t need = static_cast<size_t>(blocks + kSlices) * sosg.ny * sosg.nx * sizeof(float);
         if (!ws || ws_bytes < need) {
             set_error("pact_sos_to_delays_adjoint: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
             return PACT_EWORKSPACE;
@@ -616,8 +642,12 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
             n_items, per_block, dL_dw, scale, partial);
         if (int st = launch_status("pact_sos_to_delays_adjoint")) return st;
         const int n_nodes = sosg.ny * sosg.nx;
-        rays_adj_reduce_kernel<<<ceil_div(n_nodes, 64), 256, 0, as_stream(stream)>>>(partial, blocks, n_nodes,
-                                                                                     accumulate, dL_dsos);
+        float* part2 = partial + static_cast<size_t>(blocks) * n_nodes;
+        rays_adj_reduce1_kernel<<<dim3(ceil_div(n_nodes, 256), kSlices), 256, 0, as_stream(stream)>>>(
+            partial, blocks, n_nodes, part2);
+        if (int st = launch_status("pact_sos_to_delays_adjoint")) return st;
+        rays_adj_reduce2_kernel<<<ceil_div(n_nodes, 256), 256, 0, as_stream(stream)>>>(part2, n_nodes, accumulate,
+                                                                                      dL_dsos);
         return launch_status("pact_sos_to_delays_adjoint");
     }
     const size_t lds = static_cast<size_t>(kTile + 2) * (kTile + 2) * kAdjThreads * sizeof(float) +

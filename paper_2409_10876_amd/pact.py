@@ -65,6 +65,13 @@ _SIGS = {
     "pact_loss_and_grad": (_I, [_P, _P, _P, _I, _PRING, _P, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
     "pact_tv_grad": (_I, [_P, _P, _PGRID, _F, _P, _P, _P]),
     "pact_adam_step": (_I, [_P, _P, _P, _P, _P, _I, _P, _F, _F, _F, _F, _P]),
+    "pact_nf_param_count": (_Z, [_I, _I]),
+    "pact_nf_packed_count": (_Z, [_I, _I]),
+    "pact_nf_pack": (_I, [_P, _I, _I, _P, _P]),
+    "pact_nf_sos_to_delays": (_I, [_P, _P, _P, _I, _I, _F, _F, _F, _P, _I, _PRING, _I, _P, _P]),
+    "pact_nf_sos_to_delays_adjoint_workspace_size": (_Z, [_I, _I]),
+    "pact_nf_sos_to_delays_adjoint": (_I, [_P, _P, _P, _I, _I, _F, _F, _F, _P, _I, _PRING, _I, _P, _P, _P, _P,
+                                           _Z, _P]),
 }
 
 _lib = None
@@ -117,7 +124,7 @@ def _ptr(t, dtype=None, name="tensor", numel=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-F32, C64, U8, I32 = torch.float32, torch.complex64, torch.uint8, torch.int32
+F32, C64, U8, I32, BF16 = torch.float32, torch.complex64, torch.uint8, torch.int32, torch.bfloat16
 
 
 @dataclass(frozen=True)
@@ -315,7 +322,64 @@ def tv_grad(sos, mask, g: Geometry, lam, grad, loss):
 
 
 def adam_step(sos, m, v, t, mask, grad, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """mask None: every entry is free."""
     n = sos.numel()
     _check(load().pact_adam_step(_ptr(sos, F32, "sos"), _ptr(m, F32, "m", n), _ptr(v, F32, "v", n),
                                  _ptr(t, I32, "t", 2), _ptr(mask, U8, "mask", n), n, _ptr(grad, F32, "grad", n),
                                  lr, b1, b2, eps, _stream()), "pact_adam_step")
+
+
+# ---- neural-field SOS ----
+
+@dataclass(frozen=True)
+class NfNet:
+    """Neural-field network sizes and SOS mapping (see include/pact.h)."""
+    n_freq: int = 128
+    width: int = 128
+    amp: float = 0.15
+    mask_radius: float = 26.0
+
+    @property
+    def n_params(self) -> int:
+        return int(load().pact_nf_param_count(self.n_freq, self.width))
+
+    @property
+    def n_packed(self) -> int:
+        return int(load().pact_nf_packed_count(self.n_freq, self.width))
+
+
+def nf_pack(params, net: NfNet, out=None):
+    out = torch.empty(net.n_packed, dtype=BF16, device=params.device) if out is None else out
+    _check(load().pact_nf_pack(_ptr(params, F32, "params", net.n_params), net.n_freq, net.width,
+                               _ptr(out, BF16, "packed", net.n_packed), _stream()), "pact_nf_pack")
+    return out
+
+
+def nf_sos_to_delays(B, params, packed, net: NfNet, v0, centres, g: Geometry, n_samples, out=None):
+    N = centres.shape[0]
+    out = torch.empty(N, g.n_elem, dtype=F32, device=params.device) if out is None else out
+    _check(load().pact_nf_sos_to_delays(
+        _ptr(B, F32, "B", 2 * net.n_freq), _ptr(params, F32, "params", net.n_params),
+        _ptr(packed, BF16, "packed", net.n_packed), net.n_freq, net.width, net.amp, net.mask_radius, v0,
+        _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples, _ptr(out, F32, "w", N * g.n_elem), _stream()),
+        "pact_nf_sos_to_delays")
+    return out
+
+
+def nf_sos_to_delays_adjoint_workspace_size(net: NfNet) -> int:
+    return int(load().pact_nf_sos_to_delays_adjoint_workspace_size(net.n_freq, net.width))
+
+
+def nf_sos_to_delays_adjoint(B, params, packed, net: NfNet, v0, centres, g: Geometry, n_samples, dL_dw, out=None,
+                             scale=None, ws=None):
+    N = centres.shape[0]
+    out = torch.empty(net.n_params, dtype=F32, device=params.device) if out is None else out
+    need = nf_sos_to_delays_adjoint_workspace_size(net)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=params.device) if ws is None else ws
+    _check(load().pact_nf_sos_to_delays_adjoint(
+        _ptr(B, F32, "B", 2 * net.n_freq), _ptr(params, F32, "params", net.n_params),
+        _ptr(packed, BF16, "packed", net.n_packed), net.n_freq, net.width, net.amp, net.mask_radius, v0,
+        _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples, _ptr(dL_dw, F32, "dL_dw", N * g.n_elem),
+        _ptr(scale, F32, "scale", 1), _ptr(out, F32, "dL_dparams", net.n_params), _ptr(ws, name="ws"), ws.numel(),
+        _stream()), "pact_nf_sos_to_delays_adjoint")
+    return out

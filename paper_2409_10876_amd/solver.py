@@ -1,4 +1,4 @@
-"""Optimisation of the pixel-grid SOS (Sec. 3.3) on top of the libpact calls.
+"""Optimisation of the pixel-grid and neural-field SOS (Sec. 3.3) on top of the libpact calls.
 
 * ``prepare_scan``: channel data -> DAS stack -> windowed half spectra Y, once
   per scan (Eq. DAS, Eq. conv), resident in HBM for every step.
@@ -160,3 +160,59 @@ class SosLoss(torch.autograd.Function):
         scale = gout.reshape(1).to(F32).contiguous()
         grad = pact.sos_to_delays_adjoint(sos, scan.geom, scan.v0, scan.centres, ctx.n_samples, gw, scale=scale)
         return grad, None, None, None
+
+
+class NeuralFieldSolver:
+    """Adam on the parameters of the neural-field SOS (coordinate network of Sec. 3.3); all state on the
+    device.  One step = pack the BF16 weights -> delays through the network at every ray sample -> fused
+    deconvolution loss and dL/dw -> network adjoint -> Adam."""
+
+    def __init__(self, scan: ScanData, B, params, net: "pact.NfNet", lr: float, eps: float, n_samples: int,
+                 b1=0.9, b2=0.999, adam_eps=1e-8):
+        g = scan.geom
+        dev = scan.S.device
+        self.scan, self.g, self.net = scan, g, net
+        self.lr, self.eps, self.n_samples = float(lr), float(eps), int(n_samples)
+        self.b1, self.b2, self.adam_eps = b1, b2, adam_eps
+        self.B = torch.as_tensor(B, dtype=F32).to(dev).contiguous()
+        self.params = torch.as_tensor(params, dtype=F32).to(dev).contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.packed = pact.nf_pack(self.params, net)
+        N = scan.centres.shape[0]
+        M = scan.d.numel()
+        self.w = torch.empty(N, g.n_elem, dtype=F32, device=dev)
+        self.gw = torch.empty(N, g.n_elem, dtype=F32, device=dev)
+        self.grad = torch.empty_like(self.params)
+        self.loss = torch.zeros(1, dtype=F32, device=dev)
+        self.ws_loss = torch.empty(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
+                                   dtype=torch.uint8, device=dev)
+        self.ws_nf = torch.empty(max(1, pact.nf_sos_to_delays_adjoint_workspace_size(net)), dtype=torch.uint8,
+                                 device=dev)
+
+    def pack(self):
+        pact.nf_pack(self.params, self.net, out=self.packed)
+
+    def delays(self):
+        pact.nf_sos_to_delays(self.B, self.params, self.packed, self.net, self.scan.v0, self.scan.centres, self.g,
+                              self.n_samples, out=self.w)
+
+    def loss_grad(self):
+        pact.loss_and_grad(self.scan.Y, self.w, self.scan.centres, self.g, self.scan.d, self.eps, loss=self.loss,
+                           dL_dw=self.gw, ws=self.ws_loss)
+
+    def adjoint(self):
+        pact.nf_sos_to_delays_adjoint(self.B, self.params, self.packed, self.net, self.scan.v0, self.scan.centres,
+                                      self.g, self.n_samples, self.gw, out=self.grad, ws=self.ws_nf)
+
+    def update(self):
+        pact.adam_step(self.params, self.m, self.v, self.t, None, self.grad, self.lr, self.b1, self.b2,
+                       self.adam_eps)
+
+    def step(self):
+        self.pack()
+        self.delays()
+        self.loss_grad()
+        self.adjoint()
+        self.update()
