@@ -71,8 +71,16 @@ def traffic_bytes(stage):
     return rec["bytes"] if digest == rec["sha256_16"] else None
 
 
-# Measured HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, scaled), keyed to the kernel source it was taken on.
-TRAFFIC = {}
+# Measured HBM traffic per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a plain 256 MiB
+# copy kernel read as 256 MiB; rocprofv3 counter runs recorded under profiles/), keyed to the kernel source
+# it was taken on.
+TRAFFIC = {
+    "sos_to_delays": {"source": "rays.hip", "sha256_16": "2a53c10b9bff7ebe", "bytes": 1051536},
+    "loss_and_grad": {"source": "loss.hip", "sha256_16": "20898f327f3d1ad8", "bytes": 62129258},
+    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "2a53c10b9bff7ebe", "bytes": 47641288},
+    "tv_grad": {"source": "optim.hip", "sha256_16": "682a954aac982894", "bytes": 407052},
+    "adam_step": {"source": "optim.hip", "sha256_16": "682a954aac982894", "bytes": 513418}
+}
 
 
 def cpu_baseline(scan, inp, n_steps):
@@ -205,7 +213,7 @@ def main():
         "sos_to_delays": ("rays_fwd_kernel", "alu", samples * FLOPS_PER_SAMPLE_FWD, "flop"),
         "loss_and_grad": ("loss_grad_kernel + loss_finish_kernel", "hbm",
                           N * M * Pp * (Pp // 2 + 1) * 8 + 2 * rays_io + 4, "byte"),   # Y once, w in, dL/dw out
-        "sos_to_delays_adjoint": ("rays_adj_grid_kernel + rays_adj_reduce_kernel", "alu",
+        "sos_to_delays_adjoint": ("rays_adj_grid_kernel + rays_adj_reduce1_kernel + rays_adj_reduce2_kernel", "alu",
                                   samples * FLOPS_PER_SAMPLE_ADJ, "flop"),
         "tv_grad": ("tv_kernel", "hbm", G2 * (4 + 1 + 4 + 4) + 4, "byte"),           # sos, mask, grad r+w
         "adam_step": ("adam_kernel", "hbm", G2 * (4 * 7 + 1) + 8, "byte"),          # sos, m, v r+w, grad, mask
