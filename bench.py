@@ -79,7 +79,7 @@ TRAFFIC = {
     "loss_and_grad": {"source": "loss.hip", "sha256_16": "20898f327f3d1ad8", "bytes": 62129258},
     "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "2a53c10b9bff7ebe", "bytes": 47641288},
     "tv_grad": {"source": "optim.hip", "sha256_16": "682a954aac982894", "bytes": 407052},
-    "adam_step": {"source": "optim.hip", "sha256_16": "682a954aac982894", "bytes": 513418}
+    "adam_step": {"source": "optim.hip", "sha256_16": "682a954aac982894", "bytes": 513418},
 }
 
 
@@ -181,7 +181,7 @@ def main():
     # Per-stage timing, same process and data: HIP events on the launch stream around each stage of
     # optimisation steps run eagerly (ROCm does not allow timing events inside captured graphs).
     stages = {"sos_to_delays": solver.delays, "loss_and_grad": solver.loss_grad,
-              "sos_to_delays_adjoint": solver.adjoint, "tv_grad": solver.regularise, "adam_step": solver.update}
+              "sos_to_delays_adjoint": solver.adjoint, "tv_adam_step": solver.tv_update}
     reps = args.timing_steps
     evs = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
            for k in stages}
@@ -215,8 +215,8 @@ def main():
                           N * M * Pp * (Pp // 2 + 1) * 8 + 2 * rays_io + 4, "byte"),   # Y once, w in, dL/dw out
         "sos_to_delays_adjoint": ("rays_adj_grid_kernel + rays_adj_reduce1_kernel + rays_adj_reduce2_kernel", "alu",
                                   samples * FLOPS_PER_SAMPLE_ADJ, "flop"),
-        "tv_grad": ("tv_kernel", "hbm", G2 * (4 + 1 + 4 + 4) + 4, "byte"),           # sos, mask, grad r+w
-        "adam_step": ("adam_kernel", "hbm", G2 * (4 * 7 + 1) + 8, "byte"),          # sos, m, v r+w, grad, mask
+        # sos in, sos out, m and v read and written, grad, mask
+        "tv_adam_step": ("tv_adam_kernel", "hbm", G2 * (4 * 7 + 1) + 12, "byte"),
     }
     rooflines = {}
     for k, (kern, bound, units, unit) in work.items():

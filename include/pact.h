@@ -234,6 +234,16 @@ PACT_API int pact_tv_grad(const float* sos, const unsigned char* mask, const pac
 PACT_API int pact_adam_step(float* sos, float* m, float* v, int* t, const unsigned char* mask, int n, const float* grad,
                    float lr, float b1, float b2, float eps, void* stream);
 
+/* TV and Adam in one pass (the last two steps of an optimisation step, Eq. jr and Sec. 3.3):
+ *   g = grad + lambda dTV/dsos (TV as in pact_tv_grad, at sos_in),  loss += lambda TV(sos_in),
+ *   sos_out = Adam(sos_in, g) on the free nodes (as pact_adam_step), sos_out = sos_in on fixed nodes.
+ * grad is read only.  sos_out must be a different buffer from sos_in (every node's TV reads its
+ * neighbours' old values); callers alternate two buffers.  m, v [G] and t (DEVICE int[2]) as in
+ * pact_adam_step. */
+PACT_API int pact_tv_adam_step(const float* sos_in, float* sos_out, float* m, float* v, int* t,
+                               const unsigned char* mask, const pact_grid* sosg, const float* grad, float lambda,
+                               float* loss, float lr, float b1, float b2, float eps, void* stream);
+
 /* ---- Neural-field SOS (coordinate network of Sec. 3.3) queried at every ray sample ----
  *
  * Network (128 frequencies, width 128, 4 hidden layers; other sizes return -4):

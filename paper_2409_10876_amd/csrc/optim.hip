@@ -15,6 +15,29 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ float sgn(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
 
+// TV pairs of node (a, b): its value share (the pairs it starts) and its subgradient (all four pairs).
+__device__ __forceinline__ void tv_node(const float* __restrict__ v, const unsigned char* __restrict__ mask, int idx,
+                                        int a, int b, int Gy, int Gx, float& tv, float& g) {
+    const float x = v[idx];
+    const bool m = mask[idx] != 0;
+    tv = 0.0f;
+    g = 0.0f;
+    // pair (a, b)-(a+1, b) and (a, b)-(a, b+1): counted once, by their first node
+    if (a + 1 < Gy && (m || mask[idx + Gx])) {
+        const float dv = v[idx + Gx] - x;
+        tv += fabsf(dv);
+        g -= sgn(dv);
+    }
+    if (b + 1 < Gx && (m || mask[idx + 1])) {
+        const float dv = v[idx + 1] - x;
+        tv += fabsf(dv);
+        g -= sgn(dv);
+    }
+    // the same pairs seen from their second node
+    if (a > 0 && (m || mask[idx - Gx])) g += sgn(x - v[idx - Gx]);
+    if (b > 0 && (m || mask[idx - 1])) g += sgn(x - v[idx - 1]);
+}
+
 __global__ __launch_bounds__(kThreads) void tv_kernel(const float* __restrict__ v,
                                                       const unsigned char* __restrict__ mask, int Gy, int Gx,
                                                       float lambda, float* __restrict__ grad,
@@ -24,27 +47,65 @@ __global__ __launch_bounds__(kThreads) void tv_kernel(const float* __restrict__ 
     float tv = 0.0f;
     if (idx < Gy * Gx) {
         const int a = idx / Gx, b = idx - a * Gx;
-        const float x = v[idx];
-        const bool m = mask[idx] != 0;
-        float g = 0.0f;
-        // pair (a, b)-(a+1, b) and (a, b)-(a, b+1): counted once, by their first node
-        if (a + 1 < Gy && (m || mask[idx + Gx])) {
-            const float dv = v[idx + Gx] - x;
-            tv += fabsf(dv);
-            g -= sgn(dv);
-        }
-        if (b + 1 < Gx && (m || mask[idx + 1])) {
-            const float dv = v[idx + 1] - x;
-            tv += fabsf(dv);
-            g -= sgn(dv);
-        }
-        // the same pairs seen from their second node
-        if (a > 0 && (m || mask[idx - Gx])) g += sgn(x - v[idx - Gx]);
-        if (b > 0 && (m || mask[idx - 1])) g += sgn(x - v[idx - 1]);
+        float g;
+        tv_node(v, mask, idx, a, b, Gy, Gx, tv, g);
         grad[idx] = fmaf(lambda, g, grad[idx]);
     }
     tv = block_sum(tv, red);
     if (threadIdx.x == 0 && tv != 0.0f) atomicAdd(loss, lambda * tv);
+}
+
+// One Adam update of p with gradient g at step `step` (PyTorch's rule); returns the new parameter.
+__device__ __forceinline__ float adam_node(float p, float g, float& m, float& v, int step, float lr, float b1,
+                                           float b2, float eps) {
+    const float bc1 = 1.0f - powf(b1, static_cast<float>(step));
+    const float bc2 = 1.0f - powf(b2, static_cast<float>(step));
+    m = fmaf(b1, m, (1.0f - b1) * g);
+    v = fmaf(b2, v, (1.0f - b2) * g * g);
+    return p - (lr / bc1) * m / fmaf(sqrtf(v), 1.0f / sqrtf(bc2), eps);
+}
+
+// Every workgroup has read t[0] (above its barrier); the last workgroup to arrive advances it.
+__device__ __forceinline__ void advance_step(int* t, int step) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(reinterpret_cast<unsigned*>(t + 1), 1u);
+        if (prev == gridDim.x - 1) {
+            t[0] = step;
+            t[1] = 0;
+        }
+    }
+}
+
+// TV subgradient added to the data gradient, then Adam, reading sos_in and writing sos_out (so that every
+// thread sees its neighbours' old values); fixed nodes are copied.
+__global__ __launch_bounds__(kThreads) void tv_adam_kernel(const float* __restrict__ sos_in,
+                                                           float* __restrict__ sos_out, float* __restrict__ m,
+                                                           float* __restrict__ v, int* __restrict__ t,
+                                                           const unsigned char* __restrict__ mask, int Gy, int Gx,
+                                                           const float* __restrict__ grad, float lambda,
+                                                           float* __restrict__ loss, float lr, float b1, float b2,
+                                                           float eps) {
+    __shared__ float red[kThreads / 64];
+    const int step = t[0] + 1;
+    const int idx = blockIdx.x * kThreads + threadIdx.x;
+    float tv = 0.0f;
+    if (idx < Gy * Gx) {
+        const int a = idx / Gx, b = idx - a * Gx;
+        float g_tv = 0.0f;
+        if (lambda != 0.0f) tv_node(sos_in, mask, idx, a, b, Gy, Gx, tv, g_tv);
+        float p = sos_in[idx];
+        if (mask[idx]) {
+            float mm = m[idx], vv = v[idx];
+            p = adam_node(p, fmaf(lambda, g_tv, grad[idx]), mm, vv, step, lr, b1, b2, eps);
+            m[idx] = mm;
+            v[idx] = vv;
+        }
+        sos_out[idx] = p;
+    }
+    tv = block_sum(tv, red);
+    if (threadIdx.x == 0 && tv != 0.0f) atomicAdd(loss, lambda * tv);
+    advance_step(t, step);
 }
 
 __global__ __launch_bounds__(kThreads) void adam_kernel(float* __restrict__ p, float* __restrict__ m,
@@ -55,25 +116,12 @@ __global__ __launch_bounds__(kThreads) void adam_kernel(float* __restrict__ p, f
     const int step = t[0] + 1;
     const int idx = blockIdx.x * kThreads + threadIdx.x;
     if (idx < n && (!mask || mask[idx])) {
-        const float bc1 = 1.0f - powf(b1, static_cast<float>(step));
-        const float bc2 = 1.0f - powf(b2, static_cast<float>(step));
-        const float g = grad[idx];
-        const float mm = fmaf(b1, m[idx], (1.0f - b1) * g);
-        const float vv = fmaf(b2, v[idx], (1.0f - b2) * g * g);
+        float mm = m[idx], vv = v[idx];
+        p[idx] = adam_node(p[idx], grad[idx], mm, vv, step, lr, b1, b2, eps);
         m[idx] = mm;
         v[idx] = vv;
-        p[idx] -= (lr / bc1) * mm / fmaf(sqrtf(vv), 1.0f / sqrtf(bc2), eps);
     }
-    // every thread of this workgroup has read t[0] (above the barrier); the last workgroup to arrive
-    // advances it
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(reinterpret_cast<unsigned*>(t + 1), 1u);
-        if (prev == gridDim.x - 1) {
-            t[0] = step;
-            t[1] = 0;
-        }
-    }
+    advance_step(t, step);
 }
 
 }  // namespace
@@ -107,4 +155,26 @@ extern "C" int pact_adam_step(float* sos, float* m, float* v, int* t, const unsi
     adam_kernel<<<ceil_div(n, kThreads), kThreads, 0, as_stream(stream)>>>(sos, m, v, t, mask, n, grad, lr, b1, b2,
                                                                            eps);
     return launch_status("pact_adam_step");
+}
+
+extern "C" int pact_tv_adam_step(const float* sos_in, float* sos_out, float* m, float* v, int* t,
+                                 const unsigned char* mask, const pact_grid* sosg_, const float* grad, float lambda,
+                                 float* loss, float lr, float b1, float b2, float eps, void* stream) {
+    if (!sosg_) {
+        pact::set_error("pact_tv_adam_step: null geometry pointer");
+        return PACT_EINVAL;
+    }
+    const pact_grid sosg = *sosg_;
+    using namespace pact;
+    clear_error();
+    PACT_CHECK_ARG(sos_in && sos_out && m && v && t && mask && grad && loss, "pact_tv_adam_step: null pointer");
+    PACT_CHECK_ARG(sos_in != sos_out, "pact_tv_adam_step: sos_out must not be sos_in");
+    if (int s = check_grid(sosg, "pact_tv_adam_step")) return s;
+    PACT_CHECK_ARG(std::isfinite(lambda), "pact_tv_adam_step: lambda must be finite");
+    PACT_CHECK_ARG(b1 >= 0.0f && b1 < 1.0f && b2 >= 0.0f && b2 < 1.0f, "pact_tv_adam_step: betas must be in [0, 1)");
+    PACT_CHECK_ARG(eps > 0.0f && std::isfinite(lr), "pact_tv_adam_step: eps must be positive and lr finite");
+    tv_adam_kernel<<<ceil_div(static_cast<long long>(sosg.ny) * sosg.nx, kThreads), kThreads, 0,
+                     as_stream(stream)>>>(sos_in, sos_out, m, v, t, mask, sosg.ny, sosg.nx, grad, lambda, loss, lr,
+                                          b1, b2, eps);
+    return launch_status("pact_tv_adam_step");
 }

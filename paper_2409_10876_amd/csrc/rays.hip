@@ -370,13 +370,14 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
 // into K segments of consecutive samples (K chosen on the host so that the work is about one segment
 // per lane) and work item (ray, segment) goes to one lane, which walks its samples with the same
 // position formula as the forward pass.  Rays are numbered element-major, so that the lanes of a wave
-// hold parallel rays from neighbouring patch centres and rarely hit the same node at once.  Every
-// sample adds its four bilinear shares to the accumulator with integer LDS atomics, in fixed point at
-// a power-of-two scale F chosen per workgroup from a bound on any node's sum:
+// hold parallel rays from neighbouring patch centres and rarely hit the same node at once.  A lane sums
+// the four bilinear shares of consecutive samples in the same cell in registers and adds them to the
+// accumulator with integer LDS atomics when its walk leaves the cell, in fixed point at a power-of-two
+// scale F chosen per workgroup from a bound on any node's sum:
 //   |sum| <= sum over the workgroup's rays of |dL/dw * sc| * v0 / vmin^2 * (2 sqrt(2) ds + dl),
 // since a ray meets a node's bilinear support over at most 2 sqrt(2) ds and every weight is <= 1.
 // F = 2^30 / bound (rounded down to a power of two) keeps every partial sum inside int32 with room for
-// the truncation of each term.  Integer sums do not depend on the order of the atomics, so the result is
+// the truncation of each flushed term.  Integer sums do not depend on the order of the atomics, so the result is
 // deterministic.  The interior nodes are written, scaled back, to one partial grid per workgroup, and
 // the two reduce kernels add the partial grids in a fixed order.
 constexpr int kGridThreads = 1024;
@@ -433,6 +434,8 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
         const float q0 = ok ? dL_dw[static_cast<size_t>(i) * n_elem + n] * dl * sc * F : 0.0f;
         const int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
         float sf = static_cast<float>(s0) + 0.5f;
+        int cprev = -1;
+        float a00 = 0.0f, a01 = 0.0f, a10 = 0.0f, a11 = 0.0f;
         for (int s = s0; s < s1; ++s, sf += 1.0f) {
             const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
             const float bf = floorf(gx), af = floorf(gy);
@@ -446,11 +449,29 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
             const float r = __builtin_amdgcn_rcpf(v0 + fmaf(fy, bot - top, top));
             const float qv = q0 * r * r;                     // dL/dw * dl * v0 / v^2, times F
             const float qy1 = qv * fy, qy0 = qv - qy1;
-            // truncation toward zero: at most one unit of 2^-30 of the bound per term
-            atomicAdd(acc + c, static_cast<int>(qy0 - qy0 * fx));
-            atomicAdd(acc + c + 1, static_cast<int>(qy0 * fx));
-            atomicAdd(acc + c + W, static_cast<int>(qy1 - qy1 * fx));
-            atomicAdd(acc + c + W + 1, static_cast<int>(qy1 * fx));
+            // consecutive samples in the same cell add into registers; a cell's four shares go to LDS
+            // once, when the walk leaves it (truncation toward zero: at most one unit of 2^-30 of the
+            // bound per flush)
+            if (c != cprev) {
+                if (cprev >= 0) {
+                    atomicAdd(acc + cprev, static_cast<int>(a00));
+                    atomicAdd(acc + cprev + 1, static_cast<int>(a01));
+                    atomicAdd(acc + cprev + W, static_cast<int>(a10));
+                    atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
+                }
+                cprev = c;
+                a00 = a01 = a10 = a11 = 0.0f;
+            }
+            a00 += qy0 - qy0 * fx;
+            a01 += qy0 * fx;
+            a10 += qy1 - qy1 * fx;
+            a11 += qy1 * fx;
+        }
+        if (cprev >= 0) {
+            atomicAdd(acc + cprev, static_cast<int>(a00));
+            atomicAdd(acc + cprev + 1, static_cast<int>(a01));
+            atomicAdd(acc + cprev + W, static_cast<int>(a10));
+            atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
         }
     }
     __syncthreads();

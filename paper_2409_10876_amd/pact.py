@@ -65,6 +65,7 @@ _SIGS = {
     "pact_loss_and_grad": (_I, [_P, _P, _P, _I, _PRING, _P, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
     "pact_tv_grad": (_I, [_P, _P, _PGRID, _F, _P, _P, _P]),
     "pact_adam_step": (_I, [_P, _P, _P, _P, _P, _I, _P, _F, _F, _F, _F, _P]),
+    "pact_tv_adam_step": (_I, [_P, _P, _P, _P, _P, _P, _PGRID, _P, _F, _P, _F, _F, _F, _F, _P]),
     "pact_nf_param_count": (_Z, [_I, _I]),
     "pact_nf_packed_count": (_Z, [_I, _I]),
     "pact_nf_pack": (_I, [_P, _I, _I, _P, _P]),
@@ -327,6 +328,15 @@ def adam_step(sos, m, v, t, mask, grad, lr, b1=0.9, b2=0.999, eps=1e-8):
     _check(load().pact_adam_step(_ptr(sos, F32, "sos"), _ptr(m, F32, "m", n), _ptr(v, F32, "v", n),
                                  _ptr(t, I32, "t", 2), _ptr(mask, U8, "mask", n), n, _ptr(grad, F32, "grad", n),
                                  lr, b1, b2, eps, _stream()), "pact_adam_step")
+
+
+def tv_adam_step(sos_in, sos_out, m, v, t, mask, g: Geometry, grad, lam, loss, lr, b1=0.9, b2=0.999, eps=1e-8):
+    n = g.sos_ny * g.sos_nx
+    _check(load().pact_tv_adam_step(_ptr(sos_in, F32, "sos_in", n), _ptr(sos_out, F32, "sos_out", n),
+                                    _ptr(m, F32, "m", n), _ptr(v, F32, "v", n), _ptr(t, I32, "t", 2),
+                                    _ptr(mask, U8, "mask", n), g.sosg, _ptr(grad, F32, "grad", n), lam,
+                                    _ptr(loss, F32, "loss", 1), lr, b1, b2, eps, _stream()), "pact_tv_adam_step")
+    return sos_out
 
 
 # ---- neural-field SOS ----

@@ -4,7 +4,7 @@
   per scan (Eq. DAS, Eq. conv), resident in HBM for every step.
 * ``PixelGridSolver``: one step = sos_to_delays -> loss_and_grad (fused
   Eq. TF + Eq. multi-deconv + Eq. jr and dL/dw) -> sos_to_delays_adjoint ->
-  tv_grad -> adam_step, all on torch's current stream with preallocated
+  tv_adam_step, all on torch's current stream with preallocated
   buffers, so that a run of steps can be captured once into a HIP graph and
   replayed.
 * ``SosLoss``: the data term of Eq. jr as a torch.autograd.Function whose
@@ -73,7 +73,10 @@ class PixelGridSolver:
         else:
             sos = torch.as_tensor(sos_init, dtype=F32).to(dev).clone()
         sos = torch.where(self.mask.bool(), sos, torch.full_like(sos, v0))
-        self.sos = sos.contiguous()
+        # two SOS buffers: the fused TV + Adam update reads one and writes the other
+        self._bufs = [sos.contiguous(), torch.empty_like(sos)]
+        self._cur = 0
+        self._graph_cur0 = 0
         self.m = torch.zeros_like(self.sos)
         self.v = torch.zeros_like(self.sos)
         self.t = torch.zeros(2, dtype=torch.int32, device=dev)
@@ -90,6 +93,11 @@ class PixelGridSolver:
         self.graph = None
         self.graph_steps = 0
 
+    @property
+    def sos(self) -> torch.Tensor:
+        """The current SOS node grid."""
+        return self._bufs[self._cur]
+
     # one optimisation step (a2 -> a8), enqueued on the current stream
     def delays(self):
         pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w)
@@ -103,22 +111,33 @@ class PixelGridSolver:
                                    out=self.grad, ws=self.ws_adj)
 
     def regularise(self):
+        """TV value and subgradient added to loss and grad (the separate form of the fused update)."""
         if self.lam != 0.0:
             pact.tv_grad(self.sos, self.mask, self.g, self.lam, self.grad, self.loss)
 
     def update(self):
+        """Adam in place with grad as it stands (the separate form of the fused update)."""
         pact.adam_step(self.sos, self.m, self.v, self.t, self.mask, self.grad, self.lr, self.b1, self.b2,
                        self.adam_eps)
+
+    def tv_update(self):
+        """TV and Adam in one kernel, from the current buffer into the other one."""
+        pact.tv_adam_step(self._bufs[self._cur], self._bufs[1 - self._cur], self.m, self.v, self.t, self.mask,
+                          self.g, self.grad, self.lam, self.loss, self.lr, self.b1, self.b2, self.adam_eps)
+        self._cur = 1 - self._cur
 
     def step(self):
         self.delays()
         self.loss_grad()
         self.adjoint()
-        self.regularise()
-        self.update()
+        self.tv_update()
 
     def capture(self, steps: int):
-        """Capture `steps` consecutive steps into one HIP graph (run one eager step first)."""
+        """Capture `steps` (even) consecutive steps into one HIP graph (run one eager step first).  The
+        steps alternate the two SOS buffers, so a replay starts and ends on the same one."""
+        if steps % 2:
+            raise ValueError("capture an even number of steps (the SOS buffers alternate)")
+        self._graph_cur0 = self._cur
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -133,6 +152,9 @@ class PixelGridSolver:
     def run(self, steps: int):
         """Advance `steps` steps, by graph replays where a captured graph divides the count."""
         if self.graph is not None and steps % self.graph_steps == 0:
+            if self._cur != self._graph_cur0:         # an odd number of eager steps since the capture
+                self._bufs[self._graph_cur0].copy_(self.sos)
+                self._cur = self._graph_cur0
             for _ in range(steps // self.graph_steps):
                 self.graph.replay()
         else:

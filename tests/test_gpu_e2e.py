@@ -84,13 +84,13 @@ def test_graph_replay_matches_eager(setup):
     a = P.PixelGridSolver(sd, inp.mask, eps=scan.eps, lam=scan.lam_tv, lr=scan.lr, n_samples=scan.n_samples)
     b = P.PixelGridSolver(sd, inp.mask, eps=scan.eps, lam=scan.lam_tv, lr=scan.lr, n_samples=scan.n_samples)
     a.step(); b.step()
-    a.capture(3)                       # capturing does not run the steps
+    a.capture(4)                       # capturing does not run the steps
     torch.cuda.synchronize()
     assert rel_l2(a.sos - sd.v0, b.sos - sd.v0) < 1e-5
     for _ in range(3):
-        a.run(3)
+        a.run(4)
         torch.cuda.synchronize()       # eager work and syncs between replays
-        b.run(3)
+        b.run(4)
         torch.cuda.synchronize()
         assert a.t.tolist() == b.t.tolist()
         err = rel_l2(a.sos - sd.v0, b.sos - sd.v0)

@@ -290,3 +290,39 @@ def test_tv_and_adam(lib):
     dref = ref.p - torch.tensor(v, dtype=torch.float64)
     assert rel_l2(dp, dref) < 1e-4
     assert torch.equal(p.cpu()[torch.tensor(mask == 0)], torch.tensor(v)[torch.tensor(mask == 0)])
+
+
+def test_tv_adam_fused_matches_oracle(lib):
+    """The fused TV + Adam update (reads one SOS buffer, writes the other) against the oracle: TV subgradient
+    at the old SOS added to the data gradient, then the FP64 Adam step; loss gains lambda TV."""
+    announce("tv_adam_step")
+    scan = RAGGED
+    rng = np.random.default_rng(19)
+    v = _random_sos(scan, 20)
+    mask = synth.free_node_mask(scan)
+    lam = f32(0.37)
+    g = lib.geometry_from(scan)
+    mk = dev32(mask).to(torch.uint8)
+    a, b = dev32(v), torch.empty(v.shape, dtype=torch.float32, device="cuda")
+    m = torch.zeros_like(a)
+    s2 = torch.zeros_like(a)
+    t = torch.zeros(2, dtype=torch.int32, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    ref = Oadam.Adam(torch.tensor(v, dtype=torch.float64), mask, lr=f32(1e-3))
+    tv_sum = 0.0
+    for k in range(4):
+        gk = rng.normal(size=v.shape).astype(np.float32)
+        cur = ref.p.clone()
+        (tv_g,) = Oloss.vjp(lambda vv: Oloss.tv(vv, mask), (cur,), torch.tensor(1.0, dtype=torch.float64))
+        tv_sum += lam * Oloss.tv(cur, mask).item()
+        ref.step(torch.tensor(gk, dtype=torch.float64) + lam * tv_g)
+        lib.pact.tv_adam_step(a, b, m, s2, t, mk, g, dev32(gk), lam, loss, f32(1e-3))
+        a, b = b, a
+    torch.cuda.synchronize()
+    assert t.tolist() == [4, 0]
+    dp = a.cpu().double() - torch.tensor(v, dtype=torch.float64)
+    dref = ref.p - torch.tensor(v, dtype=torch.float64)
+    print(f"tv_adam_step rel L2 {rel_l2(dp, dref):.2e}")
+    assert rel_l2(dp, dref) < 1e-4
+    assert abs(loss.item() - tv_sum) <= 1e-5 * tv_sum
+    assert torch.equal(a.cpu()[torch.tensor(mask == 0)], torch.tensor(v)[torch.tensor(mask == 0)])
