@@ -245,12 +245,111 @@ def main():
         "rooflines": rooflines,
         "stage_us": breakdown,
     }
+    out["reconstruction"] = reconstruction_quality(P, sd, solver, inp, scan, elapsed / args.steps)
+    out["delay_sweep"] = delay_sweep(P, sd, scan, solver)
+    out["paper_neural_field"] = siren_leg(P, sd, scan, inp, reps=args.timing_steps)
     if args.nf_steps > 0:
         out["neural_field"] = nf_leg(P, sd, scan, args.nf_steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, inp, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def reconstruction_quality(P, sd, solver, inp, scan, job_s):
+    """The state after the last timed job: SOS error on the free nodes and the stitched deconvolved image
+    (Supp. S1.4) against the synthetic truth (PSNR / SSIM after normalisation to the truth's range)."""
+    import torch
+    from paper_2409_10876_amd import metrics
+    g = sd.geom
+    N = sd.centres.shape[0]
+    X = torch.empty(N, g.P, g.P, dtype=torch.complex64, device=sd.S.device)
+    solver.delays()
+    P.pact.loss_and_grad(sd.Y, solver.w, sd.centres, g, sd.d, solver.eps, X=X)
+    img = P.pact.stitch(P.pact.ifft2_real(X), g)
+    # the same with no SOS correction (uniform v0): what the deconvolution alone gives
+    w0 = torch.zeros_like(solver.w)
+    P.pact.loss_and_grad(sd.Y, w0, sd.centres, g, sd.d, solver.eps, X=X)
+    img0 = P.pact.stitch(P.pact.ifft2_real(X), g)
+    das = sd.stack[len(scan.delays) // 2]                  # the d = 0 DAS image
+    torch.cuda.synchronize()
+    ref = torch.tensor(inp.ip_true)
+    mask = torch.tensor(inp.mask).bool()
+    vt = torch.tensor(inp.sos_true)
+    rmse = lambda v: 1e3 * torch.sqrt(((v.cpu().double() - vt)[mask] ** 2).mean()).item()
+    q = {}
+    for name, im in (("reconstructed", img), ("uniform_sos", img0), ("das_d0", das)):
+        a, b = metrics.normalise(im.cpu(), ref)
+        q[name] = {"psnr_db": metrics.psnr(a, b), "ssim": metrics.ssim(a, b)}
+    return {"sos_rmse_m_per_s": rmse(solver.sos), "sos_rmse_initial_m_per_s": rmse(torch.full_like(vt, scan.v0)),
+            "time_to_rmse_s": job_s, "ip_image": q,
+            "note": "plain method after one timed job; IP figures after scaling to the synthetic truth's range"}
+
+
+def delay_sweep(P, sd, scan, solver, counts=(4, 8, 11, 16), reps=20):
+    """Fused loss-and-gradient time against the number of delay channels M (the paper's M-vs-time trend),
+    on spectra of the same patch geometry."""
+    import torch
+    g = sd.geom
+    N = sd.centres.shape[0]
+    out = {}
+    for M in counts:
+        d = torch.linspace(-0.8, 0.8, M, device=sd.S.device)
+        Y = torch.randn(N, M, g.P, g.P // 2 + 1, dtype=torch.complex64, device=sd.S.device)
+        ws = torch.empty(max(1, P.pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)), dtype=torch.uint8,
+                         device=sd.S.device)
+        loss = torch.zeros(1, device=sd.S.device)
+        gw = torch.empty_like(solver.w)
+        P.pact.loss_and_grad(Y, solver.w, sd.centres, g, d, solver.eps, loss=loss, dL_dw=gw, ws=ws)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(1_000_000)
+        a.record()
+        for _ in range(reps):
+            P.pact.loss_and_grad(Y, solver.w, sd.centres, g, d, solver.eps, loss=loss, dL_dw=gw, ws=ws)
+        b.record()
+        torch.cuda.synchronize()
+        us = 1e3 * a.elapsed_time(b) / reps
+        out[str(M)] = {"loss_and_grad_us": us, "GB_per_s": N * M * g.P * (g.P // 2 + 1) * 8 / (us * 1e-6) / 1e9}
+        del Y, ws
+    return out
+
+
+def siren_leg(P, sd, scan, inp, reps=100, graph_steps=50):
+    """The paper's own neural-field form on the same scan: a 2 -> 256 -> 1 sinusoidal network (1027
+    parameters) on the SOS-grid nodes, then the pixel-grid path; Adam on the network.  Graph-replayed steps
+    per second, and each stage with HIP events."""
+    import torch
+    import synth
+    solver = P.SirenSolver(sd, inp.mask, synth.nf.siren_params(256, 30.0), 256, 30.0, scan.mask_radius, lr=5e-3,
+                           eps=scan.eps, n_samples=scan.n_samples)
+    solver.step()
+    torch.cuda.synchronize()
+    solver.capture(graph_steps)
+    solver.run(graph_steps)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    solver.run(4 * graph_steps)
+    b.record()
+    torch.cuda.synchronize()
+    us_step = 1e3 * a.elapsed_time(b) / (4 * graph_steps)
+    stages = {"siren_sos": solver.sos_grid, "sos_to_delays": solver.delays, "loss_and_grad": solver.loss_grad,
+              "adjoints (rays + network)": solver.adjoint, "adam_step": solver.update}
+    evs = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+           for k in stages}
+    torch.cuda._sleep(int(reps * 2_000_000))
+    for r in range(reps):
+        for k, fn in stages.items():
+            evs[k][r][0].record()
+            fn()
+            evs[k][r][1].record()
+    torch.cuda.synchronize()
+    us = {k: 1e3 * sum(x.elapsed_time(y) for x, y in v) / reps for k, v in evs.items()}
+    print(f"[bench] paper neural field: {us_step:.1f} us/step; " + ", ".join(f"{k} {v:.1f}" for k, v in us.items()),
+          flush=True)
+    return {"steps_per_s": 1e6 / us_step, "us_per_step": us_step, "stage_us": us,
+            "config": "sinusoidal network 2 -> 256 -> 1 (1027 parameters, omega0 30) on the 140^2 SOS nodes, "
+                      "then the pixel-grid path; no TV"}
 
 
 def nf_leg(P, sd, scan, steps):

@@ -128,6 +128,15 @@ PACT_API int pact_das_stack(const float* S, int n_t, float fs, float t0, const p
 PACT_API int pact_patch_fft(const float* stack, int M, const pact_grid* img, const pact_patches* pp, int half,
                    float* Y, void* stream);
 
+/* Gaussian-weighted stitching of patch images into the image (Supp. S1.4):
+ *   image[y][x] = sum_i x[i][y - y_i][x - x_i] / sum_i g[y - y_i][x - x_i]  where the weight sum > 1e-12,
+ *   0 elsewhere,
+ * over the patches i covering the pixel (patch i = (a, b) at y_i = a stride, x_i = b stride), g the
+ * window of pact_patch_fft.  x [N][P][P] (e.g. the deconvolved patches Re(IFFT2 X_hat)), N = npy * npx;
+ * image [img.ny][img.nx] (overwritten).  Deterministic (per-pixel gather, fixed order). */
+PACT_API int pact_stitch(const float* patches, int N, const pact_grid* img, const pact_patches* pp, float* image,
+                         void* stream);
+
 /* Real part of the normalised inverse 2-D transform of B full P x P spectra:
  * x[b] = Re(IFFT2(X[b])), X complex [B][P][P], x [B][P][P].  Used for the
  * PSF h = Re(IFFT2 H) and the deconvolved patch x_hat = Re(IFFT2 X_hat). P <= 96. */
@@ -244,6 +253,24 @@ PACT_API int pact_tv_adam_step(const float* sos_in, float* sos_out, float* m, fl
                                const unsigned char* mask, const pact_grid* sosg, const float* grad, float lambda,
                                float* loss, float lr, float b1, float b2, float eps, void* stream);
 
+/* ---- The paper's neural-field SOS: a sinusoidal network on the SOS-grid nodes (Sec. 3.3) ----
+ *
+ * v[a][b] = v0 + s (w2 . sin(omega0 (W1 (x_b, y_a) + b1)) + b2) + o on the free nodes (mask != 0),
+ * v0 on the others; (x_b, y_a) = node centre (placed like pixel centres, spacing sosg.spacing) divided
+ * by mask_radius.  params: DEVICE float vector of 4 hidden + 3 values: W1 [hidden][2] (x, y),
+ * b1 [hidden], w2 [hidden], b2, s, o (1027 values at the paper's 256 features).  hidden <= 1024.
+ * The node grid then feeds pact_sos_to_delays like the pixel grid. */
+PACT_API int pact_siren_sos(const float* params, int hidden, float omega0, const unsigned char* mask,
+                            const pact_grid* sosg, float mask_radius, float v0, float* sos, void* stream);
+
+/* Adjoint: dL_dparams (overwritten) = sum over the free nodes of dL_dsos dv/dparams.  ws: DEVICE
+ * workspace of pact_siren_sos_adjoint_workspace_size() bytes (one partial per 256 nodes); partials
+ * are combined in a fixed order. */
+PACT_API size_t pact_siren_sos_adjoint_workspace_size(const pact_grid* sosg, int hidden);
+PACT_API int pact_siren_sos_adjoint(const float* params, int hidden, float omega0, const unsigned char* mask,
+                                    const pact_grid* sosg, float mask_radius, const float* dL_dsos,
+                                    float* dL_dparams, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Neural-field SOS (coordinate network of Sec. 3.3) queried at every ray sample ----
  *
  * Network (128 frequencies, width 128, 4 hidden layers; other sizes return -4):
@@ -265,22 +292,30 @@ PACT_API int pact_nf_pack(const float* params, int n_freq, int width, unsigned s
  * to element n is clipped to the mask disc (which must lie inside the ring);
  * its chord [t_a, t_b] is sampled at n_samples midpoints,
  *   w[i][n] = dl sum_s (1 - v0 / v(c_i + (t_a + (s + 1/2) dl) u_in)),  dl = (t_b - t_a) / n_samples,
- * and w = 0 for rays that miss the disc.  w [N][n_elem]. */
+ * and w = 0 for rays that miss the disc.  w [N][n_elem].
+ * act (optional, DEVICE, pact_nf_activation_bytes() bytes, or NULL): the pass also stores every
+ * sample's hidden activations (BF16) and head output, for pact_nf_sos_to_delays_adjoint to use
+ * instead of recomputing them (about 1 KB per sample: 23 GB for 169 x 512 rays x 256 samples). */
+PACT_API size_t pact_nf_activation_bytes(int N, const pact_ring* ring, int n_samples);
 PACT_API int pact_nf_sos_to_delays(const float* B, const float* params, const unsigned short* packed, int n_freq,
                           int width, float amp, float mask_radius, float v0, const float* centres, int N,
-                          const pact_ring* ring, int n_samples, float* w, void* stream);
+                          const pact_ring* ring, int n_samples, float* w, void* act, size_t act_bytes,
+                          void* stream);
 
 /* Adjoint: dL_dparams = scale * sum_{i,n} dL_dw[i][n] dw[i][n]/dparams (same layout as params,
  * overwritten), by backpropagation through the network at every sample of every ray with a
- * nonzero dL_dw.  scale: optional DEVICE scalar (NULL = 1).  ws: DEVICE workspace of
- * pact_nf_sos_to_delays_adjoint_workspace_size() bytes (one partial gradient per CU of the current
- * device); not shared by two calls in flight.  Partial gradients are combined in a fixed order. */
+ * nonzero dL_dw.  scale: optional DEVICE scalar (NULL = 1).
+ * act: the buffer filled by pact_nf_sos_to_delays with the same inputs (two backward passes read the
+ * stored activations), or NULL (four passes recompute the forward activations; same result).
+ * ws: DEVICE workspace of pact_nf_sos_to_delays_adjoint_workspace_size() bytes (one partial gradient
+ * per CU of the current device); not shared by two calls in flight.  Partial gradients are combined
+ * in a fixed order. */
 PACT_API size_t pact_nf_sos_to_delays_adjoint_workspace_size(int n_freq, int width);
 PACT_API int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, const unsigned short* packed,
                                   int n_freq, int width, float amp, float mask_radius, float v0,
                                   const float* centres, int N, const pact_ring* ring, int n_samples,
-                                  const float* dL_dw, const float* scale, float* dL_dparams, void* ws,
-                                  size_t ws_bytes, void* stream);
+                                  const float* dL_dw, const float* scale, float* dL_dparams, const void* act,
+                                  size_t act_bytes, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

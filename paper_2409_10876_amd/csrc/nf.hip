@@ -238,9 +238,20 @@ struct NfFwdLds {
     alignas(16) __bf16 feat[kPc * kLd1];
     alignas(16) __bf16 hA[kPc * kLdH];
     alignas(16) __bf16 hB[kPc * kLdH];
+    alignas(16) __bf16 hT[2][kH * kLdT];      // feature-major staging of the activations being stored
 };
 
-__global__ __launch_bounds__(kNT) void nf_fwd_kernel(NfArgs a, float* __restrict__ w_out) {
+// Stored activations of one chunk: h1..h4 feature-major, [4][128][32] BF16 (32 KB), chunk = ray * n_chunks + ch.
+constexpr int kActChunk = 4 * kH * kPc;
+
+// Copy a feature-major LDS block [128][kLdT] (the chunk's 32 points of each feature) to its stored block.
+__device__ __forceinline__ void nf_store_layer(const __bf16* hT, __bf16* dst) {
+    const int feature = threadIdx.x >> 2, part = threadIdx.x & 3;   // 512 threads x 16 bytes = 8 KB
+    *reinterpret_cast<bf16x8*>(dst + feature * kPc + 8 * part) = ld8(hT + feature * kLdT + 8 * part);
+}
+
+__global__ __launch_bounds__(kNT) void nf_fwd_kernel(NfArgs a, float* __restrict__ w_out, __bf16* __restrict__ act,
+                                                     float* __restrict__ f_out) {
     __shared__ NfFwdLds sm;
     load_tables(a, sm.tab);
     bf16x8 w1[8], w2[4], w3[4], w4[4];
@@ -260,26 +271,36 @@ __global__ __launch_bounds__(kNT) void nf_fwd_kernel(NfArgs a, float* __restrict
         float sum = 0.0f;
         for (int ch = 0; ch < n_chunks; ++ch) {
             const int s0 = ch * kPc;
+            const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
+            __bf16* dst = act ? act + chunk * kActChunk : nullptr;
             nf_features(a, r, s0, sm.tab.B, sm.feat, nullptr);
             __syncthreads();
             f32x4 acc[2];
             float h[2][4];
             nf_layer<8>(w1, sm.feat, kLd1, acc);
-            nf_activate(acc, sm.tab.bias[0], sm.hA, nullptr, h);
+            nf_activate(acc, sm.tab.bias[0], sm.hA, dst ? sm.hT[0] : nullptr, h);
             __syncthreads();
+            if (dst) nf_store_layer(sm.hT[0], dst);
             nf_layer<4>(w2, sm.hA, kLdH, acc);
-            nf_activate(acc, sm.tab.bias[1], sm.hB, nullptr, h);
+            nf_activate(acc, sm.tab.bias[1], sm.hB, dst ? sm.hT[1] : nullptr, h);
             __syncthreads();
+            if (dst) nf_store_layer(sm.hT[1], dst + kH * kPc);
             nf_layer<4>(w3, sm.hB, kLdH, acc);
-            nf_activate(acc, sm.tab.bias[2], sm.hA, nullptr, h);
+            nf_activate(acc, sm.tab.bias[2], sm.hA, dst ? sm.hT[0] : nullptr, h);
             __syncthreads();
+            if (dst) nf_store_layer(sm.hT[0], dst + 2 * kH * kPc);
             nf_layer<4>(w4, sm.hA, kLdH, acc);
-            nf_activate(acc, sm.tab.bias[3], sm.hB, nullptr, h);
+            nf_activate(acc, sm.tab.bias[3], sm.hB, dst ? sm.hT[1] : nullptr, h);
             nf_head_partial(h, sm.tab.w5, sm.headp);
             __syncthreads();
-            if (threadIdx.x < kPc && s0 + static_cast<int>(threadIdx.x) < a.Ns) {
-                const float th = tanhf(nf_head_sum(sm.headp, threadIdx.x, sm.tab.b5));
-                sum += a.amp * th / (a.v0 + a.amp * th);          // 1 - v0 / v
+            if (dst) nf_store_layer(sm.hT[1], dst + 3 * kH * kPc);
+            if (threadIdx.x < kPc) {
+                const float f = nf_head_sum(sm.headp, threadIdx.x, sm.tab.b5);
+                if (f_out) f_out[chunk * kPc + threadIdx.x] = f;
+                if (s0 + static_cast<int>(threadIdx.x) < a.Ns) {
+                    const float th = tanhf(f);
+                    sum += a.amp * th / (a.v0 + a.amp * th);      // 1 - v0 / v
+                }
             }
         }
         if (threadIdx.x < 64) {
@@ -481,6 +502,175 @@ __global__ __launch_bounds__(kNT) void nf_bwd_kernel(NfArgs a, const float* __re
     }
 }
 
+// Backward pass from stored activations (written by the forward pass): no forward recompute, so the
+// forward weights need no registers and two passes suffice (layers 2-4 and the head, then layer 1).
+template <int LO>
+struct NfBwdStoredLds {
+    NfTables tab;
+    float df[kPc];
+    alignas(16) __bf16 feat[LO == 1 ? kPc * kLd1 : 8];
+    alignas(16) __bf16 featT[LO == 1 ? kK1 * kLdT : 8];
+    alignas(16) __bf16 hT[4][kH * kLdT];      // h1..h4 of the chunk, feature-major
+    alignas(16) __bf16 dP[2][kPc * kLdH];     // delta, point-major (dgrad operand)
+    alignas(16) __bf16 dT[2][kH * kLdT];      // delta, feature-major (weight-gradient operand)
+};
+
+template <int L, int LO, int HI, int NG>
+__device__ __forceinline__ void nf_level_stored(NfBwdStoredLds<LO>& sm, const bf16x8 (&tw)[4], f32x4 (&gl)[NG],
+                                                float (&gb)[4][4], int cur) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
+    const int row0 = 16 * wv + 4 * q;
+    if (L >= LO && L <= HI) {
+        const bf16x8 da = ld8(sm.dT[cur] + (16 * wv + r16) * kLdT + 8 * q);
+        const __bf16* hT = L == 1 ? sm.featT : sm.hT[L >= 2 ? L - 2 : 0];
+#pragma unroll
+        for (int kt = 0; kt < NG; ++kt) gl[kt] = mfma(da, ld8(hT + (16 * kt + r16) * kLdT + 8 * q), gl[kt]);
+    }
+    if (L > LO) {
+        f32x4 d2[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            d2[0] = mfma(tw[ks], ld8(sm.dP[cur] + r16 * kLdH + 32 * ks + 8 * q), d2[0]);
+            d2[1] = mfma(tw[ks], ld8(sm.dP[cur] + (16 + r16) * kLdH + 32 * ks + 8 * q), d2[1]);
+        }
+        const int nxt = cur ^ 1;
+        const __bf16* hprev = sm.hT[L >= 2 ? L - 2 : 0];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int p = 16 * nt + r16;
+            bf16x4 dv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float hv = static_cast<float>(hprev[(row0 + i) * kLdT + p]);
+                dv[i] = static_cast<__bf16>(hv > 0.0f ? d2[nt][i] : 0.0f);
+                gb[L >= 2 ? L - 2 : 0][i] += static_cast<float>(dv[i]);
+                sm.dT[nxt][(row0 + i) * kLdT + p] = dv[i];
+            }
+            *reinterpret_cast<bf16x4*>(sm.dP[nxt] + p * kLdH + row0) = dv;
+        }
+    }
+    __syncthreads();
+}
+
+template <int LO, int HI>
+__global__ __launch_bounds__(kNT) void nf_bwd_stored_kernel(NfArgs a, const __bf16* __restrict__ act,
+                                                            const float* __restrict__ f_in,
+                                                            const float* __restrict__ dL_dw,
+                                                            const float* __restrict__ scale,
+                                                            float* __restrict__ partial) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char nf_dyn[];
+    NfBwdStoredLds<LO>& sm = *reinterpret_cast<NfBwdStoredLds<LO>*>(nf_dyn);
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
+    load_tables(a, sm.tab);
+    bf16x8 t2[4], t3[4], t4[4];
+    load_rows<4>(a.packed, kOffT4, kH, t4);
+    load_rows<4>(a.packed, kOffT3, kH, t3);
+    if (LO < 2) load_rows<4>(a.packed, kOffT2, kH, t2);
+    f32x4 g1[LO == 1 ? 16 : 1], g2[HI >= 2 && LO <= 2 ? 8 : 1], g3[HI >= 3 && LO <= 3 ? 8 : 1],
+        g4[HI == 4 ? 8 : 1];
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (auto& x : g1) x = zero;
+    for (auto& x : g2) x = zero;
+    for (auto& x : g3) x = zero;
+    for (auto& x : g4) x = zero;
+    float gb[4][4] = {};
+    float gw5[4] = {}, gb5 = 0.0f;
+    const float sc = scale ? *scale : 1.0f;
+    __syncthreads();
+
+    const int n_rays = a.N * a.n_elem;
+    const int n_chunks = (a.Ns + kPc - 1) / kPc;
+    const int row0 = 16 * wv + 4 * q;
+    for (int ray = blockIdx.x; ray < n_rays; ray += gridDim.x) {
+        const float g = dL_dw[ray] * sc;
+        if (g == 0.0f) continue;
+        const NfRay r = nf_ray(a, ray);
+        if (r.dl == 0.0f) continue;
+        for (int ch = 0; ch < n_chunks; ++ch) {
+            const int s0 = ch * kPc;
+            const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
+            const __bf16* src = act + chunk * kActChunk;
+            {
+                const int feature = threadIdx.x >> 2, part = threadIdx.x & 3;
+#pragma unroll
+                for (int L = 0; L < 4; ++L)
+                    *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) =
+                        ld8(src + (L * kH + feature) * kPc + 8 * part);
+            }
+            if (threadIdx.x < kPc) {
+                float d = 0.0f;
+                if (s0 + static_cast<int>(threadIdx.x) < a.Ns) {
+                    const float th = tanhf(f_in[chunk * kPc + threadIdx.x]);
+                    const float v = a.v0 + a.amp * th;
+                    d = g * r.dl * a.v0 * a.amp * (1.0f - th * th) / (v * v);
+                }
+                sm.df[threadIdx.x] = d;
+            }
+            if (LO == 1) nf_features(a, r, s0, sm.tab.B, sm.feat, sm.featT);
+            __syncthreads();
+            // delta_4 = df w5 [h4 > 0]
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int p = 16 * nt + r16;
+                const float dfp = sm.df[p];
+                bf16x4 dv;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float h4 = static_cast<float>(sm.hT[3][(row0 + i) * kLdT + p]);
+                    if (HI == 4) gw5[i] = fmaf(dfp, h4, gw5[i]);
+                    dv[i] = static_cast<__bf16>(h4 > 0.0f ? dfp * sm.tab.w5[row0 + i] : 0.0f);
+                    gb[3][i] += static_cast<float>(dv[i]);
+                    sm.dT[0][(row0 + i) * kLdT + p] = dv[i];
+                }
+                *reinterpret_cast<bf16x4*>(sm.dP[0] + p * kLdH + row0) = dv;
+            }
+            if (HI == 4 && threadIdx.x < kPc) gb5 += sm.df[threadIdx.x];
+            __syncthreads();
+            nf_level_stored<4, LO, HI, HI == 4 ? 8 : 1>(sm, t4, g4, gb, 0);
+            if (LO <= 3) nf_level_stored<3, LO, HI, (LO <= 3 && HI >= 3) ? 8 : 1>(sm, t3, g3, gb, 1);
+            if (LO <= 2) nf_level_stored<2, LO, HI, (LO <= 2 && HI >= 2) ? 8 : 1>(sm, t2, g2, gb, 0);
+            if (LO <= 1) nf_level_stored<1, LO, HI, LO == 1 ? 16 : 1>(sm, t2, g1, gb, 1);
+        }
+    }
+
+    float* out = partial + static_cast<size_t>(blockIdx.x) * kNParams;
+    auto put_w = [&](int L, const f32x4* gl, int tiles, int ld) {
+        for (int kt = 0; kt < tiles; ++kt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[param_w(L) + (row0 + i) * ld + 16 * kt + r16] = gl[kt][i];
+    };
+    if (LO == 1) put_w(1, g1, 16, kK1);
+    if (LO <= 2 && HI >= 2) put_w(2, g2, 8, kH);
+    if (LO <= 3 && HI >= 3) put_w(3, g3, 8, kH);
+    if (HI == 4) put_w(4, g4, 8, kH);
+#pragma unroll
+    for (int L = 1; L <= 4; ++L) {
+        if (L < LO || L > HI) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float s = gb[L - 1][i];
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+            if (r16 == 0) out[param_b(L) + row0 + i] = s;
+        }
+    }
+    if (HI == 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float s = gw5[i];
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+            if (r16 == 0) out[kPw5 + row0 + i] = s;
+        }
+        float s = threadIdx.x < 64 ? gb5 : 0.0f;
+        if (threadIdx.x < 64) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+            if (threadIdx.x == 0) out[kPb5] = s;
+        }
+    }
+}
+
 // dL/dparams[j] = sum over workgroups of partial[b][j], in order.
 __global__ __launch_bounds__(256) void nf_reduce_kernel(const float* __restrict__ partial, int n_part,
                                                        float* __restrict__ out) {
@@ -564,8 +754,32 @@ int launch_bwd(const NfArgs& a, const float* dL_dw, const float* scale, float* p
     return launch_status("pact_nf_sos_to_delays_adjoint");
 }
 
+template <int LO, int HI>
+int launch_bwd_stored(const NfArgs& a, const __bf16* act, const float* f_in, const float* dL_dw, const float* scale,
+                      float* partial, int blocks, hipStream_t st) {
+    static bool attr = false;
+    const size_t lds = sizeof(NfBwdStoredLds<LO>);
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(nf_bwd_stored_kernel<LO, HI>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        attr = true;
+    }
+    nf_bwd_stored_kernel<LO, HI><<<blocks, kNT, lds, st>>>(a, act, f_in, dL_dw, scale, partial);
+    return launch_status("pact_nf_sos_to_delays_adjoint");
+}
+
+size_t nf_activation_bytes(long long n_rays, int n_samples) {
+    const long long chunks = n_rays * ((n_samples + kPc - 1) / kPc);
+    return static_cast<size_t>(chunks) * (kActChunk * sizeof(__bf16) + kPc * sizeof(float));
+}
+
 }  // namespace
 }  // namespace pact
+
+extern "C" size_t pact_nf_activation_bytes(int N, const pact_ring* ring, int n_samples) {
+    if (!ring || N <= 0 || ring->n_elem <= 0 || n_samples <= 0) return 0;
+    return pact::nf_activation_bytes(static_cast<long long>(N) * ring->n_elem, n_samples);
+}
 
 extern "C" size_t pact_nf_param_count(int n_freq, int width) {
     if (n_freq <= 0 || width <= 0) return 0;
@@ -589,7 +803,8 @@ extern "C" int pact_nf_pack(const float* params, int n_freq, int width, unsigned
 
 extern "C" int pact_nf_sos_to_delays(const float* B, const float* params, const unsigned short* packed, int n_freq,
                                      int width, float amp, float mask_radius, float v0, const float* centres, int N,
-                                     const pact_ring* ring, int n_samples, float* w, void* stream) {
+                                     const pact_ring* ring, int n_samples, float* w, void* act, size_t act_bytes,
+                                     void* stream) {
     using namespace pact;
     clear_error();
     if (int s = check_nf(B, params, packed, n_freq, width, amp, mask_radius, v0, centres, N, ring, n_samples,
@@ -598,8 +813,20 @@ extern "C" int pact_nf_sos_to_delays(const float* B, const float* params, const 
     PACT_CHECK_ARG(w, "pact_nf_sos_to_delays: null output");
     const NfArgs a = nf_args(B, params, packed, amp, mask_radius, v0, centres, N, *ring, n_samples);
     const long long n_rays = static_cast<long long>(N) * ring->n_elem;
+    __bf16* act_h = nullptr;
+    float* act_f = nullptr;
+    if (act) {
+        const size_t need = nf_activation_bytes(n_rays, n_samples);
+        if (act_bytes < need) {
+            set_error("pact_nf_sos_to_delays: activation buffer of %zu bytes needed, %zu given", need, act_bytes);
+            return PACT_EWORKSPACE;
+        }
+        const size_t chunks = static_cast<size_t>(n_rays) * ((n_samples + kPc - 1) / kPc);
+        act_h = static_cast<__bf16*>(act);
+        act_f = reinterpret_cast<float*>(act_h + chunks * kActChunk);
+    }
     const int blocks = static_cast<int>(std::min<long long>(n_rays, 2LL * device_cu_count()));
-    nf_fwd_kernel<<<blocks, kNT, 0, as_stream(stream)>>>(a, w);
+    nf_fwd_kernel<<<blocks, kNT, 0, as_stream(stream)>>>(a, w, act_h, act_f);
     return launch_status("pact_nf_sos_to_delays");
 }
 
@@ -611,8 +838,9 @@ extern "C" size_t pact_nf_sos_to_delays_adjoint_workspace_size(int n_freq, int w
 extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, const unsigned short* packed,
                                              int n_freq, int width, float amp, float mask_radius, float v0,
                                              const float* centres, int N, const pact_ring* ring, int n_samples,
-                                             const float* dL_dw, const float* scale, float* dL_dparams, void* ws,
-                                             size_t ws_bytes, void* stream) {
+                                             const float* dL_dw, const float* scale, float* dL_dparams,
+                                             const void* act, size_t act_bytes, void* ws, size_t ws_bytes,
+                                             void* stream) {
     using namespace pact;
     clear_error();
     if (int s = check_nf(B, params, packed, n_freq, width, amp, mask_radius, v0, centres, N, ring, n_samples,
@@ -628,6 +856,23 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
     const NfArgs a = nf_args(B, params, packed, amp, mask_radius, v0, centres, N, *ring, n_samples);
     float* partial = static_cast<float*>(ws);
     hipStream_t st = as_stream(stream);
+    if (act) {
+        const long long n_rays = static_cast<long long>(N) * ring->n_elem;
+        const size_t need = nf_activation_bytes(n_rays, n_samples);
+        if (act_bytes < need) {
+            set_error("pact_nf_sos_to_delays_adjoint: activation buffer of %zu bytes needed, %zu given", need,
+                      act_bytes);
+            return PACT_EWORKSPACE;
+        }
+        const size_t chunks = static_cast<size_t>(n_rays) * ((n_samples + kPc - 1) / kPc);
+        const __bf16* act_h = static_cast<const __bf16*>(act);
+        const float* act_f = reinterpret_cast<const float*>(act_h + chunks * kActChunk);
+        // two passes from the stored activations: layers 2-4 and the head, then layer 1
+        if (int s = launch_bwd_stored<2, 4>(a, act_h, act_f, dL_dw, scale, partial, blocks, st)) return s;
+        if (int s = launch_bwd_stored<1, 1>(a, act_h, act_f, dL_dw, scale, partial, blocks, st)) return s;
+        nf_reduce_kernel<<<ceil_div(kNParams, 256), 256, 0, st>>>(partial, blocks, dL_dparams);
+        return launch_status("pact_nf_sos_to_delays_adjoint");
+    }
     // four passes, each recomputing the forward activations: layers 3-4 (and the head), layer 2, and the
     // two column halves of layer 1, so that each pass's gradient accumulators fit in registers
     if (int s = launch_bwd<3, 4, 0, 0>(a, dL_dw, scale, partial, blocks, st)) return s;

@@ -65,14 +65,19 @@ _SIGS = {
     "pact_loss_and_grad": (_I, [_P, _P, _P, _I, _PRING, _P, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
     "pact_tv_grad": (_I, [_P, _P, _PGRID, _F, _P, _P, _P]),
     "pact_adam_step": (_I, [_P, _P, _P, _P, _P, _I, _P, _F, _F, _F, _F, _P]),
+    "pact_stitch": (_I, [_P, _I, _PGRID, _PPATCH, _P, _P]),
+    "pact_siren_sos": (_I, [_P, _I, _F, _P, _PGRID, _F, _F, _P, _P]),
+    "pact_siren_sos_adjoint_workspace_size": (_Z, [_PGRID, _I]),
+    "pact_siren_sos_adjoint": (_I, [_P, _I, _F, _P, _PGRID, _F, _P, _P, _P, _Z, _P]),
     "pact_tv_adam_step": (_I, [_P, _P, _P, _P, _P, _P, _PGRID, _P, _F, _P, _F, _F, _F, _F, _P]),
     "pact_nf_param_count": (_Z, [_I, _I]),
     "pact_nf_packed_count": (_Z, [_I, _I]),
     "pact_nf_pack": (_I, [_P, _I, _I, _P, _P]),
-    "pact_nf_sos_to_delays": (_I, [_P, _P, _P, _I, _I, _F, _F, _F, _P, _I, _PRING, _I, _P, _P]),
+    "pact_nf_activation_bytes": (_Z, [_I, _PRING, _I]),
+    "pact_nf_sos_to_delays": (_I, [_P, _P, _P, _I, _I, _F, _F, _F, _P, _I, _PRING, _I, _P, _P, _Z, _P]),
     "pact_nf_sos_to_delays_adjoint_workspace_size": (_Z, [_I, _I]),
     "pact_nf_sos_to_delays_adjoint": (_I, [_P, _P, _P, _I, _I, _F, _F, _F, _P, _I, _PRING, _I, _P, _P, _P, _P,
-                                           _Z, _P]),
+                                           _Z, _P, _Z, _P]),
 }
 
 _lib = None
@@ -330,6 +335,37 @@ def adam_step(sos, m, v, t, mask, grad, lr, b1=0.9, b2=0.999, eps=1e-8):
                                  lr, b1, b2, eps, _stream()), "pact_adam_step")
 
 
+def stitch(patches, g: Geometry, out=None):
+    """Gaussian-weighted stitching of patch images [N][P][P] into the image [ny][nx]."""
+    N = patches.shape[0]
+    out = torch.empty(g.ny, g.nx, dtype=F32, device=patches.device) if out is None else out
+    _check(load().pact_stitch(_ptr(patches, F32, "patches", N * g.P * g.P), N, g.img, g.patches,
+                              _ptr(out, F32, "image", g.ny * g.nx), _stream()), "pact_stitch")
+    return out
+
+
+def siren_sos(params, hidden, omega0, mask, g: Geometry, mask_radius, v0, out=None):
+    """The paper's sinusoidal network on the SOS-grid nodes -> SOS node grid [sos_ny][sos_nx]."""
+    n = g.sos_ny * g.sos_nx
+    out = torch.empty(g.sos_ny, g.sos_nx, dtype=F32, device=params.device) if out is None else out
+    _check(load().pact_siren_sos(_ptr(params, F32, "params", 4 * hidden + 3), hidden, omega0,
+                                 _ptr(mask, U8, "mask", n), g.sosg, mask_radius, v0, _ptr(out, F32, "sos", n),
+                                 _stream()), "pact_siren_sos")
+    return out
+
+
+def siren_sos_adjoint(params, hidden, omega0, mask, g: Geometry, mask_radius, dL_dsos, out=None, ws=None):
+    n = g.sos_ny * g.sos_nx
+    out = torch.empty(4 * hidden + 3, dtype=F32, device=params.device) if out is None else out
+    need = int(load().pact_siren_sos_adjoint_workspace_size(g.sosg, hidden))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=params.device) if ws is None else ws
+    _check(load().pact_siren_sos_adjoint(_ptr(params, F32, "params", 4 * hidden + 3), hidden, omega0,
+                                         _ptr(mask, U8, "mask", n), g.sosg, mask_radius,
+                                         _ptr(dL_dsos, F32, "dL_dsos", n), _ptr(out, F32, "dL_dparams", 4 * hidden + 3),
+                                         _ptr(ws, name="ws"), ws.numel(), _stream()), "pact_siren_sos_adjoint")
+    return out
+
+
 def tv_adam_step(sos_in, sos_out, m, v, t, mask, g: Geometry, grad, lam, loss, lr, b1=0.9, b2=0.999, eps=1e-8):
     n = g.sos_ny * g.sos_nx
     _check(load().pact_tv_adam_step(_ptr(sos_in, F32, "sos_in", n), _ptr(sos_out, F32, "sos_out", n),
@@ -365,14 +401,19 @@ def nf_pack(params, net: NfNet, out=None):
     return out
 
 
-def nf_sos_to_delays(B, params, packed, net: NfNet, v0, centres, g: Geometry, n_samples, out=None):
+def nf_activation_bytes(N: int, g: Geometry, n_samples: int) -> int:
+    return int(load().pact_nf_activation_bytes(N, g.ring, n_samples))
+
+
+def nf_sos_to_delays(B, params, packed, net: NfNet, v0, centres, g: Geometry, n_samples, out=None, act=None):
+    """act: optional uint8 device buffer of nf_activation_bytes() bytes that receives the activations."""
     N = centres.shape[0]
     out = torch.empty(N, g.n_elem, dtype=F32, device=params.device) if out is None else out
     _check(load().pact_nf_sos_to_delays(
         _ptr(B, F32, "B", 2 * net.n_freq), _ptr(params, F32, "params", net.n_params),
         _ptr(packed, BF16, "packed", net.n_packed), net.n_freq, net.width, net.amp, net.mask_radius, v0,
-        _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples, _ptr(out, F32, "w", N * g.n_elem), _stream()),
-        "pact_nf_sos_to_delays")
+        _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples, _ptr(out, F32, "w", N * g.n_elem),
+        _ptr(act, name="act"), act.numel() if act is not None else 0, _stream()), "pact_nf_sos_to_delays")
     return out
 
 
@@ -381,7 +422,7 @@ def nf_sos_to_delays_adjoint_workspace_size(net: NfNet) -> int:
 
 
 def nf_sos_to_delays_adjoint(B, params, packed, net: NfNet, v0, centres, g: Geometry, n_samples, dL_dw, out=None,
-                             scale=None, ws=None):
+                             scale=None, ws=None, act=None):
     N = centres.shape[0]
     out = torch.empty(net.n_params, dtype=F32, device=params.device) if out is None else out
     need = nf_sos_to_delays_adjoint_workspace_size(net)
@@ -390,6 +431,7 @@ def nf_sos_to_delays_adjoint(B, params, packed, net: NfNet, v0, centres, g: Geom
         _ptr(B, F32, "B", 2 * net.n_freq), _ptr(params, F32, "params", net.n_params),
         _ptr(packed, BF16, "packed", net.n_packed), net.n_freq, net.width, net.amp, net.mask_radius, v0,
         _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples, _ptr(dL_dw, F32, "dL_dw", N * g.n_elem),
-        _ptr(scale, F32, "scale", 1), _ptr(out, F32, "dL_dparams", net.n_params), _ptr(ws, name="ws"), ws.numel(),
-        _stream()), "pact_nf_sos_to_delays_adjoint")
+        _ptr(scale, F32, "scale", 1), _ptr(out, F32, "dL_dparams", net.n_params), _ptr(act, name="act"),
+        act.numel() if act is not None else 0, _ptr(ws, name="ws"), ws.numel(), _stream()),
+        "pact_nf_sos_to_delays_adjoint")
     return out

@@ -190,7 +190,7 @@ class NeuralFieldSolver:
     deconvolution loss and dL/dw -> network adjoint -> Adam."""
 
     def __init__(self, scan: ScanData, B, params, net: "pact.NfNet", lr: float, eps: float, n_samples: int,
-                 b1=0.9, b2=0.999, adam_eps=1e-8):
+                 b1=0.9, b2=0.999, adam_eps=1e-8, store_activations: bool = True):
         g = scan.geom
         dev = scan.S.device
         self.scan, self.g, self.net = scan, g, net
@@ -212,13 +212,16 @@ class NeuralFieldSolver:
                                    dtype=torch.uint8, device=dev)
         self.ws_nf = torch.empty(max(1, pact.nf_sos_to_delays_adjoint_workspace_size(net)), dtype=torch.uint8,
                                  device=dev)
+        # every sample's activations from the forward pass, read back by the adjoint (else it recomputes them)
+        self.act = (torch.empty(pact.nf_activation_bytes(N, g, self.n_samples), dtype=torch.uint8, device=dev)
+                    if store_activations else None)
 
     def pack(self):
         pact.nf_pack(self.params, self.net, out=self.packed)
 
     def delays(self):
         pact.nf_sos_to_delays(self.B, self.params, self.packed, self.net, self.scan.v0, self.scan.centres, self.g,
-                              self.n_samples, out=self.w)
+                              self.n_samples, out=self.w, act=self.act)
 
     def loss_grad(self):
         pact.loss_and_grad(self.scan.Y, self.w, self.scan.centres, self.g, self.scan.d, self.eps, loss=self.loss,
@@ -226,7 +229,7 @@ class NeuralFieldSolver:
 
     def adjoint(self):
         pact.nf_sos_to_delays_adjoint(self.B, self.params, self.packed, self.net, self.scan.v0, self.scan.centres,
-                                      self.g, self.n_samples, self.gw, out=self.grad, ws=self.ws_nf)
+                                      self.g, self.n_samples, self.gw, out=self.grad, ws=self.ws_nf, act=self.act)
 
     def update(self):
         pact.adam_step(self.params, self.m, self.v, self.t, None, self.grad, self.lr, self.b1, self.b2,
@@ -238,3 +241,88 @@ class NeuralFieldSolver:
         self.loss_grad()
         self.adjoint()
         self.update()
+
+
+class SirenSolver:
+    """The paper's neural-field form (Sec. 3.3): Adam on the 1027 parameters of a sinusoidal network on the
+    SOS-grid nodes; each step evaluates the network on the nodes, then runs the pixel-grid path (rays, fused
+    loss, ray adjoint) and the network's adjoint.  No TV (the paper sets lambda = 0 for the neural field)."""
+
+    def __init__(self, scan: ScanData, mask, params, hidden: int, omega0: float, mask_radius: float, lr: float,
+                 eps: float, n_samples: int, b1=0.9, b2=0.999, adam_eps=1e-8):
+        g = scan.geom
+        dev = scan.S.device
+        self.scan, self.g = scan, g
+        self.hidden, self.omega0, self.rho = int(hidden), float(omega0), float(mask_radius)
+        self.lr, self.eps, self.n_samples = float(lr), float(eps), int(n_samples)
+        self.b1, self.b2, self.adam_eps = b1, b2, adam_eps
+        self.mask = torch.as_tensor(mask, dtype=torch.uint8).to(dev).contiguous()
+        self.params = torch.as_tensor(params, dtype=F32).to(dev).contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.sos = torch.empty(g.sos_ny, g.sos_nx, dtype=F32, device=dev)
+        N = scan.centres.shape[0]
+        M = scan.d.numel()
+        self.w = torch.empty(N, g.n_elem, dtype=F32, device=dev)
+        self.gw = torch.empty(N, g.n_elem, dtype=F32, device=dev)
+        self.grad_sos = torch.empty_like(self.sos)
+        self.grad = torch.empty_like(self.params)
+        self.loss = torch.zeros(1, dtype=F32, device=dev)
+        self.ws_loss = torch.empty(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
+                                   dtype=torch.uint8, device=dev)
+        self.ws_adj = torch.empty(max(1, pact.sos_to_delays_adjoint_workspace_size(g, N)), dtype=torch.uint8,
+                                  device=dev)
+        self.ws_net = torch.empty(max(1, int(pact.load().pact_siren_sos_adjoint_workspace_size(g.sosg,
+                                                                                               self.hidden))),
+                                  dtype=torch.uint8, device=dev)
+        self.graph = None
+        self.graph_steps = 0
+
+    def sos_grid(self):
+        pact.siren_sos(self.params, self.hidden, self.omega0, self.mask, self.g, self.rho, self.scan.v0,
+                       out=self.sos)
+
+    def delays(self):
+        pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w)
+
+    def loss_grad(self):
+        pact.loss_and_grad(self.scan.Y, self.w, self.scan.centres, self.g, self.scan.d, self.eps, loss=self.loss,
+                           dL_dw=self.gw, ws=self.ws_loss)
+
+    def adjoint(self):
+        pact.sos_to_delays_adjoint(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
+                                   out=self.grad_sos, ws=self.ws_adj)
+        pact.siren_sos_adjoint(self.params, self.hidden, self.omega0, self.mask, self.g, self.rho, self.grad_sos,
+                               out=self.grad, ws=self.ws_net)
+
+    def update(self):
+        pact.adam_step(self.params, self.m, self.v, self.t, None, self.grad, self.lr, self.b1, self.b2,
+                       self.adam_eps)
+
+    def step(self):
+        self.sos_grid()
+        self.delays()
+        self.loss_grad()
+        self.adjoint()
+        self.update()
+
+    def capture(self, steps: int):
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(steps):
+                    self.step()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph, self.graph_steps = g, steps
+        return g
+
+    def run(self, steps: int):
+        if self.graph is not None and steps % self.graph_steps == 0:
+            for _ in range(steps // self.graph_steps):
+                self.graph.replay()
+        else:
+            for _ in range(steps):
+                self.step()

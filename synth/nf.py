@@ -51,3 +51,15 @@ def init_params(cfg: NfConfig = NF, seed: int | None = None, head_scale: float =
     p = np.concatenate(parts).astype(np.float32)
     assert p.size == cfg.n_params
     return p
+
+
+def siren_params(hidden: int = 256, omega0: float = 30.0, seed: int = 0, s0: float = 0.05) -> np.ndarray:
+    """Initial parameters of the paper's sinusoidal network (float32), layout W1 [hidden][2], b1, w2, b2, s, o:
+    first layer uniform in +-1/fan_in (fan_in = 2), output layer uniform in +-sqrt(6 / hidden) / omega0 (the
+    usual initialisation of sinusoidal networks), b2 = o = 0 and output scale s0 (mm/us)."""
+    rng = np.random.default_rng(2000 + seed)
+    lim2 = math.sqrt(6.0 / hidden) / omega0
+    p = np.concatenate([rng.uniform(-0.5, 0.5, 2 * hidden), rng.uniform(-0.5, 0.5, hidden),
+                        rng.uniform(-lim2, lim2, hidden), [0.0, s0, 0.0]]).astype(np.float32)
+    assert p.size == 4 * hidden + 3
+    return p

@@ -134,6 +134,30 @@ def test_nf_adjoint(lib):
     assert rel_l2(got2, 2.0 * got) < 1e-6
 
 
+@pytest.mark.parametrize("n_samples", [40, 64])
+def test_nf_stored_activations_match_recompute(lib, n_samples):
+    """The forward pass with activation storage gives the same delays, and the two-pass adjoint from the
+    stored activations the same gradient as the four-pass recomputing adjoint (same operations on the
+    same BF16 values)."""
+    announce(f"nf stored activations N_s={n_samples}")
+    c = NfCase(lib, SMALL, n_samples, rho=9.0, seed=9)
+    N = c.ov.centres.shape[0]
+    act = torch.empty(lib.pact.nf_activation_bytes(N, c.g, n_samples), dtype=torch.uint8, device="cuda")
+    w0 = lib.pact.nf_sos_to_delays(c.B, c.params, c.packed, c.net, c.v0, c.centres, c.g, n_samples)
+    w1 = lib.pact.nf_sos_to_delays(c.B, c.params, c.packed, c.net, c.v0, c.centres, c.g, n_samples, act=act)
+    rng = np.random.default_rng(10)
+    gw = dev32(rng.normal(size=(N, SMALL.n_elem)).astype(np.float32))
+    g0 = lib.pact.nf_sos_to_delays_adjoint(c.B, c.params, c.packed, c.net, c.v0, c.centres, c.g, n_samples, gw)
+    g1 = lib.pact.nf_sos_to_delays_adjoint(c.B, c.params, c.packed, c.net, c.v0, c.centres, c.g, n_samples, gw,
+                                          act=act)
+    torch.cuda.synchronize()
+    print(f"stored vs recompute: delays equal {torch.equal(w0, w1)}, gradient rel L2 {rel_l2(g1, g0):.2e}")
+    assert torch.equal(w0, w1)
+    assert rel_l2(g1, g0) < 1e-6
+    want = c.oracle_vjp(c.ov.centres, c.ring, gw.cpu().double(), bf16=True)
+    assert rel_l2(g1, want) < TOL_NF_GRAD
+
+
 def test_nf_adjoint_smooth_features(lib):
     """Low frequencies (0.05 cycles/mm): smooth features, little cancellation in the weight-gradient sums and
     few flipped roundings, so the kernels' backward logic is held to the delay bound."""

@@ -326,3 +326,37 @@ def test_tv_adam_fused_matches_oracle(lib):
     assert rel_l2(dp, dref) < 1e-4
     assert abs(loss.item() - tv_sum) <= 1e-5 * tv_sum
     assert torch.equal(a.cpu()[torch.tensor(mask == 0)], torch.tensor(v)[torch.tensor(mask == 0)])
+
+
+@pytest.mark.parametrize("scan", WORKLOADS, ids=lambda s: s.name)
+def test_stitch(lib, scan):
+    """Gaussian-weighted stitching of patch images against the oracle's, on random patches and on the
+    deconvolved patches of a real stack (X_hat from the fused kernel, then the inverse transform)."""
+    from oracle import stitch as Ostitch
+    announce(f"stitch {scan.name}")
+    ov = OracleView(scan)
+    g = lib.geometry_from(scan)
+    N = ov.centres.shape[0]
+    rng = np.random.default_rng(21)
+    x = rng.normal(size=(N, scan.P, scan.P)).astype(np.float32)
+    got = lib.pact.stitch(dev32(x), g)
+    torch.cuda.synchronize()
+    want = Ostitch.stitch(torch.tensor(x, dtype=torch.float64), scan.ny, scan.nx, scan.P, scan.stride, ov.px, ov.fwhm)
+    err = rel_l2(got, want)
+    print(f"stitch rel L2 {err:.2e}")
+    assert err < TOL_SPECTRA
+    # the reconstruction's last step: X_hat -> patches -> image
+    w, _ = _wavefronts(scan, 22)
+    Y = random_real_patches_spectra(N, scan.M, scan.P, rng).to(torch.complex64).to(torch.complex128)
+    eps = f32(1e-3)
+    H = Opsf.transfer_functions(w, ov.centres, ov.R, ov.phi0, ov.delays, scan.P, ov.px)
+    img_want = Ostitch.stitch(Odec.patch_images(Odec.multichannel_deconv(Y, H, eps)), scan.ny, scan.nx, scan.P,
+                              scan.stride, ov.px, ov.fwhm)
+    X = torch.empty(N, scan.P, scan.P, dtype=torch.complex64, device="cuda")
+    lib.pact.loss_and_grad(devc64(Opatch.half_spectrum(Y)), dev32(w), dev32(ov.centres), g, dev32(ov.delays), eps,
+                           X=X)
+    img = lib.pact.stitch(lib.pact.ifft2_real(X), g)
+    torch.cuda.synchronize()
+    e2 = rel_l2(img, img_want)
+    print(f"X_hat -> image rel L2 {e2:.2e}")
+    assert e2 < TOL_DECONV

@@ -1,0 +1,84 @@
+"""GPU parity of the paper's neural-field SOS (sinusoidal network on the SOS-grid nodes) against the FP64
+oracle of oracle/siren.py.  The network output feeds FP32 rays, so the node SOS is held to the delay
+tolerance (on the contrast v - v0) and every gradient to the gradient tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import siren as Os, loss as Oloss
+
+from gpu_common import RAGGED, TOL_DELAYS, TOL_GRAD, TOL_LOSS, OracleView, announce, dev32, devc64, f32, rel_l2, \
+    random_real_patches_spectra
+
+pytestmark = pytest.mark.gpu
+
+F64 = torch.float64
+OMEGA0 = 30.0
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2409_10876_amd as P
+    return P
+
+
+def _case(scan, seed):
+    p = synth.nf.siren_params(256, OMEGA0, seed, s0=0.05)
+    mask = synth.free_node_mask(scan)
+    return p, mask
+
+
+@pytest.mark.parametrize("scan", [synth.TINY, RAGGED, synth.PAPER], ids=lambda s: s.name)
+def test_siren_sos_and_adjoint(lib, scan):
+    announce(f"siren sos + adjoint {scan.name}")
+    p, mask = _case(scan, 1)
+    g = lib.geometry_from(scan)
+    rho, v0 = f32(scan.mask_radius), f32(scan.v0)
+    got = lib.pact.siren_sos(dev32(p), 256, OMEGA0, dev32(mask).to(torch.uint8), g, rho, v0)
+    rng = np.random.default_rng(2)
+    gv = rng.normal(size=(scan.sos_n, scan.sos_n)).astype(np.float32)
+    gp = lib.pact.siren_sos_adjoint(dev32(p), 256, OMEGA0, dev32(mask).to(torch.uint8), g, rho, dev32(gv))
+    torch.cuda.synchronize()
+    fn = lambda q: Os.sos_grid(q, scan.sos_n, scan.sos_n, f32(scan.sos_spacing), rho, mask, v0, OMEGA0)
+    pt = torch.tensor(p, dtype=F64)
+    want = fn(pt)
+    (gwant,) = Oloss.vjp(fn, (pt,), torch.tensor(gv, dtype=F64))
+    e1, e2 = rel_l2(got - v0, want - v0), rel_l2(gp, gwant)
+    print(f"siren node SOS rel L2 (contrast) {e1:.2e}, parameter gradient rel L2 {e2:.2e}")
+    assert e1 < TOL_DELAYS and e2 < TOL_GRAD
+    assert torch.equal(got.cpu()[torch.tensor(mask == 0)], torch.full((int((mask == 0).sum()),), v0))
+
+
+def test_siren_step_gradient_matches_oracle_chain(lib):
+    """One step of the paper's neural-field form (network -> node SOS -> rays -> fused loss -> ray adjoint ->
+    network adjoint) against the oracle's chain on the same spectra."""
+    scan = RAGGED
+    announce("siren step gradient")
+    p, mask = _case(scan, 3)
+    ov = OracleView(scan)
+    g = lib.geometry_from(scan)
+    N = ov.centres.shape[0]
+    rng = np.random.default_rng(4)
+    Y = random_real_patches_spectra(N, scan.M, scan.P, rng).to(torch.complex64).to(torch.complex128)
+    eps = f32(1e-3)
+    rho = f32(scan.mask_radius)
+    fn = lambda q: Os.sos_grid(q, scan.sos_n, scan.sos_n, ov.ds, rho, mask, ov.v0, OMEGA0)
+    pt = torch.tensor(p, dtype=F64)
+    v = fn(pt)
+    L, gv, _, _ = Oloss.loss_and_grad(v, np.ones_like(mask), Y, ov.geom(eps=eps), 0.0)
+    (want,) = Oloss.vjp(fn, (pt,), gv)
+
+    from oracle import patches as Opatch
+    sd = lib.ScanData(g, torch.zeros(1, device="cuda"), dev32(ov.delays), 1.0, 0.0, ov.v0)
+    sd.Y = devc64(Opatch.half_spectrum(Y))
+    solver = lib.SirenSolver(sd, mask, p, 256, OMEGA0, rho, lr=5e-3, eps=eps, n_samples=scan.n_samples)
+    solver.sos_grid()
+    solver.delays()
+    solver.loss_grad()
+    solver.adjoint()
+    torch.cuda.synchronize()
+    el = abs(solver.loss.item() - L.item()) / L.item()
+    eg = rel_l2(solver.grad, want)
+    print(f"siren step: loss rel {el:.2e}, dL/dparams rel L2 {eg:.2e}")
+    assert el < TOL_LOSS and eg < TOL_GRAD
