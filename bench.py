@@ -75,11 +75,10 @@ def traffic_bytes(stage):
 # copy kernel read as 256 MiB; rocprofv3 counter runs recorded under profiles/), keyed to the kernel source
 # it was taken on.
 TRAFFIC = {
-    "sos_to_delays": {"source": "rays.hip", "sha256_16": "2a53c10b9bff7ebe", "bytes": 1051536},
-    "loss_and_grad": {"source": "loss.hip", "sha256_16": "20898f327f3d1ad8", "bytes": 62129258},
-    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "2a53c10b9bff7ebe", "bytes": 47641288},
-    "tv_grad": {"source": "optim.hip", "sha256_16": "682a954aac982894", "bytes": 407052},
-    "adam_step": {"source": "optim.hip", "sha256_16": "682a954aac982894", "bytes": 513418},
+    "sos_to_delays": {"source": "rays.hip", "sha256_16": "fd82dc2567efbd46", "bytes": 1051542},
+    "loss_and_grad": {"source": "loss.hip", "sha256_16": "9fbd5c21e02c7b36", "bytes": 61946612},
+    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "fd82dc2567efbd46", "bytes": 47641628},
+    "tv_adam_step": {"source": "optim.hip", "sha256_16": "58740c5b3292f6bb", "bytes": 684343}
 }
 
 
@@ -395,7 +394,7 @@ def nf_leg(P, sd, scan, steps):
                                      "achieved": pts * bwd / (us["nf_sos_to_delays_adjoint"] * 1e-6) / 1e12,
                                      "peak": peak, "unit": "TFLOP/s", "alg_flops_per_launch": pts * bwd,
                                      "avg_launch_us": us["nf_sos_to_delays_adjoint"],
-                                     "note": "four passes, each recomputing the forward activations"},
+                                     "note": "two passes over the activations stored by the forward pass"},
     }
     for v in roof.values():
         v["frac"] = v["achieved"] / v["peak"]

@@ -264,7 +264,7 @@ PACT_API int pact_siren_sos(const float* params, int hidden, float omega0, const
                             const pact_grid* sosg, float mask_radius, float v0, float* sos, void* stream);
 
 /* Adjoint: dL_dparams (overwritten) = sum over the free nodes of dL_dsos dv/dparams.  ws: DEVICE
- * workspace of pact_siren_sos_adjoint_workspace_size() bytes (one partial per 256 nodes); partials
+ * workspace of pact_siren_sos_adjoint_workspace_size() bytes (one partial per 64 nodes); partials
  * are combined in a fixed order. */
 PACT_API size_t pact_siren_sos_adjoint_workspace_size(const pact_grid* sosg, int hidden);
 PACT_API int pact_siren_sos_adjoint(const float* params, int hidden, float omega0, const unsigned char* mask,

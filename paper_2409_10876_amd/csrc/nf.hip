@@ -586,21 +586,34 @@ __global__ __launch_bounds__(kNT) void nf_bwd_stored_kernel(NfArgs a, const __bf
         if (g == 0.0f) continue;
         const NfRay r = nf_ray(a, ray);
         if (r.dl == 0.0f) continue;
+        // the chunk's stored activations come through registers: the next chunk's loads are issued before
+        // this chunk's work, so their HBM latency hides behind it (barriers wait on LDS only)
+        const int feature = threadIdx.x >> 2, part = threadIdx.x & 3;
+        bf16x8 nxt[4];
+        float fnxt = 0.0f;
+        {
+            const size_t chunk0 = static_cast<size_t>(ray) * n_chunks;
+            const __bf16* src = act + chunk0 * kActChunk;
+#pragma unroll
+            for (int L = 0; L < 4; ++L) nxt[L] = ld8(src + (L * kH + feature) * kPc + 8 * part);
+            if (threadIdx.x < kPc) fnxt = f_in[chunk0 * kPc + threadIdx.x];
+        }
         for (int ch = 0; ch < n_chunks; ++ch) {
             const int s0 = ch * kPc;
             const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
-            const __bf16* src = act + chunk * kActChunk;
-            {
-                const int feature = threadIdx.x >> 2, part = threadIdx.x & 3;
 #pragma unroll
-                for (int L = 0; L < 4; ++L)
-                    *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) =
-                        ld8(src + (L * kH + feature) * kPc + 8 * part);
+            for (int L = 0; L < 4; ++L) *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) = nxt[L];
+            const float fcur = fnxt;
+            if (ch + 1 < n_chunks) {
+                const __bf16* src = act + (chunk + 1) * kActChunk;
+#pragma unroll
+                for (int L = 0; L < 4; ++L) nxt[L] = ld8(src + (L * kH + feature) * kPc + 8 * part);
+                if (threadIdx.x < kPc) fnxt = f_in[(chunk + 1) * kPc + threadIdx.x];
             }
             if (threadIdx.x < kPc) {
                 float d = 0.0f;
                 if (s0 + static_cast<int>(threadIdx.x) < a.Ns) {
-                    const float th = tanhf(f_in[chunk * kPc + threadIdx.x]);
+                    const float th = tanhf(fcur);
                     const float v = a.v0 + a.amp * th;
                     d = g * r.dl * a.v0 * a.amp * (1.0f - th * th) / (v * v);
                 }

@@ -572,12 +572,13 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
         attr = true;
     }
-    // segments per ray: the largest power of two (at most 64, at least 8 samples a segment) whose work items
-    // fit in one round of two workgroups per CU
+    // segments per ray: the smallest power of two (at most 64, at least 16 samples a segment) whose work
+    // items fill about two rounds of two workgroups per CU (measured at 86,528 rays x 256 samples: K = 8 is
+    // 10% faster than one round with K = 4)
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
     const long long lanes = 2LL * device_cu_count() * kThreads;
     int K = 1;
-    while (K < 64 && n_rays * (2 * K) <= lanes && n_samples / (2 * K) >= 8) K *= 2;
+    while (K < 64 && n_rays * K < lanes && n_samples / (2 * K) >= 16) K *= 2;
     PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "pact_sos_to_delays: too many rays");
     const int n_items = static_cast<int>(n_rays * K);
     const int blocks = static_cast<int>(std::min<long long>(ceil_div(n_items, kThreads), 2LL * device_cu_count()));

@@ -2,17 +2,19 @@
 // coordinates, v = v0 + s (w2 . sin(omega0 (W1 x + b1)) + b2) + o on the free nodes, v0 on the fixed ones;
 // x = node centre / mask radius.  The node grid then feeds the straight-ray kernels like the pixel grid.
 //
-// Forward: one thread per node, the parameters in LDS.  Adjoint: one workgroup per chunk of nodes with one
-// thread per hidden feature, so each thread accumulates its own feature's gradients over the chunk without
-// atomics; per-chunk partials are summed in a fixed order by a second kernel.  The network is small (1027
-// parameters, 19,600 nodes at 140 x 140): both kernels take a few microseconds next to the ray kernels.
+// Forward: four lanes per node, each summing a quarter of the features (then two shuffles), the
+// parameters in LDS.  Adjoint: one workgroup per chunk of 64 nodes with one thread per hidden feature, so
+// each thread accumulates its own feature's gradients over the chunk without atomics; per-chunk partials
+// are summed in a fixed order by two small kernels.  Small chunks give ~300 workgroups at 140 x 140 nodes,
+// enough to spread the 1027-parameter network over the chip.
 #include "common.h"
 
 namespace pact {
 namespace {
 
 constexpr int kSirenMaxHidden = 1024;
-constexpr int kNodesPerChunk = 256;
+constexpr int kNodesPerChunk = 64;
+constexpr int kLanesPerNode = 4;
 
 __device__ __forceinline__ void node_xy(int idx, int Gy, int Gx, float spacing, float inv_rho, float& x, float& y) {
     const int a = idx / Gx, b = idx - a * Gx;
@@ -20,13 +22,14 @@ __device__ __forceinline__ void node_xy(int idx, int Gy, int Gx, float spacing, 
     y = (static_cast<float>(a) - 0.5f * static_cast<float>(Gy - 1)) * spacing * inv_rho;
 }
 
-// f(x, y) = w2 . sin(omega0 (W1 (x, y) + b1)) + b2 from parameters in LDS
-__device__ __forceinline__ float siren_f(const float* p, int H, float omega0, float x, float y) {
+// Part of w2 . sin(omega0 (W1 (x, y) + b1)) over features k0, k0 + step, ... (parameters in LDS)
+__device__ __forceinline__ float siren_part(const float* p, int H, float omega0, float x, float y, int k0, int step) {
     const float* W1 = p;
     const float* b1 = p + 2 * H;
     const float* w2 = p + 3 * H;
-    float f = p[4 * H];
-    for (int k = 0; k < H; ++k) f = fmaf(w2[k], sinf(omega0 * fmaf(W1[2 * k], x, fmaf(W1[2 * k + 1], y, b1[k]))), f);
+    float f = 0.0f;
+    for (int k = k0; k < H; k += step)
+        f = fmaf(w2[k], sinf(omega0 * fmaf(W1[2 * k], x, fmaf(W1[2 * k + 1], y, b1[k]))), f);
     return f;
 }
 
@@ -37,15 +40,19 @@ __global__ __launch_bounds__(256) void siren_fwd_kernel(const float* __restrict_
     __shared__ float p[4 * kSirenMaxHidden + 3];
     for (int k = threadIdx.x; k < 4 * H + 3; k += blockDim.x) p[k] = params[k];
     __syncthreads();
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Gy * Gx) return;
-    float v = v0;
-    if (mask[idx]) {
+    // lanes 4j .. 4j + 3 of the workgroup share node blockIdx.x * 64 + j
+    const int idx = blockIdx.x * (blockDim.x / kLanesPerNode) + threadIdx.x / kLanesPerNode;
+    const int part = threadIdx.x % kLanesPerNode;
+    const bool live = idx < Gy * Gx && mask[idx] != 0;
+    float f = 0.0f;
+    if (live) {
         float x, y;
         node_xy(idx, Gy, Gx, spacing, inv_rho, x, y);
-        v = v0 + fmaf(p[4 * H + 1], siren_f(p, H, omega0, x, y), p[4 * H + 2]);
+        f = siren_part(p, H, omega0, x, y, part, kLanesPerNode);
     }
-    sos[idx] = v;
+    f += __shfl_xor(f, 1, kLanesPerNode);
+    f += __shfl_xor(f, 2, kLanesPerNode);
+    if (part == 0 && idx < Gy * Gx) sos[idx] = live ? v0 + fmaf(p[4 * H + 1], f + p[4 * H], p[4 * H + 2]) : v0;
 }
 
 // Partial gradients of one chunk of nodes: partial[chunk][4H + 3] in the parameter layout.
@@ -62,24 +69,29 @@ __global__ __launch_bounds__(256) void siren_adj_kernel(const float* __restrict_
     const int n0 = blockIdx.x * kNodesPerChunk;
     const int count = min(kNodesPerChunk, Gy * Gx - n0);
     const float s = p[4 * H + 1];
-    // per node of the chunk: coordinates, g = dL/dv on free nodes (0 on fixed ones) and the network output
+    // per node of the chunk (four lanes per node): coordinates, g = dL/dv on free nodes (0 on fixed ones)
+    // and the network output
     float gsum = 0.0f, gfsum = 0.0f;
-    for (int j = threadIdx.x; j < kNodesPerChunk; j += blockDim.x) {
+    {
+        const int j = threadIdx.x / kLanesPerNode, part = threadIdx.x % kLanesPerNode;
         float x = 0.0f, y = 0.0f, g = 0.0f, f = 0.0f;
-        if (j < count) {
-            const int idx = n0 + j;
-            node_xy(idx, Gy, Gx, spacing, inv_rho, x, y);
-            if (mask[idx]) {
-                g = dL_dsos[idx];
-                f = siren_f(p, H, omega0, x, y);
-            }
+        const bool live = j < count && mask[n0 + j] != 0;
+        if (j < count) node_xy(n0 + j, Gy, Gx, spacing, inv_rho, x, y);
+        if (live) f = siren_part(p, H, omega0, x, y, part, kLanesPerNode);
+        f += __shfl_xor(f, 1, kLanesPerNode);
+        f += __shfl_xor(f, 2, kLanesPerNode);
+        if (live) {
+            g = dL_dsos[n0 + j];
+            f += p[4 * H];
         }
-        nx_[j] = x;
-        ny_[j] = y;
-        ng[j] = g;
-        nf[j] = f;
-        gsum += g;
-        gfsum += g * f;
+        if (part == 0) {
+            nx_[j] = x;
+            ny_[j] = y;
+            ng[j] = g;
+            nf[j] = f;
+            gsum = g;
+            gfsum = g * f;
+        }
     }
     gsum = block_sum(gsum, red);
     gfsum = block_sum(gfsum, red);     // its barriers also publish the node tables
@@ -90,8 +102,11 @@ __global__ __launch_bounds__(256) void siren_adj_kernel(const float* __restrict_
         for (int j = 0; j < count; ++j) {
             const float g = ng[j];
             if (g == 0.0f) continue;
-            float sn, cs;
-            sincosf(omega0 * fmaf(wx, nx_[j], fmaf(wy, ny_[j], bk)), &sn, &cs);
+            // sin and cos from the hardware units, which take revolutions (reduced to [-1/2, 1/2]); their
+            // error, ~1e-6, is far inside the gradient tolerance
+            float rev = omega0 * fmaf(wx, nx_[j], fmaf(wy, ny_[j], bk)) * (1.0f / kTwoPi);
+            rev -= rintf(rev);
+            const float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
             const float df = g * s;                        // dL/df at the node
             gw2 = fmaf(df, sn, gw2);
             const float dz = df * w2k * cs * omega0;       // dL/d(W1[k] . x + b1[k])
@@ -111,12 +126,29 @@ __global__ __launch_bounds__(256) void siren_adj_kernel(const float* __restrict_
     }
 }
 
-__global__ __launch_bounds__(256) void siren_reduce_kernel(const float* __restrict__ partial, int n_part, int n,
-                                                          float* __restrict__ out) {
+// Fixed-order sum of the per-chunk partials in two levels (kSlices contiguous runs of partials per
+// parameter, then the runs), so that ~300 partials of ~1000 parameters are read by many threads at once.
+constexpr int kSlices = 16;
+
+__global__ __launch_bounds__(256) void siren_reduce1_kernel(const float* __restrict__ partial, int n_part, int n,
+                                                           float* __restrict__ part2) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int slice = blockIdx.y;
+    if (j >= n) return;
+    const int per = (n_part + kSlices - 1) / kSlices;
+    const int b1 = min((slice + 1) * per, n_part);
+    float s = 0.0f;
+    for (int b = slice * per; b < b1; ++b) s += partial[static_cast<size_t>(b) * n + j];
+    part2[static_cast<size_t>(slice) * n + j] = s;
+}
+
+__global__ __launch_bounds__(256) void siren_reduce2_kernel(const float* __restrict__ part2, int n,
+                                                           float* __restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     float s = 0.0f;
-    for (int b = 0; b < n_part; ++b) s += partial[static_cast<size_t>(b) * n + j];
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) s += part2[static_cast<size_t>(k) * n + j];
     out[j] = s;
 }
 
@@ -140,15 +172,15 @@ extern "C" int pact_siren_sos(const float* params, int hidden, float omega0, con
     if (int s = check_siren(params, hidden, omega0, mask, sosg, mask_radius, "pact_siren_sos")) return s;
     PACT_CHECK_ARG(sos, "pact_siren_sos: null output");
     const int n = sosg->ny * sosg->nx;
-    siren_fwd_kernel<<<ceil_div(n, 256), 256, 0, as_stream(stream)>>>(params, hidden, omega0, mask, sosg->ny, sosg->nx,
-                                                                     sosg->spacing, 1.0f / mask_radius, v0, sos);
+    siren_fwd_kernel<<<ceil_div(n, 256 / kLanesPerNode), 256, 0, as_stream(stream)>>>(
+        params, hidden, omega0, mask, sosg->ny, sosg->nx, sosg->spacing, 1.0f / mask_radius, v0, sos);
     return launch_status("pact_siren_sos");
 }
 
 extern "C" size_t pact_siren_sos_adjoint_workspace_size(const pact_grid* sosg, int hidden) {
     if (!sosg || sosg->ny <= 0 || sosg->nx <= 0 || hidden <= 0) return 0;
     const size_t chunks = (static_cast<size_t>(sosg->ny) * sosg->nx + pact::kNodesPerChunk - 1) / pact::kNodesPerChunk;
-    return chunks * (4 * static_cast<size_t>(hidden) + 3) * sizeof(float);
+    return (chunks + pact::kSlices) * (4 * static_cast<size_t>(hidden) + 3) * sizeof(float);
 }
 
 extern "C" int pact_siren_sos_adjoint(const float* params, int hidden, float omega0, const unsigned char* mask,
@@ -170,6 +202,9 @@ extern "C" int pact_siren_sos_adjoint(const float* params, int hidden, float ome
     siren_adj_kernel<<<chunks, 256, 0, as_stream(stream)>>>(params, hidden, omega0, mask, sosg->ny, sosg->nx,
                                                            sosg->spacing, 1.0f / mask_radius, dL_dsos, partial);
     if (int s = launch_status("pact_siren_sos_adjoint")) return s;
-    siren_reduce_kernel<<<ceil_div(np, 256), 256, 0, as_stream(stream)>>>(partial, chunks, np, dL_dparams);
+    float* part2 = partial + static_cast<size_t>(chunks) * np;
+    siren_reduce1_kernel<<<dim3(ceil_div(np, 256), kSlices), 256, 0, as_stream(stream)>>>(partial, chunks, np, part2);
+    if (int s = launch_status("pact_siren_sos_adjoint")) return s;
+    siren_reduce2_kernel<<<ceil_div(np, 256), 256, 0, as_stream(stream)>>>(part2, np, dL_dparams);
     return launch_status("pact_siren_sos_adjoint");
 }

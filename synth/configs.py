@@ -110,10 +110,15 @@ TINY = Scan(
     delays=delays_from_sos_offsets(50.0, 1.5, (-0.020, -0.010, 0.0, 0.010, 0.020)),
     P=32, stride=16, fwhm=fwhm_for_patch(32, 0.2),
     sos_n=32, sos_spacing=0.8, mask_radius=12.0,
-    n_samples=256, eps=1e-6, lam_tv=1e-4, lr=2e-3, steps=10,
+    n_samples=256, eps=1e-6, lam_tv=1e7, lr=2e-3, steps=10,
     phantom="disc", n_blobs=20, blob_radius=11.0,
 )
 
+# TV weights.  The loss here is an unnormalised sum (about 4e12 at v = v0 for the paper-shaped scan, 1e10
+# for the small one), so the paper's lambda = 1e-4, which belongs to its own normalisation, would leave TV
+# without effect.  lambda = 3e9 with lr = 1e-3 mm/us gave the lowest SOS error over 500 steps in a sweep
+# of lr in {3e-4, 1e-3} x lambda in {1e9, 3e9, 1e10, 3e10} on the paper-shaped scan (9.8 -> 5.6 m/s); the
+# small scan takes the same ratio to its loss.
 PAPER = Scan(
     name="paper", ny=560, nx=560, px=0.1,
     n_elem=512, radius=110.0, phi0=0.0,
@@ -121,7 +126,7 @@ PAPER = Scan(
     delays=uniform_delays(-0.8, 0.8, 11),
     P=80, stride=40, fwhm=fwhm_for_patch(80, 0.1),
     sos_n=140, sos_spacing=0.4, mask_radius=26.0,
-    n_samples=256, eps=1e-6, lam_tv=1e-4, lr=1e-3, steps=500,
+    n_samples=256, eps=1e-6, lam_tv=3e9, lr=1e-3, steps=500,
     phantom="ellipses", n_blobs=100, blob_radius=25.0,
 )
 

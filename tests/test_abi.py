@@ -100,3 +100,15 @@ def test_binding_refuses_host_tensors(P):
     g = P.geometry_from(synth.TINY)
     with pytest.raises(ValueError):
         P.pact.sos_to_delays(torch.zeros(32, 32), g, 1.5, torch.zeros(49, 2), 256, out=torch.zeros(49, 256))
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No fallback: without libpact.so every call raises PactError."""
+    import paper_2409_10876_amd.pact as pt
+    saved = pt._lib
+    try:
+        pt._lib = None
+        with pytest.raises(pt.PactError, match="missing"):
+            pt.load(str(tmp_path / "libpact.so"))
+    finally:
+        pt._lib = saved

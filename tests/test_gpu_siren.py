@@ -44,9 +44,14 @@ def test_siren_sos_and_adjoint(lib, scan):
     pt = torch.tensor(p, dtype=F64)
     want = fn(pt)
     (gwant,) = Oloss.vjp(fn, (pt,), torch.tensor(gv, dtype=F64))
-    e1, e2 = rel_l2(got - v0, want - v0), rel_l2(gp, gwant)
-    print(f"siren node SOS rel L2 (contrast) {e1:.2e}, parameter gradient rel L2 {e2:.2e}")
-    assert e1 < TOL_DELAYS and e2 < TOL_GRAD
+    # the node SOS is an FP32 output: per node it can be right only to its last FP32 step (1.2e-7 mm/us at
+    # 1.5), on top of the 1e-5 relative bound of the arithmetic on the contrast v - v0
+    err = (got.cpu().double() - want).abs().max().item()
+    bound = 2 * 2.0 ** -23 * 1.6 + TOL_DELAYS * (want - v0).abs().max().item()
+    e1, e2 = rel_l2(got.double() - v0, want - v0), rel_l2(gp, gwant)
+    print(f"siren node SOS: max error {err:.2e} (bound {bound:.2e}), contrast rel L2 {e1:.2e}; "
+          f"parameter gradient rel L2 {e2:.2e}")
+    assert err <= bound and e2 < TOL_GRAD
     assert torch.equal(got.cpu()[torch.tensor(mask == 0)], torch.full((int((mask == 0).sum()),), v0))
 
 
