@@ -23,7 +23,7 @@
 // all the chunks it processes; the registers hold the layers of one pass only, so the adjoint runs four
 // passes (layers 3-4, layer 2, and each half of layer 1's columns), each recomputing the forward
 // activations.  Each workgroup writes
-// its partial gradient once; a second kernel sums the partials in a fixed order.
+// its partial gradient once; two small kernels sum the partials in a fixed order.
 #include "common.h"
 
 namespace pact {
@@ -684,14 +684,37 @@ __global__ __launch_bounds__(kNT) void nf_bwd_stored_kernel(NfArgs a, const __bf
     }
 }
 
-// dL/dparams[j] = sum over workgroups of partial[b][j], in order.
-__global__ __launch_bounds__(256) void nf_reduce_kernel(const float* __restrict__ partial, int n_part,
-                                                       float* __restrict__ out) {
+// dL/dparams[j] = sum over workgroups of partial[b][j] in a fixed order, in two levels (kSlices contiguous
+// runs of partials, then the runs) so that many threads read the partials at once.
+constexpr int kSlices = 16;
+
+__global__ __launch_bounds__(256) void nf_reduce1_kernel(const float* __restrict__ partial, int n_part,
+                                                        float* __restrict__ part2) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int slice = blockIdx.y;
+    if (j >= kNParams) return;
+    const int per = (n_part + kSlices - 1) / kSlices;
+    const int b1 = min((slice + 1) * per, n_part);
+    float s = 0.0f;
+    for (int b = slice * per; b < b1; ++b) s += partial[static_cast<size_t>(b) * kNParams + j];
+    part2[static_cast<size_t>(slice) * kNParams + j] = s;
+}
+
+__global__ __launch_bounds__(256) void nf_reduce2_kernel(const float* __restrict__ part2, float* __restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= kNParams) return;
     float s = 0.0f;
-    for (int b = 0; b < n_part; ++b) s += partial[static_cast<size_t>(b) * kNParams + j];
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) s += part2[static_cast<size_t>(k) * kNParams + j];
     out[j] = s;
+}
+
+int launch_nf_reduce(const float* partial, int n_part, float* out, hipStream_t st) {
+    float* part2 = const_cast<float*>(partial) + static_cast<size_t>(n_part) * kNParams;
+    nf_reduce1_kernel<<<dim3(ceil_div(kNParams, 256), kSlices), 256, 0, st>>>(partial, n_part, part2);
+    if (int s = launch_status("pact_nf_sos_to_delays_adjoint")) return s;
+    nf_reduce2_kernel<<<ceil_div(kNParams, 256), 256, 0, st>>>(part2, out);
+    return launch_status("pact_nf_sos_to_delays_adjoint");
 }
 
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
@@ -845,7 +868,7 @@ extern "C" int pact_nf_sos_to_delays(const float* B, const float* params, const 
 
 extern "C" size_t pact_nf_sos_to_delays_adjoint_workspace_size(int n_freq, int width) {
     if (n_freq != pact::kF || width != pact::kH) return 0;
-    return static_cast<size_t>(pact::device_cu_count()) * pact::kNParams * sizeof(float);
+    return static_cast<size_t>(pact::device_cu_count() + pact::kSlices) * pact::kNParams * sizeof(float);
 }
 
 extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, const unsigned short* packed,
@@ -861,7 +884,7 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
         return s;
     PACT_CHECK_ARG(dL_dw && dL_dparams, "pact_nf_sos_to_delays_adjoint: null pointer");
     const int blocks = device_cu_count();
-    const size_t need = static_cast<size_t>(blocks) * kNParams * sizeof(float);
+    const size_t need = static_cast<size_t>(blocks + kSlices) * kNParams * sizeof(float);
     if (!ws || ws_bytes < need) {
         set_error("pact_nf_sos_to_delays_adjoint: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
         return PACT_EWORKSPACE;
@@ -883,8 +906,7 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
         // two passes from the stored activations: layers 2-4 and the head, then layer 1
         if (int s = launch_bwd_stored<2, 4>(a, act_h, act_f, dL_dw, scale, partial, blocks, st)) return s;
         if (int s = launch_bwd_stored<1, 1>(a, act_h, act_f, dL_dw, scale, partial, blocks, st)) return s;
-        nf_reduce_kernel<<<ceil_div(kNParams, 256), 256, 0, st>>>(partial, blocks, dL_dparams);
-        return launch_status("pact_nf_sos_to_delays_adjoint");
+        return launch_nf_reduce(partial, blocks, dL_dparams, st);
     }
     // four passes, each recomputing the forward activations: layers 3-4 (and the head), layer 2, and the
     // two column halves of layer 1, so that each pass's gradient accumulators fit in registers
@@ -892,6 +914,5 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
     if (int s = launch_bwd<2, 2, 0, 0>(a, dL_dw, scale, partial, blocks, st)) return s;
     if (int s = launch_bwd<1, 1, 0, 8>(a, dL_dw, scale, partial, blocks, st)) return s;
     if (int s = launch_bwd<1, 1, 8, 8>(a, dL_dw, scale, partial, blocks, st)) return s;
-    nf_reduce_kernel<<<ceil_div(kNParams, 256), 256, 0, st>>>(partial, blocks, dL_dparams);
-    return launch_status("pact_nf_sos_to_delays_adjoint");
+    return launch_nf_reduce(partial, blocks, dL_dparams, st);
 }
