@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed for the CPU baseline")
     ap.add_argument("--nf-steps", type=int, default=3, help="neural-field optimisation steps timed (0: skip)")
+    ap.add_argument("--batch-scans", type=int, default=0,
+                    help="also time this many independent uneven scans solved together (0: skip)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run one plain 256 MiB device copy kernel first (the reference for HBM counter scaling)")
     return ap.parse_args()
@@ -249,6 +251,8 @@ def main():
     out["paper_neural_field"] = siren_leg(P, sd, scan, inp, reps=args.timing_steps)
     if args.nf_steps > 0:
         out["neural_field"] = nf_leg(P, sd, scan, args.nf_steps)
+    if args.batch_scans > 0:
+        out["batched"] = batch_leg(P, args.batch_scans)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, inp, args.cpu_steps)
@@ -349,6 +353,43 @@ def siren_leg(P, sd, scan, inp, reps=100, graph_steps=50):
     return {"steps_per_s": 1e6 / us_step, "us_per_step": us_step, "stage_us": us,
             "config": "sinusoidal network 2 -> 256 -> 1 (1027 parameters, omega0 30) on the 140^2 SOS nodes, "
                       "then the pixel-grid path; no TV"}
+
+
+def batch_leg(P, n_scans, steps=100, graph_steps=10):
+    """Independent scans of uneven sizes (256^2 .. 768^2 px, 256 .. 1024 elements, 7 .. 15 delays, 64^2 or
+    80^2 patches) solved together: per-scan step graphs replayed on one stream each, against the same work
+    one scan after another.  Reports optimisation steps per second summed over the scans."""
+    import numpy as np
+    import torch
+    import synth
+    t0 = time.perf_counter()
+    scans = synth.configs.batch_scans(n_scans)
+    solvers = []
+    for k, sc in enumerate(scans):
+        inp = synth.make_inputs(sc, seed=sc.seed)
+        sd = P.prepare_scan(sc, inp.S, np.asarray(sc.delays, dtype=np.float32))
+        solvers.append(P.PixelGridSolver(sd, inp.mask, eps=sc.eps, lam=sc.lam_tv, lr=sc.lr, n_samples=sc.n_samples))
+    print(f"[bench] batch: {n_scans} scans prepared in {time.perf_counter() - t0:.1f} s", flush=True)
+    batch = P.BatchedSolver(solvers, graph_steps=graph_steps)
+    batch.run(graph_steps)
+    batch.run_sequential(graph_steps)
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn in (("sequential", batch.run_sequential), ("concurrent", batch.run)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn(steps)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        out[name] = {"ms": ms, "scan_steps_per_s": n_scans * steps / (ms * 1e-3)}
+    out["speedup"] = out["sequential"]["ms"] / out["concurrent"]["ms"]
+    out["scans"] = [{"px": s.ny, "n_elem": s.n_elem, "M": s.M, "P": s.P, "patches": s.n_patches, "sos_n": s.sos_n}
+                    for s in scans]
+    out["patches_x_delays_per_s"] = sum(s.n_patches * s.M for s in scans) * steps / (out["concurrent"]["ms"] * 1e-3)
+    print(f"[bench] batch: {n_scans} scans x {steps} steps: sequential {out['sequential']['ms']:.1f} ms, "
+          f"concurrent {out['concurrent']['ms']:.1f} ms", flush=True)
+    return out
 
 
 def nf_leg(P, sd, scan, steps):

@@ -9,8 +9,8 @@ there is no fallback implementation.
 from . import pact  # noqa: F401
 from .pact import PactError, Geometry, load  # noqa: F401
 
-from .solver import (ScanData, PixelGridSolver, NeuralFieldSolver, SirenSolver, SosLoss,  # noqa: E402,F401
-                     geometry_from, prepare_scan)
+from .solver import (ScanData, PixelGridSolver, NeuralFieldSolver, SirenSolver, BatchedSolver,  # noqa: E402,F401
+                     SosLoss, geometry_from, prepare_scan)
 
-__all__ = ["pact", "PactError", "Geometry", "load", "ScanData", "PixelGridSolver", "NeuralFieldSolver", "SirenSolver", "SosLoss",
+__all__ = ["pact", "PactError", "Geometry", "load", "ScanData", "PixelGridSolver", "NeuralFieldSolver", "SirenSolver", "BatchedSolver", "SosLoss",
            "geometry_from", "prepare_scan"]

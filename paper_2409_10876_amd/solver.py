@@ -326,3 +326,36 @@ class SirenSolver:
         else:
             for _ in range(steps):
                 self.step()
+
+
+class BatchedSolver:
+    """Independent scans solved together (many reconstructions at once): one PixelGridSolver per scan, each
+    with its own captured step graph, replayed on its own HIP stream so that the scans' kernels overlap and
+    fill the chip where one scan's small kernels and tails would leave it idle.  Each scan's results are the
+    ones it gets alone (the kernels are deterministic and share no buffers)."""
+
+    def __init__(self, solvers, graph_steps: int = 10):
+        self.solvers = list(solvers)
+        self.graph_steps = graph_steps
+        self.streams = [torch.cuda.Stream() for _ in self.solvers]
+        for s in self.solvers:
+            s.step()
+        torch.cuda.synchronize()
+        for s in self.solvers:
+            s.capture(graph_steps)
+        torch.cuda.synchronize()
+
+    def run(self, steps: int):
+        """Advance every scan by `steps` (a multiple of graph_steps), all scans concurrently."""
+        cur = torch.cuda.current_stream()
+        for s, st in zip(self.solvers, self.streams):
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                s.run(steps)
+        for st in self.streams:
+            cur.wait_stream(st)
+
+    def run_sequential(self, steps: int):
+        """The same work, one scan after another on the current stream (the reference for the overlap)."""
+        for s in self.solvers:
+            s.run(steps)

@@ -137,3 +137,29 @@ def describe(s: Scan) -> str:
     return (f"{s.name}: {s.ny}x{s.nx} px @ {s.px} mm, ring {s.n_elem} el R={s.radius} mm, "
             f"{s.n_t} samples @ {s.fs} /us, M={s.M}, patches {s.n_patches} of {s.P}^2 "
             f"(stride {s.stride}), SOS {s.sos_n}^2 @ {s.sos_spacing} mm, N_s={s.n_samples}")
+
+
+def batch_scans(n: int = 32, seed: int = 0, n_blobs: int = 10) -> list:
+    """Independent scans of uneven sizes for batched solves: square images of 256^2 to 768^2 pixels at
+    0.1 mm, 256 to 1024 ring elements (radius 110 mm), 7 to 15 delays uniform in [-0.8, 0.8] mm, patches of
+    64^2 or 80^2 at half-patch stride, SOS node grid at 0.4 mm over the image, mask radius 0.45 of the
+    image side, records long enough for the farthest pixel."""
+    import math
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        side = int(rng.integers(16, 49)) * 16                      # 256 .. 768 pixels
+        P = int(rng.choice([64, 80]))
+        n_elem = int(rng.choice([256, 384, 512, 768, 1024]))
+        M = int(rng.integers(7, 16))
+        field = side * 0.1
+        G = int(round(field / 0.4))
+        reach = 110.0 + field * math.sqrt(2) / 2 + 2.0             # farthest pixel, mm
+        n_t = int(math.ceil(reach / 1.5 * 40.0 / 512.0)) * 512
+        out.append(PAPER.with_(name=f"batch{k}", ny=side, nx=side, n_elem=n_elem, n_t=n_t,
+                               delays=uniform_delays(-0.8, 0.8, M), P=P, stride=P // 2,
+                               fwhm=fwhm_for_patch(P, 0.1), sos_n=G, sos_spacing=0.4,
+                               mask_radius=0.45 * field, n_blobs=n_blobs, blob_radius=0.4 * field,
+                               seed=seed * 1000 + k))
+    return out
