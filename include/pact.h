@@ -318,6 +318,83 @@ PACT_API int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, 
                                   const float* dL_dw, const float* scale, float* dL_dparams, const void* act,
                                   size_t act_bytes, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Learned warm start: convolutional SOS initialiser ----
+ *
+ * Not part of the paper's method, which uses no training data (Sec. 3.3): a convolutional network maps
+ * the delay-and-sum stack (Eq. DAS), averaged down to the SOS node grid, to a starting SOS for the
+ * optimisation of Eq. jr.  Its training scans are generated by the method's own forward model
+ * (Eq. TOF through Eq. wf, then Eq. DAS).
+ *
+ * Tensors are DEVICE BF16, NHWC: [n][H][W][C], channels contiguous.  Built channel counts (ci, co):
+ * (16, 64), (64, 64), (64, 16); others return -4.  Operands are BF16, accumulation and biases FP32, results
+ * rounded to the nearest BF16.  Every output is overwritten. */
+
+/* 3 x 3 convolution, stride 1, zero padding 1:
+ *   y[n][r][c][o] = act(bias[o] + sum_{ky,kx,i} W[o][ky][kx][i] x[n][r + ky - 1][c + kx - 1][i]),
+ * act = relu when relu != 0, then y = 0 where mask <= 0 when mask (same layout as y) is not NULL.
+ * packed: the weights as made by pact_conv3x3_pack, pact_conv3x3_packed_count(ci, co) BF16 values.
+ * bias: DEVICE float [co] or NULL.  The input gradient of a convolution is this call with the packed
+ * adjoint weights (ci and co swapped), no bias, and the ReLU mask of the layer below as mask. */
+PACT_API size_t pact_conv3x3_packed_count(int ci, int co);
+/* weights: DEVICE float [co][3][3][ci].  packed: [co][K] BF16 with K = 9 ci rounded up to 32,
+ * k = (3 ky + kx) ci + i, zero beyond 9 ci.  packed_adjoint (or NULL): the weights of the input
+ * gradient, [ci][K'] with K' = 9 co rounded up to 32, k = (3 (2 - ky) + (2 - kx)) co + o. */
+PACT_API int pact_conv3x3_pack(const float* weights, int ci, int co, void* packed, void* packed_adjoint,
+                               void* stream);
+PACT_API int pact_conv3x3_bf16(const void* x, int n, int H, int W, int ci, const void* packed, const float* bias,
+                               int co, int relu, const void* mask, void* y, void* stream);
+
+/* Weight and bias gradients of a convolution from its input x [n][H][W][ci] and output gradient
+ * g [n][H][W][co]: grad (DEVICE float, co * 9 * ci + co values, overwritten) =
+ *   dW[o][ky][kx][i] = sum_{n,r,c} g[n][r][c][o] x[n][r + ky - 1][c + kx - 1][i], then db[o] = sum g[..][o],
+ * the layout of the weights followed by the bias.  ws: DEVICE workspace of
+ * pact_conv3x3_wgrad_workspace_size() bytes (one partial per workgroup, summed in a fixed order). */
+PACT_API size_t pact_conv3x3_wgrad_workspace_size(int n, int H, int W, int ci, int co);
+PACT_API int pact_conv3x3_wgrad_bf16(const void* x, const void* g, int n, int H, int W, int ci, int co,
+                                     float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* Resampling between resolutions (H, W even, C a multiple of 8; H, W are the larger grid's):
+ *   pool2:           y [n][H/2][W/2][C] = mean of x [n][H][W][C] over 2 x 2 blocks
+ *   up2_add:         y [n][H][W][C] = x [n][H/2][W/2][C] at the parent pixel + skip [n][H][W][C]
+ *   up2_add_adjoint: g_low [n][H/2][W/2][C] = (sum of g_high over the 2 x 2 children) where mask_low > 0
+ *                    (mask_low NULL: everywhere), else 0
+ *   pool2_adjoint:   g_high [n][H][W][C] = (g_low at the parent / 4 + skip) where mask > 0, else 0
+ *                    (skip, mask may be NULL) */
+PACT_API int pact_pool2_bf16(const void* x, int n, int H, int W, int C, void* y, void* stream);
+PACT_API int pact_up2_add_bf16(const void* x, const void* skip, int n, int H, int W, int C, void* y, void* stream);
+PACT_API int pact_up2_add_adjoint_bf16(const void* g_high, const void* mask_low, int n, int H, int W, int C,
+                                       void* g_low, void* stream);
+PACT_API int pact_pool2_adjoint_bf16(const void* g_low, const void* skip, const void* mask, int n, int H, int W,
+                                     int C, void* g_high, void* stream);
+
+/* Network input from a delay-and-sum stack [M][H][W] (DEVICE float): x [H/f][W/f][C] BF16 with
+ * x[r][c][m] = scale * mean of stack[m] over the f x f block (r, c), 0 for m >= M (M <= C, C a multiple of 8). */
+PACT_API int pact_warm_input(const float* stack, int M, int H, int W, int factor, float scale, int C, void* x,
+                             void* stream);
+
+/* Training loss of the network output z [n][H][W][C] (channel 0 used) against the target
+ * t [n][H][W] (DEVICE float) on the free nodes (mask [H][W], DEVICE uint8, 1 = free):
+ *   loss = norm * sum_{n, free nodes} (z - t)^2 (DEVICE scalar),  g = d loss / d z [n][H][W][C] BF16
+ * (channel 0 = 2 norm (z - t) on free nodes, 0 elsewhere and in every other channel).
+ * ws: DEVICE workspace of pact_warm_loss_workspace_size() bytes; the block sums are added in a fixed order. */
+PACT_API size_t pact_warm_loss_workspace_size(int n, int H, int W);
+PACT_API int pact_warm_loss(const void* z, int n, int H, int W, int C, const float* target,
+                            const unsigned char* mask, float norm, float* loss, void* g, void* ws, size_t ws_bytes,
+                            void* stream);
+/* SOS map from the network output: sos [n][H][W] = v0 + scale * z[..][0] on free nodes, v0 elsewhere. */
+PACT_API int pact_warm_sos(const void* z, int n, int H, int W, int C, const unsigned char* mask, float v0,
+                           float scale, float* sos, void* stream);
+
+/* Synthetic channel data of a training scan (the stand-in for full-wave data): sources b at
+ * sources [n_src][2] (x, y mm) with amplitude amp[b] and width sigma[b] (mm); w [n_src][n_elem]: the
+ * wavefront errors of Eq. wf from each source to each element (pact_sos_to_delays with the sources as
+ * centres).  Arrival time T = (|r_n - c_b| - w[b][n]) / v0 (Eq. TOF), and
+ *   S[n][t] = sum_b amp[b] (1 - u^2) exp(-u^2 / 2) over |u| <= 8,  u = v0 (t0 + t / fs - T) / sigma[b],
+ * S [n_elem][n_t] DEVICE float. */
+PACT_API int pact_ricker_channels(const float* w, const float* sources, const float* amp, const float* sigma,
+                                  int n_src, const pact_ring* ring, float v0, int n_t, float fs, float t0, float* S,
+                                  void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@ from .pact import PactError, Geometry, load  # noqa: F401
 
 from .solver import (ScanData, PixelGridSolver, NeuralFieldSolver, SirenSolver, BatchedSolver,  # noqa: E402,F401
                      SosLoss, geometry_from, prepare_scan)
+from . import warmstart  # noqa: E402,F401
 
 __all__ = ["pact", "PactError", "Geometry", "load", "ScanData", "PixelGridSolver", "NeuralFieldSolver", "SirenSolver", "BatchedSolver", "SosLoss",
-           "geometry_from", "prepare_scan"]
+           "geometry_from", "prepare_scan", "warmstart"]

@@ -78,6 +78,20 @@ _SIGS = {
     "pact_nf_sos_to_delays_adjoint_workspace_size": (_Z, [_I, _I]),
     "pact_nf_sos_to_delays_adjoint": (_I, [_P, _P, _P, _I, _I, _F, _F, _F, _P, _I, _PRING, _I, _P, _P, _P, _P,
                                            _Z, _P, _Z, _P]),
+    "pact_conv3x3_packed_count": (_Z, [_I, _I]),
+    "pact_conv3x3_pack": (_I, [_P, _I, _I, _P, _P, _P]),
+    "pact_conv3x3_bf16": (_I, [_P, _I, _I, _I, _I, _P, _P, _I, _I, _P, _P, _P]),
+    "pact_conv3x3_wgrad_workspace_size": (_Z, [_I, _I, _I, _I, _I]),
+    "pact_conv3x3_wgrad_bf16": (_I, [_P, _P, _I, _I, _I, _I, _I, _P, _P, _Z, _P]),
+    "pact_pool2_bf16": (_I, [_P, _I, _I, _I, _I, _P, _P]),
+    "pact_up2_add_bf16": (_I, [_P, _P, _I, _I, _I, _I, _P, _P]),
+    "pact_up2_add_adjoint_bf16": (_I, [_P, _P, _I, _I, _I, _I, _P, _P]),
+    "pact_pool2_adjoint_bf16": (_I, [_P, _P, _P, _I, _I, _I, _I, _P, _P]),
+    "pact_warm_input": (_I, [_P, _I, _I, _I, _I, _F, _I, _P, _P]),
+    "pact_warm_loss_workspace_size": (_Z, [_I, _I, _I]),
+    "pact_warm_loss": (_I, [_P, _I, _I, _I, _I, _P, _P, _F, _P, _P, _P, _Z, _P]),
+    "pact_warm_sos": (_I, [_P, _I, _I, _I, _I, _P, _F, _F, _P, _P]),
+    "pact_ricker_channels": (_I, [_P, _P, _P, _P, _I, _PRING, _F, _I, _F, _F, _P, _P]),
 }
 
 _lib = None
@@ -434,4 +448,136 @@ def nf_sos_to_delays_adjoint(B, params, packed, net: NfNet, v0, centres, g: Geom
         _ptr(scale, F32, "scale", 1), _ptr(out, F32, "dL_dparams", net.n_params), _ptr(act, name="act"),
         act.numel() if act is not None else 0, _ptr(ws, name="ws"), ws.numel(), _stream()),
         "pact_nf_sos_to_delays_adjoint")
+    return out
+
+
+# ---- learned warm start: convolution layers and the training-scan generator ----
+
+def conv3x3_packed_count(ci: int, co: int) -> int:
+    return int(load().pact_conv3x3_packed_count(ci, co))
+
+
+def conv3x3_pack(weights, ci, co, packed=None, packed_adjoint=None, adjoint=True):
+    """weights [co][3][3][ci] float -> (packed [co][K] bf16, packed adjoint [ci][K'] bf16 or None)."""
+    dev = weights.device
+    packed = torch.empty(conv3x3_packed_count(ci, co), dtype=BF16, device=dev) if packed is None else packed
+    if adjoint and packed_adjoint is None:
+        packed_adjoint = torch.empty(conv3x3_packed_count(co, ci), dtype=BF16, device=dev)
+    _check(load().pact_conv3x3_pack(_ptr(weights, F32, "weights", co * 9 * ci), ci, co,
+                                    _ptr(packed, BF16, "packed", conv3x3_packed_count(ci, co)),
+                                    _ptr(packed_adjoint, BF16, "packed_adjoint", conv3x3_packed_count(co, ci)),
+                                    _stream()), "pact_conv3x3_pack")
+    return packed, packed_adjoint
+
+
+def conv3x3(x, packed, co, bias=None, relu=False, mask=None, out=None):
+    """x [n][H][W][ci] bf16 -> [n][H][W][co] bf16."""
+    n, H, W, ci = x.shape
+    out = torch.empty(n, H, W, co, dtype=BF16, device=x.device) if out is None else out
+    _check(load().pact_conv3x3_bf16(_ptr(x, BF16, "x"), n, H, W, ci,
+                                    _ptr(packed, BF16, "packed", conv3x3_packed_count(ci, co)),
+                                    _ptr(bias, F32, "bias", co), co, int(relu),
+                                    _ptr(mask, BF16, "mask", n * H * W * co),
+                                    _ptr(out, BF16, "y", n * H * W * co), _stream()), "pact_conv3x3_bf16")
+    return out
+
+
+def conv3x3_wgrad_workspace_size(n, H, W, ci, co) -> int:
+    return int(load().pact_conv3x3_wgrad_workspace_size(n, H, W, ci, co))
+
+
+def conv3x3_wgrad(x, g, out=None, ws=None):
+    """Weight and bias gradients [co * 9 * ci + co] (float) from input x and output gradient g."""
+    n, H, W, ci = x.shape
+    co = g.shape[3]
+    out = torch.empty(co * 9 * ci + co, dtype=F32, device=x.device) if out is None else out
+    need = conv3x3_wgrad_workspace_size(n, H, W, ci, co)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device) if ws is None else ws
+    _check(load().pact_conv3x3_wgrad_bf16(_ptr(x, BF16, "x"), _ptr(g, BF16, "g", n * H * W * co), n, H, W, ci, co,
+                                          _ptr(out, F32, "grad", co * 9 * ci + co), _ptr(ws, name="ws"), ws.numel(),
+                                          _stream()), "pact_conv3x3_wgrad_bf16")
+    return out
+
+
+def pool2(x, out=None):
+    n, H, W, C = x.shape
+    out = torch.empty(n, H // 2, W // 2, C, dtype=BF16, device=x.device) if out is None else out
+    _check(load().pact_pool2_bf16(_ptr(x, BF16, "x"), n, H, W, C, _ptr(out, BF16, "y", n * (H // 2) * (W // 2) * C),
+                                  _stream()), "pact_pool2_bf16")
+    return out
+
+
+def up2_add(x, skip, out=None):
+    n, H, W, C = skip.shape
+    out = torch.empty_like(skip) if out is None else out
+    _check(load().pact_up2_add_bf16(_ptr(x, BF16, "x", n * (H // 2) * (W // 2) * C), _ptr(skip, BF16, "skip"), n, H,
+                                    W, C, _ptr(out, BF16, "y", n * H * W * C), _stream()), "pact_up2_add_bf16")
+    return out
+
+
+def up2_add_adjoint(g_high, mask_low=None, out=None):
+    n, H, W, C = g_high.shape
+    out = torch.empty(n, H // 2, W // 2, C, dtype=BF16, device=g_high.device) if out is None else out
+    cnt = n * (H // 2) * (W // 2) * C
+    _check(load().pact_up2_add_adjoint_bf16(_ptr(g_high, BF16, "g_high"), _ptr(mask_low, BF16, "mask_low", cnt), n,
+                                            H, W, C, _ptr(out, BF16, "g_low", cnt), _stream()),
+           "pact_up2_add_adjoint_bf16")
+    return out
+
+
+def pool2_adjoint(g_low, skip=None, mask=None, out=None):
+    n, h, w, C = g_low.shape
+    H, W = 2 * h, 2 * w
+    cnt = n * H * W * C
+    out = torch.empty(n, H, W, C, dtype=BF16, device=g_low.device) if out is None else out
+    _check(load().pact_pool2_adjoint_bf16(_ptr(g_low, BF16, "g_low"), _ptr(skip, BF16, "skip", cnt),
+                                          _ptr(mask, BF16, "mask", cnt), n, H, W, C, _ptr(out, BF16, "g_high", cnt),
+                                          _stream()), "pact_pool2_adjoint_bf16")
+    return out
+
+
+def warm_input(stack, factor, scale, channels=16, out=None):
+    """DAS stack [M][H][W] float -> network input [H/f][W/f][channels] bf16."""
+    M, H, W = stack.shape
+    out = torch.empty(H // factor, W // factor, channels, dtype=BF16, device=stack.device) if out is None else out
+    _check(load().pact_warm_input(_ptr(stack, F32, "stack"), M, H, W, factor, scale, channels,
+                                  _ptr(out, BF16, "x", (H // factor) * (W // factor) * channels), _stream()),
+           "pact_warm_input")
+    return out
+
+
+def warm_loss_workspace_size(n, H, W) -> int:
+    return int(load().pact_warm_loss_workspace_size(n, H, W))
+
+
+def warm_loss(z, target, mask, norm, loss=None, g=None, ws=None):
+    n, H, W, C = z.shape
+    dev = z.device
+    loss = torch.empty(1, dtype=F32, device=dev) if loss is None else loss
+    g = torch.empty_like(z) if g is None else g
+    need = warm_loss_workspace_size(n, H, W)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev) if ws is None else ws
+    _check(load().pact_warm_loss(_ptr(z, BF16, "z"), n, H, W, C, _ptr(target, F32, "target", n * H * W),
+                                 _ptr(mask, U8, "mask", H * W), norm, _ptr(loss, F32, "loss", 1),
+                                 _ptr(g, BF16, "g", n * H * W * C), _ptr(ws, name="ws"), ws.numel(), _stream()),
+           "pact_warm_loss")
+    return loss, g
+
+
+def warm_sos(z, mask, v0, scale, out=None):
+    n, H, W, C = z.shape
+    out = torch.empty(n, H, W, dtype=F32, device=z.device) if out is None else out
+    _check(load().pact_warm_sos(_ptr(z, BF16, "z"), n, H, W, C, _ptr(mask, U8, "mask", H * W), v0, scale,
+                                _ptr(out, F32, "sos", n * H * W), _stream()), "pact_warm_sos")
+    return out
+
+
+def ricker_channels(w, sources, amp, sigma, g: Geometry, v0, n_t, fs, t0=0.0, out=None):
+    """Channel data [n_elem][n_t] of Ricker sources with wavefront errors w [n_src][n_elem]."""
+    n_src = sources.shape[0]
+    out = torch.empty(g.n_elem, n_t, dtype=F32, device=w.device) if out is None else out
+    _check(load().pact_ricker_channels(_ptr(w, F32, "w", n_src * g.n_elem), _ptr(sources, F32, "sources", 2 * n_src),
+                                       _ptr(amp, F32, "amp", n_src), _ptr(sigma, F32, "sigma", n_src), n_src, g.ring,
+                                       v0, n_t, fs, t0, _ptr(out, F32, "S", g.n_elem * n_t), _stream()),
+           "pact_ricker_channels")
     return out
