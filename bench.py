@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed for the CPU baseline")
     ap.add_argument("--nf-steps", type=int, default=3, help="neural-field optimisation steps timed (0: skip)")
+    ap.add_argument("--warm-scans", type=int, default=4,
+                    help="held-out scans of the learned warm-start comparison (0: skip)")
     ap.add_argument("--batch-scans", type=int, default=0,
                     help="also time this many independent uneven scans solved together (0: skip)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -253,6 +255,8 @@ def main():
         out["neural_field"] = nf_leg(P, sd, scan, args.nf_steps)
     if args.batch_scans > 0:
         out["batched"] = batch_leg(P, args.batch_scans)
+    if args.warm_scans > 0:
+        out["warm_start"] = warm_leg(P, args.warm_scans)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, inp, args.cpu_steps)
@@ -390,6 +394,109 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
     print(f"[bench] batch: {n_scans} scans x {steps} steps: sequential {out['sequential']['ms']:.1f} ms, "
           f"concurrent {out['concurrent']['ms']:.1f} ms", flush=True)
     return out
+
+
+WARM_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2409_10876_amd", "weights",
+                            "warm_start.safetensors")
+WARM_LEVELS = (1, 1, 2, 2, 4, 2, 1, 1)       # resolution divisor of each convolution's grid
+
+
+def warm_flops(batch, G, real=False):
+    """MFMA flops of one training step of the warm-start network (forward, input gradients of layers 2..8,
+    weight gradients), as executed (K padded to 32) or with the real channel counts (11 inputs, 1 output)."""
+    from paper_2409_10876_amd import warmstart as W
+    kpad = lambda c: (9 * c + 31) // 32 * 32          # noqa: E731
+    tot = 0
+    for l, ((ci, co, _), s) in enumerate(zip(W.ARCH, WARM_LEVELS)):
+        px = batch * (G // s) ** 2
+        if real:
+            ci = 11 if l == 0 else ci
+            co = 1 if l == 7 else co
+            tot += 2 * px * co * 9 * ci * (2 if l == 0 else 3)
+        else:
+            tot += 2 * px * co * kpad(ci) + 2 * px * co * 9 * ci + (2 * px * ci * kpad(co) if l > 0 else 0)
+    return tot
+
+
+def warm_leg(P, n_scans, batch=32, reps=20):
+    """Learned warm start (an addition to the paper's self-supervised method): the committed trained
+    initialiser on held-out scans of the paper-shaped geometry, plain optimisation from v0 against the
+    network's SOS followed by the same steps; the training step and the main convolution kernel against
+    the dense BF16 MFMA peak."""
+    import numpy as np
+    import torch
+    import synth
+    from synth.warm import WARM, phantom_batch
+    from paper_2409_10876_amd import train_warm_start as T, warmstart as W
+    if not os.path.exists(WARM_WEIGHTS):
+        return {"skipped": "no trained weights at paper_2409_10876_amd/weights/warm_start.safetensors"}
+    dev = torch.device("cuda:0")
+    params, scale, meta = W.load_params(WARM_WEIGHTS)
+    scan = synth.PAPER
+    G = scan.sos_n
+    sim = T.make_sim(scan, dev)
+    net = W.WarmStartNet(1, G, G, params=params, n_inputs=scan.M, device=dev)
+    rows = []
+    for i in range(WARM.n_train, WARM.n_train + n_scans):
+        sos, blobs = phantom_batch(scan, [i])
+        rows.append(T.evaluate_scan(net, sim, scan, sos[0], blobs[0], scale, device=dev))
+    summary = T.summarise(rows)
+    curves = {k: np.mean([r[k] for r in rows], axis=0).tolist() for k in ("rmse_curve_plain", "rmse_curve_warm")}
+    # training step and convolution timing at the training batch (synthetic inputs, the trained weights)
+    tnet = W.WarmStartNet(batch, G, G, params=params, n_inputs=scan.M, device=dev)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    x = torch.zeros(batch, G, G, 16)
+    x[..., :scan.M] = torch.randn(batch, G, G, scan.M, generator=g)
+    x = x.to(torch.bfloat16).to(dev)
+    tg = torch.randn(batch, G, G, generator=g).to(dev)
+    mask = torch.from_numpy(synth.free_node_mask(scan)).to(dev)
+    n_free = int(mask.sum())
+    for _ in range(3):
+        tnet.train_step(x, tg, mask, n_free, 1e-4)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        tnet.train_step(x, tg, mask, n_free, 1e-4)
+    b.record()
+    torch.cuda.synchronize()
+    ms_step = a.elapsed_time(b) / reps
+    fl, fl_real = warm_flops(batch, G), warm_flops(batch, G, real=True)
+    # the 64 -> 64 convolution at full resolution (layers 2 and 7), one launch timed on the launch stream
+    conv = lambda: P.pact.conv3x3(tnet.a1, tnet.packed[1][0], 64, bias=tnet.weights(1)[1], relu=True,  # noqa: E731
+                                  out=tnet.a2)
+    conv()
+    a.record()
+    for _ in range(reps):
+        conv()
+    b.record()
+    torch.cuda.synchronize()
+    us_conv = 1e3 * a.elapsed_time(b) / reps
+    conv_flops = 2 * batch * G * G * 64 * 576
+    wg = lambda: P.pact.conv3x3_wgrad(tnet.a1, tnet.gf[2], out=tnet.grad_slice(1), ws=tnet.ws)  # noqa: E731
+    wg()
+    a.record()
+    for _ in range(reps):
+        wg()
+    b.record()
+    torch.cuda.synchronize()
+    us_wg = 1e3 * a.elapsed_time(b) / reps
+    print(f"[bench] warm start: rmse v0 {summary['rmse_v0']:.2f} net {summary['rmse_net']:.2f} plain "
+          f"{summary['rmse_plain']:.2f} m/s; train step {ms_step:.2f} ms; conv 64->64 {us_conv:.1f} us; "
+          f"weight gradient {us_wg:.1f} us", flush=True)
+    return {
+        "held_out_scans": n_scans, "summary": summary, "mean_rmse_curves_per_10_steps": curves,
+        "weights": {k: meta[k] for k in meta}, "network": "8 conv 3x3, 64 channels, 2 poolings, 2 doublings with "
+        "skips; BF16 MFMA, FP32 accumulation; input: 11-delay DAS stack averaged to 140^2",
+        "train_step": {"batch": batch, "ms": ms_step, "mfma_flops_executed": fl, "mfma_flops_real_channels": fl_real,
+                       "tflops_executed": fl / (ms_step * 1e-3) / 1e12, "frac_of_bf16_peak": fl / (ms_step * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS},
+        "conv3x3_64x64": {"kernel": "conv3x3_kernel<64,64>", "shape": f"{batch}x{G}x{G}x64", "us": us_conv,
+                          "tflops": conv_flops / (us_conv * 1e-6) / 1e12,
+                          "frac_of_bf16_peak": conv_flops / (us_conv * 1e-6) / 1e12 / MFMA_BF16_PEAK_TFLOPS},
+        "conv3x3_wgrad_64x64": {"kernel": "conv3x3_wgrad_kernel<64,64> + sum_partials1/2", "us": us_wg,
+                                "tflops": conv_flops / (us_wg * 1e-6) / 1e12,
+                                "frac_of_bf16_peak": conv_flops / (us_wg * 1e-6) / 1e12 / MFMA_BF16_PEAK_TFLOPS},
+    }
 
 
 def nf_leg(P, sd, scan, steps):

@@ -190,6 +190,13 @@ class WarmStartNet:
         self.backward(x, gz)
         return self.loss
 
+    def loss_only(self, x, target, mask, n_free: int):
+        """Forward and the mean squared error (no backward pass)."""
+        n = x.shape[0]
+        z = self.forward(x)
+        pact.warm_loss(z, target, mask, 1.0 / (n * n_free), loss=self.loss, g=self.gz[:n], ws=self.ws_loss)
+        return self.loss
+
     def train_step(self, x, target, mask, n_free: int, lr: float):
         self.loss_grad(x, target, mask, n_free)
         pact.adam_step(self.params, self.m, self.v, self.t, None, self.grad, lr)

@@ -282,3 +282,27 @@ def test_training_steps_reduce_the_loss(lib):
     losses = [float(net.train_step(xd, td, md, H * W, 1e-3)) for _ in range(60)]
     assert np.isfinite(losses).all()
     assert losses[-1] < 0.5 * losses[0], losses[::10]
+
+
+def test_trained_network_gain(lib):
+    # the committed trained initialiser on two held-out scans of the paper-shaped geometry: its SOS is much
+    # closer to the truth than the uniform v0, and at least as close as 500 plain optimisation steps
+    import os
+    import synth
+    from synth.warm import WARM, phantom_batch
+    from paper_2409_10876_amd import train_warm_start as T, warmstart as W
+    path = os.path.join(os.path.dirname(lib.__file__), "weights", "warm_start.safetensors")
+    assert os.path.exists(path), "trained weights missing"
+    announce("trained warm start on 2 held-out scans")
+    params, scale, _ = W.load_params(path)
+    scan = synth.PAPER
+    sim = T.make_sim(scan, "cuda")
+    net = W.WarmStartNet(1, scan.sos_n, scan.sos_n, params=params, n_inputs=scan.M)
+    rows = []
+    for i in (WARM.n_train, WARM.n_train + 1):
+        sos, blobs = phantom_batch(scan, [i])
+        rows.append(T.evaluate_scan(net, sim, scan, sos[0], blobs[0], scale))
+    for r in rows:
+        assert r["rmse_net"] < 0.6 * r["rmse_v0"], r
+        assert r["t_warm_to_rmse_s"] is not None, r          # reaches the plain run's final SOS error
+    assert np.mean([r["rmse_net"] for r in rows]) <= np.mean([r["rmse_plain"] for r in rows])
