@@ -542,7 +542,7 @@ def nf_leg(P, sd, scan, steps):
                                      "achieved": pts * bwd / (us["nf_sos_to_delays_adjoint"] * 1e-6) / 1e12,
                                      "peak": peak, "unit": "TFLOP/s", "alg_flops_per_launch": pts * bwd,
                                      "avg_launch_us": us["nf_sos_to_delays_adjoint"],
-                                     "note": "two passes over the activations stored by the forward pass"},
+                                     "note": "from the activations stored by the forward pass: one kernel for the head and layers 4..2 (writing the layer-1 pre-activation gradients), one for layer 1"},
     }
     for v in roof.values():
         v["frac"] = v["achieved"] / v["peak"]

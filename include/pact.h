@@ -295,7 +295,8 @@ PACT_API int pact_nf_pack(const float* params, int n_freq, int width, unsigned s
  * and w = 0 for rays that miss the disc.  w [N][n_elem].
  * act (optional, DEVICE, pact_nf_activation_bytes() bytes, or NULL): the pass also stores every
  * sample's hidden activations (BF16) and head output, for pact_nf_sos_to_delays_adjoint to use
- * instead of recomputing them (about 1 KB per sample: 23 GB for 169 x 512 rays x 256 samples). */
+ * instead of recomputing them (about 1.3 KB per sample, 29 GB for 169 x 512 rays x 256 samples; the
+ * last 256 bytes per sample are scratch of the adjoint). */
 PACT_API size_t pact_nf_activation_bytes(int N, const pact_ring* ring, int n_samples);
 PACT_API int pact_nf_sos_to_delays(const float* B, const float* params, const unsigned short* packed, int n_freq,
                           int width, float amp, float mask_radius, float v0, const float* centres, int N,
@@ -305,8 +306,9 @@ PACT_API int pact_nf_sos_to_delays(const float* B, const float* params, const un
 /* Adjoint: dL_dparams = scale * sum_{i,n} dL_dw[i][n] dw[i][n]/dparams (same layout as params,
  * overwritten), by backpropagation through the network at every sample of every ray with a
  * nonzero dL_dw.  scale: optional DEVICE scalar (NULL = 1).
- * act: the buffer filled by pact_nf_sos_to_delays with the same inputs (two backward passes read the
- * stored activations), or NULL (four passes recompute the forward activations; same result).
+ * act: the buffer filled by pact_nf_sos_to_delays with the same inputs (the stored activations are read
+ * once; the adjoint writes the layer-1 pre-activation gradients into the buffer's tail and reads them
+ * back), or NULL (four passes recompute the forward activations; same result).
  * ws: DEVICE workspace of pact_nf_sos_to_delays_adjoint_workspace_size() bytes (one partial gradient
  * per CU of the current device, plus 16 for the second level of their sum); not shared by two calls in
  * flight.  Partial gradients are combined
@@ -315,7 +317,7 @@ PACT_API size_t pact_nf_sos_to_delays_adjoint_workspace_size(int n_freq, int wid
 PACT_API int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, const unsigned short* packed,
                                   int n_freq, int width, float amp, float mask_radius, float v0,
                                   const float* centres, int N, const pact_ring* ring, int n_samples,
-                                  const float* dL_dw, const float* scale, float* dL_dparams, const void* act,
+                                  const float* dL_dw, const float* scale, float* dL_dparams, void* act,
                                   size_t act_bytes, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Learned warm start: convolutional SOS initialiser ----

@@ -20,10 +20,10 @@
 // Adjoint.  The pre-activation gradients delta_l are formed chunk by chunk (delta_4 from the head,
 // delta_{l-1} = (W_l^T delta_l) * [h_{l-1} > 0]) and the weight gradients sum delta_l h_{l-1}^T over
 // the chunk's 32 points, one MFMA K step.  Each wave accumulates its rows of dL/dW_l in registers over
-// all the chunks it processes; the registers hold the layers of one pass only, so the adjoint runs four
-// passes (layers 3-4, layer 2, and each half of layer 1's columns), each recomputing the forward
-// activations.  Each workgroup writes
-// its partial gradient once; two small kernels sum the partials in a fixed order.
+// all the chunks it processes.  From activations stored by the forward pass the adjoint runs two kernels
+// (see below); without them it runs four passes that recompute the forward activations (layers 3-4,
+// layer 2, and each half of layer 1's columns), the registers holding the layers of one pass only.
+// Each workgroup writes its partial gradient once; two small kernels sum the partials in a fixed order.
 #include "common.h"
 
 namespace pact {
@@ -502,93 +502,135 @@ __global__ __launch_bounds__(kNT) void nf_bwd_kernel(NfArgs a, const float* __re
     }
 }
 
-// Backward pass from stored activations (written by the forward pass): no forward recompute, so the
-// forward weights need no registers and two passes suffice (layers 2-4 and the head, then layer 1).
-template <int LO>
-struct NfBwdStoredLds {
+// Backward pass from stored activations (written by the forward pass), in two kernels:
+//   A (8 waves, 16 rows each): the head and layers 4, 3, 2 (weight gradients, pre-activation gradients,
+//      biases) from the stored h1..h4 and f; it also writes each chunk's layer-1 pre-activation gradient
+//      delta_1 (BF16, 8 KB per chunk) into the tail of the activation buffer;
+//   B (4 waves, 32 rows each, so that every B fragment read from LDS feeds two MFMAs): the layer-1 weight
+//      gradient delta_1 gamma^T from the stored delta_1 and recomputed features.
+// So the stored activations are read once, and layer 1's accumulators need no registers in A.  The ReLU
+// masks of a chunk are kept as one 32-bit word per feature (bit p: point p is positive), built from the
+// registers that carry the chunk into LDS, so that a lane reads the masks of its four rows in one load.
+constexpr int kWavesS = 4;
+constexpr int kNTS = 64 * kWavesS;
+constexpr int kD1Chunk = kH * kPc;     // stored delta_1 of one chunk, feature-major [128][32]
+
+template <int KS>
+__device__ __forceinline__ void load_rows32(const unsigned short* packed, int off, int ld, bf16x8 (&w)[2][KS]) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    const __bf16* base = reinterpret_cast<const __bf16*>(packed) + off + (32 * wv + r) * ld + 8 * q;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) w[rt][ks] = ld8(base + 16 * rt * ld + 32 * ks);
+}
+
+// Value of lane l ^ 1 (l ^ 2) within groups of four lanes, by DPP quad permutes (no LDS traffic).
+__device__ __forceinline__ unsigned quad_xor1(unsigned v) {
+    return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ unsigned quad_xor2(unsigned v) {
+    return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_sum(float v) {
+    v += __int_as_float(static_cast<int>(quad_xor1(static_cast<unsigned>(__float_as_int(v)))));
+    v += __int_as_float(static_cast<int>(quad_xor2(static_cast<unsigned>(__float_as_int(v)))));
+    return v;
+}
+
+struct NfBwdALds {
     NfTables tab;
-    float df[kPc];
-    alignas(16) __bf16 feat[LO == 1 ? kPc * kLd1 : 8];
-    alignas(16) __bf16 featT[LO == 1 ? kK1 * kLdT : 8];
+    alignas(16) float df[kPc];
+    alignas(16) unsigned on[4][kH];           // bit p of on[l][row]: h_{l+1}[row][p] > 0
     alignas(16) __bf16 hT[4][kH * kLdT];      // h1..h4 of the chunk, feature-major
-    alignas(16) __bf16 dP[2][kPc * kLdH];     // delta, point-major (dgrad operand)
+    alignas(16) __bf16 dP[2][kPc * kLdH];     // delta, point-major (input-gradient operand)
     alignas(16) __bf16 dT[2][kH * kLdT];      // delta, feature-major (weight-gradient operand)
 };
 
-template <int L, int LO, int HI, int NG>
-__device__ __forceinline__ void nf_level_stored(NfBwdStoredLds<LO>& sm, const bf16x8 (&tw)[4], f32x4 (&gl)[NG],
-                                                float (&gb)[4][4], int cur) {
+// Level L (4, 3 or 2) of pass A for one chunk, delta_L in buffer `cur`: dW_L += delta_L h_{L-1}^T over the
+// chunk's 32 points, and delta_{L-1} = (W_L^T delta_L) [h_{L-1} > 0] into the other buffer (its bias
+// gradient into gb).  Ends with a barrier.
+template <int L>
+__device__ __forceinline__ void nf_level_a(NfBwdALds& sm, const bf16x8 (&tw)[4], f32x4 (&gl)[8], float (&gb)[4],
+                                           int cur) {
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
     const int row0 = 16 * wv + 4 * q;
-    if (L >= LO && L <= HI) {
-        const bf16x8 da = ld8(sm.dT[cur] + (16 * wv + r16) * kLdT + 8 * q);
-        const __bf16* hT = L == 1 ? sm.featT : sm.hT[L >= 2 ? L - 2 : 0];
+    const __bf16* hprev = sm.hT[L - 2];
+    const bf16x8 da = ld8(sm.dT[cur] + (16 * wv + r16) * kLdT + 8 * q);
 #pragma unroll
-        for (int kt = 0; kt < NG; ++kt) gl[kt] = mfma(da, ld8(hT + (16 * kt + r16) * kLdT + 8 * q), gl[kt]);
-    }
-    if (L > LO) {
-        f32x4 d2[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
+    for (int kt = 0; kt < 8; ++kt) gl[kt] = mfma(da, ld8(hprev + (16 * kt + r16) * kLdT + 8 * q), gl[kt]);
+    const uint4 on = *reinterpret_cast<const uint4*>(&sm.on[L - 2][row0]);
+    f32x4 d2[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            d2[0] = mfma(tw[ks], ld8(sm.dP[cur] + r16 * kLdH + 32 * ks + 8 * q), d2[0]);
-            d2[1] = mfma(tw[ks], ld8(sm.dP[cur] + (16 + r16) * kLdH + 32 * ks + 8 * q), d2[1]);
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+            d2[nt] = mfma(tw[ks], ld8(sm.dP[cur] + (16 * nt + r16) * kLdH + 32 * ks + 8 * q), d2[nt]);
+    const unsigned onw[4] = {on.x, on.y, on.z, on.w};
+    const int nxt = cur ^ 1;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int p = 16 * nt + r16;
+        bf16x4 dv;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            dv[i] = static_cast<__bf16>((onw[i] >> p) & 1u ? d2[nt][i] : 0.0f);
+            gb[i] += static_cast<float>(dv[i]);
+            sm.dT[nxt][(row0 + i) * kLdT + p] = dv[i];
         }
-        const int nxt = cur ^ 1;
-        const __bf16* hprev = sm.hT[L >= 2 ? L - 2 : 0];
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const int p = 16 * nt + r16;
-            bf16x4 dv;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float hv = static_cast<float>(hprev[(row0 + i) * kLdT + p]);
-                dv[i] = static_cast<__bf16>(hv > 0.0f ? d2[nt][i] : 0.0f);
-                gb[L >= 2 ? L - 2 : 0][i] += static_cast<float>(dv[i]);
-                sm.dT[nxt][(row0 + i) * kLdT + p] = dv[i];
-            }
-            *reinterpret_cast<bf16x4*>(sm.dP[nxt] + p * kLdH + row0) = dv;
-        }
+        if (L > 2) *reinterpret_cast<bf16x4*>(sm.dP[nxt] + p * kLdH + row0) = dv;
     }
     __syncthreads();
 }
 
-template <int LO, int HI>
-__global__ __launch_bounds__(kNT) void nf_bwd_stored_kernel(NfArgs a, const __bf16* __restrict__ act,
-                                                            const float* __restrict__ f_in,
-                                                            const float* __restrict__ dL_dw,
-                                                            const float* __restrict__ scale,
-                                                            float* __restrict__ partial) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char nf_dyn[];
-    NfBwdStoredLds<LO>& sm = *reinterpret_cast<NfBwdStoredLds<LO>*>(nf_dyn);
+// Rows 32 wv + 16 rt + 4 q + i of a weight gradient (tiles of 16 columns) into this workgroup's partial.
+template <int NT>
+__device__ __forceinline__ void put_rows32(float* out, int off, int ld, const f32x4 (&gl)[2][NT]) {
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[off + (32 * wv + 16 * rt + 4 * q + i) * ld + 16 * kt + r16] = gl[rt][kt][i];
+}
+
+__global__ __launch_bounds__(kNT) void nf_bwd_a_kernel(NfArgs a, const __bf16* __restrict__ act,
+                                                       const float* __restrict__ f_in, __bf16* __restrict__ d1,
+                                                       const float* __restrict__ dL_dw,
+                                                       const float* __restrict__ scale, float* __restrict__ partial) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char nf_dyn[];
+    NfBwdALds& sm = *reinterpret_cast<NfBwdALds*>(nf_dyn);
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
+    const int row0 = 16 * wv + 4 * q;
     load_tables(a, sm.tab);
     bf16x8 t2[4], t3[4], t4[4];
     load_rows<4>(a.packed, kOffT4, kH, t4);
     load_rows<4>(a.packed, kOffT3, kH, t3);
-    if (LO < 2) load_rows<4>(a.packed, kOffT2, kH, t2);
-    f32x4 g1[LO == 1 ? 16 : 1], g2[HI >= 2 && LO <= 2 ? 8 : 1], g3[HI >= 3 && LO <= 3 ? 8 : 1],
-        g4[HI == 4 ? 8 : 1];
-    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (auto& x : g1) x = zero;
-    for (auto& x : g2) x = zero;
-    for (auto& x : g3) x = zero;
-    for (auto& x : g4) x = zero;
-    float gb[4][4] = {};
-    float gw5[4] = {}, gb5 = 0.0f;
+    load_rows<4>(a.packed, kOffT2, kH, t2);
+    f32x4 g2[8], g3[8], g4[8];
+#pragma unroll
+    for (int kt = 0; kt < 8; ++kt) {
+        g2[kt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        g3[kt] = g2[kt];
+        g4[kt] = g2[kt];
+    }
+    float gb[4][4] = {};                      // bias gradients of layers 1..4, rows row0 + i
+    float gw5 = 0.0f, gb5 = 0.0f;             // w5 gradient of feature t / 4 (partial over its 8 points)
     const float sc = scale ? *scale : 1.0f;
     __syncthreads();
 
     const int n_rays = a.N * a.n_elem;
     const int n_chunks = (a.Ns + kPc - 1) / kPc;
-    const int row0 = 16 * wv + 4 * q;
+    // stored blocks move through registers: thread t carries points 8 (t % 4) .. + 7 of feature t / 4 of
+    // each layer, 16 bytes; the next chunk's loads are issued before this chunk's work (barriers wait on
+    // LDS only)
+    const int feature = threadIdx.x >> 2, part = threadIdx.x & 3;
     for (int ray = blockIdx.x; ray < n_rays; ray += gridDim.x) {
         const float g = dL_dw[ray] * sc;
         if (g == 0.0f) continue;
         const NfRay r = nf_ray(a, ray);
         if (r.dl == 0.0f) continue;
-        // the chunk's stored activations come through registers: the next chunk's loads are issued before
-        // this chunk's work, so their HBM latency hides behind it (barriers wait on LDS only)
-        const int feature = threadIdx.x >> 2, part = threadIdx.x & 3;
         bf16x8 nxt[4];
         float fnxt = 0.0f;
         {
@@ -602,7 +644,17 @@ __global__ __launch_bounds__(kNT) void nf_bwd_stored_kernel(NfArgs a, const __bf
             const int s0 = ch * kPc;
             const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
 #pragma unroll
-            for (int L = 0; L < 4; ++L) *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) = nxt[L];
+            for (int L = 0; L < 4; ++L) {
+                *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) = nxt[L];
+                // ReLU bits of the feature's 32 points, gathered from the 4 threads that hold them
+                unsigned bits = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bits |= (static_cast<float>(nxt[L][j]) > 0.0f ? 1u : 0u) << j;
+                bits <<= 8 * part;
+                bits |= quad_xor1(bits);
+                bits |= quad_xor2(bits);
+                if (part == 0) sm.on[L][feature] = bits;
+            }
             const float fcur = fnxt;
             if (ch + 1 < n_chunks) {
                 const __bf16* src = act + (chunk + 1) * kActChunk;
@@ -615,73 +667,155 @@ __global__ __launch_bounds__(kNT) void nf_bwd_stored_kernel(NfArgs a, const __bf
                 if (s0 + static_cast<int>(threadIdx.x) < a.Ns) {
                     const float th = tanhf(fcur);
                     const float v = a.v0 + a.amp * th;
-                    d = g * r.dl * a.v0 * a.amp * (1.0f - th * th) / (v * v);
+                    d = g * r.dl * a.v0 * a.amp * (1.0f - th * th) / (v * v);   // d w / d f, times dL/dw
                 }
                 sm.df[threadIdx.x] = d;
             }
-            if (LO == 1) nf_features(a, r, s0, sm.tab.B, sm.feat, sm.featT);
             __syncthreads();
-            // delta_4 = df w5 [h4 > 0]
+            // w5 gradient: sum over the chunk's points of df h4, 8 points per thread
+            {
+                const float4 dA = *reinterpret_cast<const float4*>(sm.df + 8 * part);
+                const float4 dB = *reinterpret_cast<const float4*>(sm.df + 8 * part + 4);
+                const float dfv[8] = {dA.x, dA.y, dA.z, dA.w, dB.x, dB.y, dB.z, dB.w};
+                const bf16x8 hv = ld8(sm.hT[3] + feature * kLdT + 8 * part);
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const int p = 16 * nt + r16;
-                const float dfp = sm.df[p];
-                bf16x4 dv;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float h4 = static_cast<float>(sm.hT[3][(row0 + i) * kLdT + p]);
-                    if (HI == 4) gw5[i] = fmaf(dfp, h4, gw5[i]);
-                    dv[i] = static_cast<__bf16>(h4 > 0.0f ? dfp * sm.tab.w5[row0 + i] : 0.0f);
-                    gb[3][i] += static_cast<float>(dv[i]);
-                    sm.dT[0][(row0 + i) * kLdT + p] = dv[i];
-                }
-                *reinterpret_cast<bf16x4*>(sm.dP[0] + p * kLdH + row0) = dv;
+                for (int j = 0; j < 8; ++j) gw5 = fmaf(dfv[j], static_cast<float>(hv[j]), gw5);
             }
-            if (HI == 4 && threadIdx.x < kPc) gb5 += sm.df[threadIdx.x];
+            // delta_4 = df w5 [h4 > 0]
+            {
+                const uint4 on = *reinterpret_cast<const uint4*>(&sm.on[3][row0]);
+                const unsigned onw[4] = {on.x, on.y, on.z, on.w};
+                const float4 w5v = *reinterpret_cast<const float4*>(&sm.tab.w5[row0]);
+                const float w5r[4] = {w5v.x, w5v.y, w5v.z, w5v.w};
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const int p = 16 * nt + r16;
+                    const float dfp = sm.df[p];
+                    bf16x4 dv;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        dv[i] = static_cast<__bf16>((onw[i] >> p) & 1u ? dfp * w5r[i] : 0.0f);
+                        gb[3][i] += static_cast<float>(dv[i]);
+                        sm.dT[0][(row0 + i) * kLdT + p] = dv[i];
+                    }
+                    *reinterpret_cast<bf16x4*>(sm.dP[0] + p * kLdH + row0) = dv;
+                }
+            }
+            if (threadIdx.x < kPc) gb5 += sm.df[threadIdx.x];
             __syncthreads();
-            nf_level_stored<4, LO, HI, HI == 4 ? 8 : 1>(sm, t4, g4, gb, 0);
-            if (LO <= 3) nf_level_stored<3, LO, HI, (LO <= 3 && HI >= 3) ? 8 : 1>(sm, t3, g3, gb, 1);
-            if (LO <= 2) nf_level_stored<2, LO, HI, (LO <= 2 && HI >= 2) ? 8 : 1>(sm, t2, g2, gb, 0);
-            if (LO <= 1) nf_level_stored<1, LO, HI, LO == 1 ? 16 : 1>(sm, t2, g1, gb, 1);
+            nf_level_a<4>(sm, t4, g4, gb[2], 0);
+            nf_level_a<3>(sm, t3, g3, gb[1], 1);
+            nf_level_a<2>(sm, t2, g2, gb[0], 0);
+            // delta_1 (in dT[1]) of the chunk to the buffer; the next chunk rewrites dT[1] only after two
+            // barriers
+            *reinterpret_cast<bf16x8*>(d1 + chunk * kD1Chunk + feature * kPc + 8 * part) =
+                ld8(sm.dT[1] + feature * kLdT + 8 * part);
         }
     }
 
     float* out = partial + static_cast<size_t>(blockIdx.x) * kNParams;
-    auto put_w = [&](int L, const f32x4* gl, int tiles, int ld) {
-        for (int kt = 0; kt < tiles; ++kt)
+    auto put_w = [&](int off, const f32x4 (&gl)[8]) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) out[param_w(L) + (row0 + i) * ld + 16 * kt + r16] = gl[kt][i];
+        for (int kt = 0; kt < 8; ++kt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[off + (row0 + i) * kH + 16 * kt + r16] = gl[kt][i];
     };
-    if (LO == 1) put_w(1, g1, 16, kK1);
-    if (LO <= 2 && HI >= 2) put_w(2, g2, 8, kH);
-    if (LO <= 3 && HI >= 3) put_w(3, g3, 8, kH);
-    if (HI == 4) put_w(4, g4, 8, kH);
+    put_w(kPW2, g2);
+    put_w(kPW3, g3);
+    put_w(kPW4, g4);
 #pragma unroll
-    for (int L = 1; L <= 4; ++L) {
-        if (L < LO || L > HI) continue;
+    for (int L = 1; L <= 4; ++L)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float s = gb[L - 1][i];
+            float v = gb[L - 1][i];
 #pragma unroll
-            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-            if (r16 == 0) out[param_b(L) + row0 + i] = s;
+            for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+            if (r16 == 0) out[param_b(L) + row0 + i] = v;
+        }
+    const float w5s = quad_sum(gw5);
+    if (part == 0) out[kPw5 + feature] = w5s;
+    // b5: the first 32 threads hold per-point sums over the rays
+    if (threadIdx.x < 64) {
+        float v = gb5;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (threadIdx.x == 0) out[kPb5] = v;
+    }
+}
+
+// Fourier features of a chunk, feature-major only, with 256 threads: thread t takes point t % 32 and
+// frequencies 16 (t / 32) .. + 15 (the same arithmetic as nf_features).
+__device__ __forceinline__ void nf_features_t256(const NfRay& r, int s0, const float* Bs, __bf16* featT) {
+    const int p = threadIdx.x & (kPc - 1);
+    const int k0 = (threadIdx.x >> 5) * 16;
+    const float t = fmaf(static_cast<float>(s0 + p) + 0.5f, r.dl, r.ta);
+    const float px = fmaf(t, r.ux, r.cx), py = fmaf(t, r.uy, r.cy);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        float ph = fmaf(Bs[2 * (k0 + j)], px, Bs[2 * (k0 + j) + 1] * py);
+        ph -= rintf(ph);
+        featT[(k0 + j) * kLdT + p] = static_cast<__bf16>(__builtin_amdgcn_cosf(ph));
+        featT[(kF + k0 + j) * kLdT + p] = static_cast<__bf16>(__builtin_amdgcn_sinf(ph));
+    }
+}
+
+struct NfBwdBLds {
+    float B[2 * kF];
+    alignas(16) __bf16 featT[kK1 * kLdT];     // the chunk's features, feature-major
+    alignas(16) __bf16 dT[kH * kLdT];         // the chunk's delta_1, feature-major
+};
+
+__global__ __launch_bounds__(kNTS) void nf_bwd_b_kernel(NfArgs a, const __bf16* __restrict__ d1,
+                                                        const float* __restrict__ dL_dw,
+                                                        const float* __restrict__ scale, float* __restrict__ partial) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char nf_dyn[];
+    NfBwdBLds& sm = *reinterpret_cast<NfBwdBLds*>(nf_dyn);
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
+    for (int k = threadIdx.x; k < 2 * kF; k += blockDim.x) sm.B[k] = a.B[k];
+    f32x4 g1[2][16];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int kt = 0; kt < 16; ++kt) g1[rt][kt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const float sc = scale ? *scale : 1.0f;
+    const int n_rays = a.N * a.n_elem;
+    const int n_chunks = (a.Ns + kPc - 1) / kPc;
+    const int feature = threadIdx.x >> 2, part = threadIdx.x & 3;
+    for (int ray = blockIdx.x; ray < n_rays; ray += gridDim.x) {
+        if (dL_dw[ray] * sc == 0.0f) continue;               // the rays pass A skipped
+        const NfRay r = nf_ray(a, ray);
+        if (r.dl == 0.0f) continue;
+        bf16x8 nxt[2];
+        {
+            const __bf16* src = d1 + static_cast<size_t>(ray) * n_chunks * kD1Chunk;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) nxt[h] = ld8(src + (feature + 64 * h) * kPc + 8 * part);
+        }
+        for (int ch = 0; ch < n_chunks; ++ch) {
+            const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
+            __syncthreads();                                  // the previous chunk's fragments are read
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                *reinterpret_cast<bf16x8*>(sm.dT + (feature + 64 * h) * kLdT + 8 * part) = nxt[h];
+            if (ch + 1 < n_chunks) {
+                const __bf16* src = d1 + (chunk + 1) * kD1Chunk;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) nxt[h] = ld8(src + (feature + 64 * h) * kPc + 8 * part);
+            }
+            nf_features_t256(r, ch * kPc, sm.B, sm.featT);
+            __syncthreads();
+            bf16x8 da[2];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) da[rt] = ld8(sm.dT + (32 * wv + 16 * rt + r16) * kLdT + 8 * q);
+#pragma unroll
+            for (int kt = 0; kt < 16; ++kt) {
+                const bf16x8 fb = ld8(sm.featT + (16 * kt + r16) * kLdT + 8 * q);
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) g1[rt][kt] = mfma(da[rt], fb, g1[rt][kt]);
+            }
         }
     }
-    if (HI == 4) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float s = gw5[i];
-#pragma unroll
-            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-            if (r16 == 0) out[kPw5 + row0 + i] = s;
-        }
-        float s = threadIdx.x < 64 ? gb5 : 0.0f;
-        if (threadIdx.x < 64) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-            if (threadIdx.x == 0) out[kPb5] = s;
-        }
-    }
+    put_rows32<16>(partial + static_cast<size_t>(blockIdx.x) * kNParams, kPW1, kK1, g1);
 }
 
 // dL/dparams[j] = sum over workgroups of partial[b][j] in a fixed order, in two levels (kSlices contiguous
@@ -790,23 +924,31 @@ int launch_bwd(const NfArgs& a, const float* dL_dw, const float* scale, float* p
     return launch_status("pact_nf_sos_to_delays_adjoint");
 }
 
-template <int LO, int HI>
-int launch_bwd_stored(const NfArgs& a, const __bf16* act, const float* f_in, const float* dL_dw, const float* scale,
-                      float* partial, int blocks, hipStream_t st) {
+template <typename K>
+void set_lds_attr(K kernel, size_t lds) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(lds));
+}
+
+int launch_bwd_stored(const NfArgs& a, const __bf16* act, const float* f_in, __bf16* d1, const float* dL_dw,
+                      const float* scale, float* partial, int blocks, hipStream_t st) {
     static bool attr = false;
-    const size_t lds = sizeof(NfBwdStoredLds<LO>);
     if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(nf_bwd_stored_kernel<LO, HI>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        set_lds_attr(nf_bwd_a_kernel, sizeof(NfBwdALds));
+        set_lds_attr(nf_bwd_b_kernel, sizeof(NfBwdBLds));
         attr = true;
     }
-    nf_bwd_stored_kernel<LO, HI><<<blocks, kNT, lds, st>>>(a, act, f_in, dL_dw, scale, partial);
+    nf_bwd_a_kernel<<<blocks, kNT, sizeof(NfBwdALds), st>>>(a, act, f_in, d1, dL_dw, scale, partial);
+    if (int s = launch_status("pact_nf_sos_to_delays_adjoint")) return s;
+    nf_bwd_b_kernel<<<blocks, kNTS, sizeof(NfBwdBLds), st>>>(a, d1, dL_dw, scale, partial);
     return launch_status("pact_nf_sos_to_delays_adjoint");
 }
 
+// Activation buffer: h1..h4 [chunks][4][128][32] BF16, then f [chunks][32] FP32, then the adjoint's
+// delta_1 [chunks][128][32] BF16.
 size_t nf_activation_bytes(long long n_rays, int n_samples) {
     const long long chunks = n_rays * ((n_samples + kPc - 1) / kPc);
-    return static_cast<size_t>(chunks) * (kActChunk * sizeof(__bf16) + kPc * sizeof(float));
+    return static_cast<size_t>(chunks) * (kActChunk * sizeof(__bf16) + kPc * sizeof(float) + kD1Chunk * sizeof(__bf16));
 }
 
 }  // namespace
@@ -875,7 +1017,7 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
                                              int n_freq, int width, float amp, float mask_radius, float v0,
                                              const float* centres, int N, const pact_ring* ring, int n_samples,
                                              const float* dL_dw, const float* scale, float* dL_dparams,
-                                             const void* act, size_t act_bytes, void* ws, size_t ws_bytes,
+                                             void* act, size_t act_bytes, void* ws, size_t ws_bytes,
                                              void* stream) {
     using namespace pact;
     clear_error();
@@ -901,11 +1043,11 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
             return PACT_EWORKSPACE;
         }
         const size_t chunks = static_cast<size_t>(n_rays) * ((n_samples + kPc - 1) / kPc);
-        const __bf16* act_h = static_cast<const __bf16*>(act);
+        __bf16* act_h = static_cast<__bf16*>(act);
         const float* act_f = reinterpret_cast<const float*>(act_h + chunks * kActChunk);
-        // two passes from the stored activations: layers 2-4 and the head, then layer 1
-        if (int s = launch_bwd_stored<2, 4>(a, act_h, act_f, dL_dw, scale, partial, blocks, st)) return s;
-        if (int s = launch_bwd_stored<1, 1>(a, act_h, act_f, dL_dw, scale, partial, blocks, st)) return s;
+        __bf16* d1 = reinterpret_cast<__bf16*>(const_cast<float*>(act_f) + chunks * kPc);
+        // from the stored activations: the head and layers 4..2 (writing delta_1), then layer 1
+        if (int s = launch_bwd_stored(a, act_h, act_f, d1, dL_dw, scale, partial, blocks, st)) return s;
         return launch_nf_reduce(partial, blocks, dL_dparams, st);
     }
     // four passes, each recomputing the forward activations: layers 3-4 (and the head), layer 2, and the
