@@ -216,6 +216,17 @@ __device__ __forceinline__ void load_rows(const unsigned short* packed, int off,
     for (int ks = 0; ks < KS; ++ks) w[ks] = ld8(base + 32 * ks);
 }
 
+// The same for waves of 32 rows (two row tiles): rows 32 wv + 16 rt + r.
+template <int KS>
+__device__ __forceinline__ void load_rows32(const unsigned short* packed, int off, int ld, bf16x8 (&w)[2][KS]) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    const __bf16* base = reinterpret_cast<const __bf16*>(packed) + off + (32 * wv + r) * ld + 8 * q;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) w[rt][ks] = ld8(base + 16 * rt * ld + 32 * ks);
+}
+
 // Small per-workgroup tables in LDS: B, biases b1..b4, w5 (the BF16 value), b5.
 struct NfTables {
     float B[2 * kF];
@@ -244,21 +255,130 @@ struct NfFwdLds {
 // Stored activations of one chunk: h1..h4 feature-major, [4][128][32] BF16 (32 KB), chunk = ray * n_chunks + ch.
 constexpr int kActChunk = 4 * kH * kPc;
 
-// Copy a feature-major LDS block [128][kLdT] (the chunk's 32 points of each feature) to its stored block.
-__device__ __forceinline__ void nf_store_layer(const __bf16* hT, __bf16* dst) {
-    const int feature = threadIdx.x >> 2, part = threadIdx.x & 3;   // 512 threads x 16 bytes = 8 KB
-    *reinterpret_cast<bf16x8*>(dst + feature * kPc + 8 * part) = ld8(hT + feature * kLdT + 8 * part);
+
+// ---- forward pass: 4 waves of 32 rows (two MFMA row tiles per B fragment read from LDS) ----
+constexpr int kWF = 4;
+constexpr int kNTF = 64 * kWF;
+
+// Fourier features of the chunk's points into LDS, point-major, with 256 threads: thread t takes point
+// t % 32 and frequencies 16 (t / 32) .. + 15 (the arithmetic of nf_features).
+__device__ __forceinline__ void nf_features_p256(const NfRay& r, int s0, const float* Bs, __bf16* feat) {
+    const int p = threadIdx.x & (kPc - 1);
+    const int k0 = (threadIdx.x >> 5) * 16;
+    const float t = fmaf(static_cast<float>(s0 + p) + 0.5f, r.dl, r.ta);
+    const float px = fmaf(t, r.ux, r.cx), py = fmaf(t, r.uy, r.cy);
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        bf16x8 c8, s8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k0 + 8 * hh + j;
+            float ph = fmaf(Bs[2 * k], px, Bs[2 * k + 1] * py);
+            ph -= rintf(ph);
+            c8[j] = static_cast<__bf16>(__builtin_amdgcn_cosf(ph));
+            s8[j] = static_cast<__bf16>(__builtin_amdgcn_sinf(ph));
+        }
+        *reinterpret_cast<bf16x8*>(feat + p * kLd1 + k0 + 8 * hh) = c8;
+        *reinterpret_cast<bf16x8*>(feat + p * kLd1 + kF + k0 + 8 * hh) = s8;
+    }
 }
 
-__global__ __launch_bounds__(kNT) void nf_fwd_kernel(NfArgs a, float* __restrict__ w_out, __bf16* __restrict__ act,
-                                                     float* __restrict__ f_out) {
+// One dense layer for the wave's 32 rows and the chunk's 32 points: acc[rt][nt] = rows 32 wv + 16 rt ..,
+// points 16 nt ..; each B fragment feeds both row tiles.
+template <int KS>
+__device__ __forceinline__ void nf_layer2(const bf16x8 (&w)[2][KS], const __bf16* in, int ld, f32x4 (&acc)[2][2]) {
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) acc[rt][0] = acc[rt][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8 b0 = ld8(in + r * ld + 32 * ks + 8 * q);
+        const bf16x8 b1 = ld8(in + (16 + r) * ld + 32 * ks + 8 * q);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            acc[rt][0] = mfma(w[rt][ks], b0, acc[rt][0]);
+            acc[rt][1] = mfma(w[rt][ks], b1, acc[rt][1]);
+        }
+    }
+}
+
+// bias + relu + BF16, point-major (and feature-major if outT); h keeps the BF16 values as floats.
+__device__ __forceinline__ void nf_activate2(const f32x4 (&acc)[2][2], const float* bias, __bf16* out, __bf16* outT,
+                                             float (&h)[2][2][4]) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const int row0 = 32 * wv + 16 * rt + 4 * q;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            bf16x4 v;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = static_cast<__bf16>(fmaxf(acc[rt][nt][i] + bias[row0 + i], 0.0f));
+                h[rt][nt][i] = static_cast<float>(v[i]);
+            }
+            const int p = 16 * nt + r;
+            *reinterpret_cast<bf16x4*>(out + p * kLdH + row0) = v;
+            if (outT) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) outT[(row0 + i) * kLdT + p] = v[i];
+            }
+        }
+    }
+}
+
+// Head partials per 16-row tile (slot 2 wv + rt, the same slots and sums as 16-row waves).
+__device__ __forceinline__ void nf_head_partial2(const float (&h4)[2][2][4], const float* w5, float* headp) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const int row0 = 32 * wv + 16 * rt + 4 * q;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            float s = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s = fmaf(w5[row0 + i], h4[rt][nt][i], s);
+            s += __shfl_xor(s, 16, 64);
+            s += __shfl_xor(s, 32, 64);
+            if (q == 0) headp[(2 * wv + rt) * kPc + 16 * nt + r] = s;
+        }
+    }
+}
+
+// ReLU masks of a stored layer for the adjoint: one 32-bit word per row of the chunk (bit p: point p is
+// positive), from two wave ballots per row (lane r + 16 q holds rows .. + 4 q + i of point r of each N tile).
+__device__ __forceinline__ void nf_store_on2(const float (&h)[2][2][4], unsigned* words) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const unsigned long long b0 = __ballot(h[rt][0][i] > 0.0f);
+            const unsigned long long b1 = __ballot(h[rt][1][i] > 0.0f);
+            if (r == i)
+                words[32 * wv + 16 * rt + 4 * q + i] = static_cast<unsigned>((b0 >> (16 * q)) & 0xFFFFull) |
+                                                       (static_cast<unsigned>((b1 >> (16 * q)) & 0xFFFFull) << 16);
+        }
+}
+
+// Copy a feature-major LDS block [128][kLdT] to its stored block, 256 threads x 2 x 16 bytes.
+__device__ __forceinline__ void nf_store_layer256(const __bf16* hT, __bf16* dst) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int idx = threadIdx.x + kNTF * k, feature = idx >> 2, part = idx & 3;
+        *reinterpret_cast<bf16x8*>(dst + feature * kPc + 8 * part) = ld8(hT + feature * kLdT + 8 * part);
+    }
+}
+
+__global__ __launch_bounds__(kNTF, 2) void nf_fwd_kernel(NfArgs a, float* __restrict__ w_out, __bf16* __restrict__ act,
+                                                      float* __restrict__ f_out, unsigned* __restrict__ on_out) {
     __shared__ NfFwdLds sm;
     load_tables(a, sm.tab);
-    bf16x8 w1[8], w2[4], w3[4], w4[4];
-    load_rows<8>(a.packed, kOffW1, kK1, w1);
-    load_rows<4>(a.packed, kOffW2, kH, w2);
-    load_rows<4>(a.packed, kOffW3, kH, w3);
-    load_rows<4>(a.packed, kOffW4, kH, w4);
+    bf16x8 w1[2][8], w2[2][4], w3[2][4], w4[2][4];
+    load_rows32<8>(a.packed, kOffW1, kK1, w1);
+    load_rows32<4>(a.packed, kOffW2, kH, w2);
+    load_rows32<4>(a.packed, kOffW3, kH, w3);
+    load_rows32<4>(a.packed, kOffW4, kH, w4);
     __syncthreads();
     const int n_rays = a.N * a.n_elem;
     const int n_chunks = (a.Ns + kPc - 1) / kPc;
@@ -273,27 +393,32 @@ __global__ __launch_bounds__(kNT) void nf_fwd_kernel(NfArgs a, float* __restrict
             const int s0 = ch * kPc;
             const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
             __bf16* dst = act ? act + chunk * kActChunk : nullptr;
-            nf_features(a, r, s0, sm.tab.B, sm.feat, nullptr);
+            unsigned* on = dst ? on_out + chunk * 4 * kH : nullptr;
+            nf_features_p256(r, s0, sm.tab.B, sm.feat);
             __syncthreads();
-            f32x4 acc[2];
-            float h[2][4];
-            nf_layer<8>(w1, sm.feat, kLd1, acc);
-            nf_activate(acc, sm.tab.bias[0], sm.hA, dst ? sm.hT[0] : nullptr, h);
+            f32x4 acc[2][2];
+            float h[2][2][4];
+            nf_layer2<8>(w1, sm.feat, kLd1, acc);
+            nf_activate2(acc, sm.tab.bias[0], sm.hA, dst ? sm.hT[0] : nullptr, h);
+            if (on) nf_store_on2(h, on);
             __syncthreads();
-            if (dst) nf_store_layer(sm.hT[0], dst);
-            nf_layer<4>(w2, sm.hA, kLdH, acc);
-            nf_activate(acc, sm.tab.bias[1], sm.hB, dst ? sm.hT[1] : nullptr, h);
+            if (dst) nf_store_layer256(sm.hT[0], dst);
+            nf_layer2<4>(w2, sm.hA, kLdH, acc);
+            nf_activate2(acc, sm.tab.bias[1], sm.hB, dst ? sm.hT[1] : nullptr, h);
+            if (on) nf_store_on2(h, on + kH);
             __syncthreads();
-            if (dst) nf_store_layer(sm.hT[1], dst + kH * kPc);
-            nf_layer<4>(w3, sm.hB, kLdH, acc);
-            nf_activate(acc, sm.tab.bias[2], sm.hA, dst ? sm.hT[0] : nullptr, h);
+            if (dst) nf_store_layer256(sm.hT[1], dst + kH * kPc);
+            nf_layer2<4>(w3, sm.hB, kLdH, acc);
+            nf_activate2(acc, sm.tab.bias[2], sm.hA, dst ? sm.hT[0] : nullptr, h);
+            if (on) nf_store_on2(h, on + 2 * kH);
             __syncthreads();
-            if (dst) nf_store_layer(sm.hT[0], dst + 2 * kH * kPc);
-            nf_layer<4>(w4, sm.hA, kLdH, acc);
-            nf_activate(acc, sm.tab.bias[3], sm.hB, dst ? sm.hT[1] : nullptr, h);
-            nf_head_partial(h, sm.tab.w5, sm.headp);
+            if (dst) nf_store_layer256(sm.hT[0], dst + 2 * kH * kPc);
+            nf_layer2<4>(w4, sm.hA, kLdH, acc);
+            nf_activate2(acc, sm.tab.bias[3], sm.hB, dst ? sm.hT[1] : nullptr, h);
+            if (on) nf_store_on2(h, on + 3 * kH);
+            nf_head_partial2(h, sm.tab.w5, sm.headp);
             __syncthreads();
-            if (dst) nf_store_layer(sm.hT[1], dst + 3 * kH * kPc);
+            if (dst) nf_store_layer256(sm.hT[1], dst + 3 * kH * kPc);
             if (threadIdx.x < kPc) {
                 const float f = nf_head_sum(sm.headp, threadIdx.x, sm.tab.b5);
                 if (f_out) f_out[chunk * kPc + threadIdx.x] = f;
@@ -509,21 +634,12 @@ __global__ __launch_bounds__(kNT) void nf_bwd_kernel(NfArgs a, const float* __re
 //   B (4 waves, 32 rows each, so that every B fragment read from LDS feeds two MFMAs): the layer-1 weight
 //      gradient delta_1 gamma^T from the stored delta_1 and recomputed features.
 // So the stored activations are read once, and layer 1's accumulators need no registers in A.  The ReLU
-// masks of a chunk are kept as one 32-bit word per feature (bit p: point p is positive), built from the
-// registers that carry the chunk into LDS, so that a lane reads the masks of its four rows in one load.
+// masks of a chunk come from the forward pass as one 32-bit word per feature (bit p: point p is positive),
+// so that a lane reads the masks of its four rows in one load.
 constexpr int kWavesS = 4;
 constexpr int kNTS = 64 * kWavesS;
 constexpr int kD1Chunk = kH * kPc;     // stored delta_1 of one chunk, feature-major [128][32]
 
-template <int KS>
-__device__ __forceinline__ void load_rows32(const unsigned short* packed, int off, int ld, bf16x8 (&w)[2][KS]) {
-    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
-    const __bf16* base = reinterpret_cast<const __bf16*>(packed) + off + (32 * wv + r) * ld + 8 * q;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) w[rt][ks] = ld8(base + 16 * rt * ld + 32 * ks);
-}
 
 // Value of lane l ^ 1 (l ^ 2) within groups of four lanes, by DPP quad permutes (no LDS traffic).
 __device__ __forceinline__ unsigned quad_xor1(unsigned v) {
@@ -596,7 +712,8 @@ __device__ __forceinline__ void put_rows32(float* out, int off, int ld, const f3
 }
 
 __global__ __launch_bounds__(kNT) void nf_bwd_a_kernel(NfArgs a, const __bf16* __restrict__ act,
-                                                       const float* __restrict__ f_in, __bf16* __restrict__ d1,
+                                                       const float* __restrict__ f_in,
+                                                       const unsigned* __restrict__ on_in, __bf16* __restrict__ d1,
                                                        const float* __restrict__ dL_dw,
                                                        const float* __restrict__ scale, float* __restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) unsigned char nf_dyn[];
@@ -633,34 +750,28 @@ __global__ __launch_bounds__(kNT) void nf_bwd_a_kernel(NfArgs a, const __bf16* _
         if (r.dl == 0.0f) continue;
         bf16x8 nxt[4];
         float fnxt = 0.0f;
+        unsigned onx;                          // mask word threadIdx.x of the chunk ([4][128])
         {
             const size_t chunk0 = static_cast<size_t>(ray) * n_chunks;
             const __bf16* src = act + chunk0 * kActChunk;
 #pragma unroll
             for (int L = 0; L < 4; ++L) nxt[L] = ld8(src + (L * kH + feature) * kPc + 8 * part);
             if (threadIdx.x < kPc) fnxt = f_in[chunk0 * kPc + threadIdx.x];
+            onx = on_in[chunk0 * 4 * kH + threadIdx.x];
         }
         for (int ch = 0; ch < n_chunks; ++ch) {
             const int s0 = ch * kPc;
             const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
 #pragma unroll
-            for (int L = 0; L < 4; ++L) {
-                *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) = nxt[L];
-                // ReLU bits of the feature's 32 points, gathered from the 4 threads that hold them
-                unsigned bits = 0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) bits |= (static_cast<float>(nxt[L][j]) > 0.0f ? 1u : 0u) << j;
-                bits <<= 8 * part;
-                bits |= quad_xor1(bits);
-                bits |= quad_xor2(bits);
-                if (part == 0) sm.on[L][feature] = bits;
-            }
+            for (int L = 0; L < 4; ++L) *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) = nxt[L];
+            (&sm.on[0][0])[threadIdx.x] = onx;
             const float fcur = fnxt;
             if (ch + 1 < n_chunks) {
                 const __bf16* src = act + (chunk + 1) * kActChunk;
 #pragma unroll
                 for (int L = 0; L < 4; ++L) nxt[L] = ld8(src + (L * kH + feature) * kPc + 8 * part);
                 if (threadIdx.x < kPc) fnxt = f_in[(chunk + 1) * kPc + threadIdx.x];
+                onx = on_in[(chunk + 1) * 4 * kH + threadIdx.x];
             }
             if (threadIdx.x < kPc) {
                 float d = 0.0f;
@@ -930,25 +1041,43 @@ void set_lds_attr(K kernel, size_t lds) {
                               static_cast<int>(lds));
 }
 
-int launch_bwd_stored(const NfArgs& a, const __bf16* act, const float* f_in, __bf16* d1, const float* dL_dw,
-                      const float* scale, float* partial, int blocks, hipStream_t st) {
+int launch_bwd_stored(const NfArgs& a, const __bf16* act, const float* f_in, const unsigned* on, __bf16* d1,
+                      const float* dL_dw, const float* scale, float* partial, int blocks, hipStream_t st) {
     static bool attr = false;
     if (!attr) {
         set_lds_attr(nf_bwd_a_kernel, sizeof(NfBwdALds));
         set_lds_attr(nf_bwd_b_kernel, sizeof(NfBwdBLds));
         attr = true;
     }
-    nf_bwd_a_kernel<<<blocks, kNT, sizeof(NfBwdALds), st>>>(a, act, f_in, d1, dL_dw, scale, partial);
+    nf_bwd_a_kernel<<<blocks, kNT, sizeof(NfBwdALds), st>>>(a, act, f_in, on, d1, dL_dw, scale, partial);
     if (int s = launch_status("pact_nf_sos_to_delays_adjoint")) return s;
     nf_bwd_b_kernel<<<blocks, kNTS, sizeof(NfBwdBLds), st>>>(a, d1, dL_dw, scale, partial);
     return launch_status("pact_nf_sos_to_delays_adjoint");
 }
 
-// Activation buffer: h1..h4 [chunks][4][128][32] BF16, then f [chunks][32] FP32, then the adjoint's
-// delta_1 [chunks][128][32] BF16.
+// Activation buffer: h1..h4 [chunks][4][128][32] BF16, f [chunks][32] FP32, the ReLU mask words of
+// h1..h4 [chunks][4][128] (bit p: point p positive), then the adjoint's delta_1 [chunks][128][32] BF16.
+struct NfActView {
+    __bf16* h;
+    float* f;
+    unsigned* on;
+    __bf16* d1;
+};
+
+NfActView nf_act_view(void* act, long long n_rays, int n_samples) {
+    const size_t chunks = static_cast<size_t>(n_rays) * ((n_samples + kPc - 1) / kPc);
+    NfActView v;
+    v.h = static_cast<__bf16*>(act);
+    v.f = reinterpret_cast<float*>(v.h + chunks * kActChunk);
+    v.on = reinterpret_cast<unsigned*>(v.f + chunks * kPc);
+    v.d1 = reinterpret_cast<__bf16*>(v.on + chunks * 4 * kH);
+    return v;
+}
+
 size_t nf_activation_bytes(long long n_rays, int n_samples) {
     const long long chunks = n_rays * ((n_samples + kPc - 1) / kPc);
-    return static_cast<size_t>(chunks) * (kActChunk * sizeof(__bf16) + kPc * sizeof(float) + kD1Chunk * sizeof(__bf16));
+    return static_cast<size_t>(chunks) * (kActChunk * sizeof(__bf16) + kPc * sizeof(float) + 4 * kH * sizeof(unsigned) +
+                                          kD1Chunk * sizeof(__bf16));
 }
 
 }  // namespace
@@ -991,20 +1120,17 @@ extern "C" int pact_nf_sos_to_delays(const float* B, const float* params, const 
     PACT_CHECK_ARG(w, "pact_nf_sos_to_delays: null output");
     const NfArgs a = nf_args(B, params, packed, amp, mask_radius, v0, centres, N, *ring, n_samples);
     const long long n_rays = static_cast<long long>(N) * ring->n_elem;
-    __bf16* act_h = nullptr;
-    float* act_f = nullptr;
+    NfActView v = {nullptr, nullptr, nullptr, nullptr};
     if (act) {
         const size_t need = nf_activation_bytes(n_rays, n_samples);
         if (act_bytes < need) {
             set_error("pact_nf_sos_to_delays: activation buffer of %zu bytes needed, %zu given", need, act_bytes);
             return PACT_EWORKSPACE;
         }
-        const size_t chunks = static_cast<size_t>(n_rays) * ((n_samples + kPc - 1) / kPc);
-        act_h = static_cast<__bf16*>(act);
-        act_f = reinterpret_cast<float*>(act_h + chunks * kActChunk);
+        v = nf_act_view(act, n_rays, n_samples);
     }
     const int blocks = static_cast<int>(std::min<long long>(n_rays, 2LL * device_cu_count()));
-    nf_fwd_kernel<<<blocks, kNT, 0, as_stream(stream)>>>(a, w, act_h, act_f);
+    nf_fwd_kernel<<<blocks, kNTF, 0, as_stream(stream)>>>(a, w, v.h, v.f, v.on);
     return launch_status("pact_nf_sos_to_delays");
 }
 
@@ -1042,12 +1168,9 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
                       act_bytes);
             return PACT_EWORKSPACE;
         }
-        const size_t chunks = static_cast<size_t>(n_rays) * ((n_samples + kPc - 1) / kPc);
-        __bf16* act_h = static_cast<__bf16*>(act);
-        const float* act_f = reinterpret_cast<const float*>(act_h + chunks * kActChunk);
-        __bf16* d1 = reinterpret_cast<__bf16*>(const_cast<float*>(act_f) + chunks * kPc);
+        const NfActView v = nf_act_view(act, n_rays, n_samples);
         // from the stored activations: the head and layers 4..2 (writing delta_1), then layer 1
-        if (int s = launch_bwd_stored(a, act_h, act_f, d1, dL_dw, scale, partial, blocks, st)) return s;
+        if (int s = launch_bwd_stored(a, v.h, v.f, v.on, v.d1, dL_dw, scale, partial, blocks, st)) return s;
         return launch_nf_reduce(partial, blocks, dL_dparams, st);
     }
     // four passes, each recomputing the forward activations: layers 3-4 (and the head), layer 2, and the
