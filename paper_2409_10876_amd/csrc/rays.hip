@@ -107,10 +107,11 @@ __device__ __forceinline__ float contrast_sample(const float* vs, float sf, floa
     const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
     const float bf = floorf(gx), af = floorf(gy);
     const float fx = gx - bf, fy = gy - af;
-    // clamp so that the 2 x 2 stencil stays in the padded grid whatever the input
-    const int b0 = static_cast<int>(__builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx)));
-    const int a0 = static_cast<int>(__builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy)));
-    const int c = __mul24(a0, g.W) + b0;
+    // clamp so that the 2 x 2 stencil stays in the padded grid whatever the input; the flat index is
+    // formed in float (exact: the padded grid has far fewer than 2^24 nodes)
+    const float bc = __builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx));
+    const float ac = __builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy));
+    const int c = static_cast<int>(fmaf(ac, static_cast<float>(g.W), bc));
     const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + g.W], v11 = vs[c + g.W + 1];
     const float top = fmaf(fx, v01 - v00, v00);
     const float bot = fmaf(fx, v11 - v10, v10);
@@ -440,9 +441,9 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
             const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
             const float bf = floorf(gx), af = floorf(gy);
             const float fx = gx - bf, fy = gy - af;
-            const int b0 = static_cast<int>(__builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx)));
-            const int a0 = static_cast<int>(__builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy)));
-            const int c = __mul24(a0, W) + b0;
+            const float bc = __builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx));
+            const float ac = __builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy));
+            const int c = static_cast<int>(fmaf(ac, static_cast<float>(W), bc));   // exact, as in the forward
             const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
             const float top = fmaf(fx, v01 - v00, v00);
             const float bot = fmaf(fx, v11 - v10, v10);
