@@ -112,3 +112,47 @@ def test_missing_library_fails_loudly(tmp_path):
             pt.load(str(tmp_path / "libpact.so"))
     finally:
         pt._lib = saved
+
+
+def test_warm_start_argument_errors(P):
+    pt = P.pact
+    ring = pt.Ring(512, 110.0, 0.0)
+    # channel pairs that are not built, null pointers, empty shapes
+    s, msg = _status(P, "pact_conv3x3_bf16", FAKE, 2, 8, 8, 32, FAKE, None, 64, 1, None, FAKE, None)
+    assert s == -4 and "not built" in msg
+    s, msg = _status(P, "pact_conv3x3_bf16", None, 2, 8, 8, 64, FAKE, None, 64, 1, None, FAKE, None)
+    assert s == -1 and "null" in msg
+    s, msg = _status(P, "pact_conv3x3_bf16", FAKE, 0, 8, 8, 64, FAKE, None, 64, 1, None, FAKE, None)
+    assert s == -1
+    s, msg = _status(P, "pact_conv3x3_pack", FAKE, 16, 16, FAKE, None, None)
+    assert s == -4
+    assert pt.load().pact_conv3x3_packed_count(16, 64) == 64 * 160
+    assert pt.load().pact_conv3x3_packed_count(64, 16) == 16 * 576
+    # weight gradient: workspace too small
+    s, msg = _status(P, "pact_conv3x3_wgrad_bf16", FAKE, FAKE, 2, 8, 8, 64, 64, FAKE, FAKE, 16, None)
+    assert s == -3 and "workspace" in msg
+    # resampling needs even sizes and channel counts that are multiples of 8
+    s, msg = _status(P, "pact_pool2_bf16", FAKE, 1, 7, 8, 64, FAKE, None)
+    assert s == -1 and "even" in msg
+    s, msg = _status(P, "pact_up2_add_bf16", FAKE, FAKE, 1, 8, 8, 12, FAKE, None)
+    assert s == -1 and "multiple of 8" in msg
+    s, msg = _status(P, "pact_warm_input", FAKE, 20, 560, 560, 4, 1.0, 16, FAKE, None)
+    assert s == -1
+    s, msg = _status(P, "pact_warm_loss", FAKE, 2, 140, 140, 16, FAKE, FAKE, 1.0, FAKE, FAKE, FAKE, 4, None)
+    assert s == -3 and "workspace" in msg
+    s, msg = _status(P, "pact_ricker_channels", FAKE, FAKE, FAKE, FAKE, 0, ring, 1.5, 4096, 40.0, 0.0, FAKE, None)
+    assert s == -1
+    s, msg = _status(P, "pact_ricker_channels", FAKE, FAKE, FAKE, FAKE, 4, pt.Ring(0, 110.0, 0.0), 1.5, 4096, 40.0,
+                     0.0, FAKE, None)
+    assert s == -1 and "n_elem" in msg
+
+
+def test_nf_activation_buffer_too_small(P):
+    pt = P.pact
+    ring = pt.Ring(512, 110.0, 0.0)
+    need = pt.load().pact_nf_activation_bytes(169, ring, 256)
+    # h1..h4, f, the mask words and the adjoint's layer-1 gradients: 32 KB + 128 + 2 KB + 8 KB per 32 samples
+    assert need == 169 * 512 * 8 * (32768 + 128 + 2048 + 8192)
+    s, msg = _status(P, "pact_nf_sos_to_delays", FAKE, FAKE, FAKE, 128, 128, 0.15, 26.0, 1.5, FAKE, 169, ring, 256,
+                     FAKE, FAKE, need - 1, None)
+    assert s == -3 and "activation buffer" in msg
