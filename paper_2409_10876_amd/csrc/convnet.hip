@@ -96,21 +96,41 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const __bf16* __restr
 #pragma unroll
     for (int i = 0; i < 4; ++i) bv[i] = bias ? bias[16 * rt + 4 * q + i] : 0.0f;
     const int per_img = tiles_x * tiles_y;
+    // the halo of the next tile is loaded into registers while this tile is computed (barriers wait on
+    // LDS only): chunk c = threadIdx.x + kThreads k of (kTH + 2) x kHW pixels x CI / 8 parts
+    constexpr int CH = CI / 8;
+    constexpr int NCH = (kTH + 2) * kHW * CH;
+    constexpr int NPRE = (NCH + kThreads - 1) / kThreads;
+    bf16x8 pre[NPRE];
+    auto load_halo = [&](int tile) {
+        const int img = tile / per_img, rem = tile - img * per_img;
+        const int y0 = (rem / tiles_x) * kTH, x0 = (rem % tiles_x) * kTW;
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+            const int c = threadIdx.x + kThreads * k;
+            const int pix = c / CH, part = c - pix * CH;
+            const int hy = pix / kHW, hx = pix - hy * kHW;
+            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+            pre[k] = zero8();
+            if (c < NCH && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                pre[k] = ld8(x + ((static_cast<size_t>(img) * H + gy) * W + gx) * CI + 8 * part);
+        }
+    };
+    if (static_cast<int>(blockIdx.x) < n_tiles) load_halo(blockIdx.x);
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int img = tile / per_img, rem = tile - img * per_img;
         const int y0 = (rem / tiles_x) * kTH, x0 = (rem % tiles_x) * kTW;
         __syncthreads();
-        constexpr int CH = CI / 8;
-        for (int c = threadIdx.x; c < (kTH + 2) * kHW * CH; c += kThreads) {
-            const int pix = c / CH, part = c - pix * CH;
-            const int hy = pix / kHW, hx = pix - hy * kHW;
-            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-            bf16x8 v = zero8();
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-                v = ld8(x + ((static_cast<size_t>(img) * H + gy) * W + gx) * CI + 8 * part);
-            *reinterpret_cast<bf16x8*>(halo + pix * LDX + 8 * part) = v;
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+            const int c = threadIdx.x + kThreads * k;
+            if (c < NCH) {
+                const int pix = c / CH, part = c - pix * CH;
+                *reinterpret_cast<bf16x8*>(halo + pix * LDX + 8 * part) = pre[k];
+            }
         }
         __syncthreads();
+        if (tile + static_cast<int>(gridDim.x) < n_tiles) load_halo(tile + gridDim.x);
 #pragma unroll
         for (int g0 = 0; g0 < NPW; g0 += NG) {
             f32x4 acc[NG];
@@ -162,38 +182,65 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
         for (int t = 0; t < 9; ++t) acc[p][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float db[8] = {};
     const int per_img = tiles_x * tiles_y;
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    // the next tile's input halo and output gradient are loaded into registers while this tile is
+    // computed: input chunk c = threadIdx.x + kThreads k of (kWTH + 2) x kHW pixels x CI / 8 parts, output
+    // chunk c of kWTH x 16 pixels x CO / 8 parts
+    constexpr int NXC = (kWTH + 2) * kHW * CHI, NXP = (NXC + kThreads - 1) / kThreads;
+    constexpr int NGC = kWTH * kTW * CHO, NGP = (NGC + kThreads - 1) / kThreads;
+    bf16x8 px[NXP], pg[NGP];
+    auto load_tile = [&](int tile) {
         const int img = tile / per_img, rem = tile - img * per_img;
         const int y0 = (rem / tiles_x) * kWTH, x0 = (rem % tiles_x) * kTW;
-        __syncthreads();
-        // input halo rows y0 - 1 .. y0 + kWTH, columns x0 - 1 .. x0 + 16; copy s holds column j + s - 1
-        for (int c = threadIdx.x; c < (kWTH + 2) * kHW * CHI; c += kThreads) {
+#pragma unroll
+        for (int k = 0; k < NXP; ++k) {
+            const int c = threadIdx.x + kThreads * k;
             const int pix = c / CHI, part = c - pix * CHI;
             const int hy = pix / kHW, hx = pix - hy * kHW;
             const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-            bf16x8 v = zero8();
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-                v = ld8(x + ((static_cast<size_t>(img) * H + gy) * W + gx) * CI + 8 * part);
+            px[k] = zero8();
+            if (c < NXC && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                px[k] = ld8(x + ((static_cast<size_t>(img) * H + gy) * W + gx) * CI + 8 * part);
+        }
+#pragma unroll
+        for (int k = 0; k < NGP; ++k) {
+            const int c = threadIdx.x + kThreads * k;
+            const int pix = c / CHO, part = c - pix * CHO;
+            const int gy = y0 + pix / kTW, gx = x0 + pix % kTW;
+            pg[k] = zero8();
+            if (c < NGC && gy < H && gx < W) pg[k] = ld8(g + ((static_cast<size_t>(img) * H + gy) * W + gx) * CO + 8 * part);
+        }
+    };
+    if (static_cast<int>(blockIdx.x) < n_tiles) load_tile(blockIdx.x);
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        __syncthreads();
+        // input halo rows y0 - 1 .. y0 + kWTH, columns x0 - 1 .. x0 + 16; copy s holds column j + s - 1
+#pragma unroll
+        for (int k = 0; k < NXP; ++k) {
+            const int c = threadIdx.x + kThreads * k;
+            if (c >= NXC) continue;
+            const int pix = c / CHI, part = c - pix * CHI;
+            const int hy = pix / kHW, hx = pix - hy * kHW;
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 const int j = hx - s;
                 if (j < 0 || j >= kTW) continue;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) xT[(s * CI + 8 * part + e) * kXB + hy * kXR + j] = v[e];
+                for (int e = 0; e < 8; ++e) xT[(s * CI + 8 * part + e) * kXB + hy * kXR + j] = px[k][e];
             }
         }
-        for (int c = threadIdx.x; c < kWTH * kTW * CHO; c += kThreads) {
+#pragma unroll
+        for (int k = 0; k < NGP; ++k) {
+            const int c = threadIdx.x + kThreads * k;
+            if (c >= NGC) continue;
             const int pix = c / CHO, part = c - pix * CHO;
-            const int gy = y0 + pix / kTW, gx = x0 + pix % kTW;
-            bf16x8 v = zero8();
-            if (gy < H && gx < W) v = ld8(g + ((static_cast<size_t>(img) * H + gy) * W + gx) * CO + 8 * part);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                gT[(8 * part + e) * kGL + pix] = v[e];
-                db[e] += static_cast<float>(v[e]);
+                gT[(8 * part + e) * kGL + pix] = pg[k][e];
+                db[e] += static_cast<float>(pg[k][e]);
             }
         }
         __syncthreads();
+        if (tile + static_cast<int>(gridDim.x) < n_tiles) load_tile(tile + gridDim.x);
         // K step ks: pixels 32 ks .. 32 ks + 31 of the tile = rows 2 ks, 2 ks + 1; lane q takes row
         // 2 ks + q / 2, columns 8 (q % 2) .. + 7
 #pragma unroll
