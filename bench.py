@@ -490,6 +490,13 @@ def warm_leg(P, n_scans, batch=32, reps=20):
     b.record()
     torch.cuda.synchronize()
     us_wg = 1e3 * a.elapsed_time(b) / reps
+    # the FP64 oracle of the network: forward and reverse mode for one image of the training shape
+    from oracle import warmstart as Ow
+    F64 = torch.float64
+    xo = x[:1].float().cpu().to(F64)
+    t0 = time.perf_counter()
+    Ow.loss_and_grad(torch.tensor(params, dtype=F64), xo, tg[:1].cpu().to(F64), mask.cpu())
+    dt_oracle = time.perf_counter() - t0
     print(f"[bench] warm start: rmse v0 {summary['rmse_v0']:.2f} net {summary['rmse_net']:.2f} plain "
           f"{summary['rmse_plain']:.2f} m/s; train step {ms_step:.2f} ms; conv 64->64 {us_conv:.1f} us; "
           f"weight gradient {us_wg:.1f} us", flush=True)
@@ -497,6 +504,10 @@ def warm_leg(P, n_scans, batch=32, reps=20):
         "held_out_scans": n_scans, "summary": summary, "mean_rmse_curves_per_10_steps": curves,
         "weights": {k: meta[k] for k in meta}, "network": "8 conv 3x3, 64 channels, 2 poolings, 2 doublings with "
         "skips; BF16 MFMA, FP32 accumulation; input: 11-delay DAS stack averaged to 140^2",
+        "cpu_oracle": {"value": 1.0 / dt_oracle, "unit": "images/s (forward + reverse-mode gradient)",
+                       "cores": torch.get_num_threads(), "kind": "oracle",
+                       "sample": f"one {G}x{G} image, float64, in {dt_oracle:.2f} s",
+                       "gpu_images_per_s_training": batch / (ms_step * 1e-3)},
         "train_step": {"batch": batch, "ms": ms_step, "mfma_flops_executed": fl, "mfma_flops_real_channels": fl_real,
                        "tflops_executed": fl / (ms_step * 1e-3) / 1e12, "frac_of_bf16_peak": fl / (ms_step * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS},
         "conv3x3_64x64": {"kernel": "conv3x3_kernel<64,64>", "shape": f"{batch}x{G}x{G}x64", "us": us_conv,
@@ -506,6 +517,31 @@ def warm_leg(P, n_scans, batch=32, reps=20):
                                 "tflops": conv_flops / (us_wg * 1e-6) / 1e12,
                                 "frac_of_bf16_peak": conv_flops / (us_wg * 1e-6) / 1e12 / MFMA_BF16_PEAK_TFLOPS},
     }
+
+
+def nf_oracle_rate(scan, cfg, n_centres=4, n_elem=32):
+    """The FP64 oracle of the neural field (forward and the layer-by-layer backward) on a bounded sample of
+    rays of the same workload: ray samples per second on this host."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import nf as Onf
+    from oracle.geometry import patch_centres
+    F64 = torch.float64
+    B = torch.tensor(synth.nf.frequencies(cfg), dtype=F64)
+    params = torch.tensor(synth.nf.init_params(cfg), dtype=F64)
+    c = patch_centres(scan.ny, scan.nx, scan.px, scan.P, scan.stride)[:n_centres]
+    phi = scan.phi0 + 2 * np.pi * np.arange(0, scan.n_elem, scan.n_elem // n_elem)[:n_elem] / scan.n_elem
+    ring = torch.tensor(np.stack([scan.radius * np.cos(phi), scan.radius * np.sin(phi)], -1), dtype=F64)
+    gw = torch.ones(n_centres, n_elem, dtype=F64)
+    t0 = time.perf_counter()
+    Onf.sos_to_delays(params, B, c, ring, scan.mask_radius, scan.v0, cfg.amp, scan.n_samples)
+    Onf.sos_to_delays_vjp(params, B, c, ring, scan.mask_radius, scan.v0, cfg.amp, scan.n_samples, gw)
+    dt = time.perf_counter() - t0
+    pts = n_centres * n_elem * scan.n_samples
+    return {"value": pts / dt, "unit": "ray samples/s (forward + backward)", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": f"{n_centres} patch centres x {n_elem} elements x {scan.n_samples} samples "
+                                        f"in {dt:.2f} s"}
 
 
 def nf_leg(P, sd, scan, steps):
@@ -557,8 +593,10 @@ def nf_leg(P, sd, scan, steps):
         v["frac"] = v["achieved"] / v["peak"]
     print(f"[bench] neural field: {step_ms:.2f} ms/step; " + ", ".join(f"{k} {v:.0f} us" for k, v in us.items()),
           flush=True)
+    gpu_pts = pts / ((us["nf_sos_to_delays"] + us["nf_sos_to_delays_adjoint"]) * 1e-6)
     return {"steps_per_s": 1e3 / step_ms, "ms_per_step": step_ms, "steps_timed": steps, "stage_us": us,
             "rooflines": roof, "dtype": "bf16 MFMA, f32 accumulate",
+            "points_per_s_fwd_adj": gpu_pts, "cpu_oracle": nf_oracle_rate(scan, cfg),
             "config": f"Fourier features {cfg.n_freq} (sigma {cfg.sigma} /mm) -> {cfg.depth} x {cfg.width} ReLU -> "
                       f"SOS, {pts} ray samples per step"}
 
