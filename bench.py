@@ -383,7 +383,9 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
         sd = P.prepare_scan(sc, inp.S, np.asarray(sc.delays, dtype=np.float32))
         solvers.append(P.PixelGridSolver(sd, inp.mask, eps=sc.eps, lam=sc.lam_tv, lr=sc.lr, n_samples=sc.n_samples))
     print(f"[bench] batch: {n_scans} scans prepared in {time.perf_counter() - t0:.1f} s", flush=True)
-    batch = P.BatchedSolver(solvers, graph_steps=graph_steps)
+    t0 = time.perf_counter()
+    batch = P.BatchedSolver(solvers, graph_steps=graph_steps, autotune=True)
+    print(f"[bench] batch: ray tilings autotuned per scan shape in {time.perf_counter() - t0:.1f} s", flush=True)
     batch.run(graph_steps)
     batch.run_sequential(graph_steps)
     torch.cuda.synchronize()
@@ -397,8 +399,8 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
         ms = a.elapsed_time(b)
         out[name] = {"ms": ms, "scan_steps_per_s": n_scans * steps / (ms * 1e-3)}
     out["speedup"] = out["sequential"]["ms"] / out["concurrent"]["ms"]
-    out["scans"] = [{"px": s.ny, "n_elem": s.n_elem, "M": s.M, "P": s.P, "patches": s.n_patches, "sos_n": s.sos_n}
-                    for s in scans]
+    out["scans"] = [{"px": s.ny, "n_elem": s.n_elem, "M": s.M, "P": s.P, "patches": s.n_patches, "sos_n": s.sos_n,
+                     "ray_tiling": list(t)} for s, t in zip(scans, batch.tilings)]
     out["patches_x_delays_per_s"] = sum(s.n_patches * s.M for s in scans) * steps / (out["concurrent"]["ms"] * 1e-3)
     print(f"[bench] batch: {n_scans} scans x {steps} steps: sequential {out['sequential']['ms']:.1f} ms, "
           f"concurrent {out['concurrent']['ms']:.1f} ms", flush=True)

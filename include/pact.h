@@ -320,6 +320,19 @@ PACT_API int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, 
                                   const float* dL_dw, const float* scale, float* dL_dparams, void* act,
                                   size_t act_bytes, void* ws, size_t ws_bytes, void* stream);
 
+/* Autotuned ray tilings (for scans of many shapes, e.g. batched solves): times the lanes per ray of
+ * pact_sos_to_delays (1, 2, 4, .. 64) and the segments per ray of pact_sos_to_delays_adjoint (around its
+ * built-in rule) on this geometry, with HIP events on `stream`, and keeps the fastest for every later
+ * call on this device with the same N, ring element count, n_samples and SOS grid size (the built-in
+ * rules apply otherwise).  The choice changes only how each ray's sum is split, so results move in the
+ * last bits.  Synchronises the stream; do not call it while a graph is being captured.  w, dL_dsos, ws:
+ * DEVICE scratch as for the two calls (overwritten); dL_dw: a DEVICE gradient to time the adjoint with.
+ * tiling (HOST, 2 ints, or NULL) receives {forward lanes per ray, adjoint segments per ray} (0: not
+ * tuned, the tile form of the adjoint). */
+PACT_API int pact_rays_autotune(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
+                                const pact_ring* ring, int n_samples, const float* dL_dw, float* w, float* dL_dsos,
+                                void* ws, size_t ws_bytes, int* tiling, void* stream);
+
 /* ---- Learned warm start: convolutional SOS initialiser ----
  *
  * Not part of the paper's method, which uses no training data (Sec. 3.3): a convolutional network maps

@@ -34,6 +34,12 @@
 // the forward sum.
 #include "common.h"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 namespace pact {
 
 int device_cu_count();
@@ -549,6 +555,37 @@ int check_rays(const float* sos, pact_grid sosg, float v0, const float* centres,
     return PACT_OK;
 }
 
+// Ray tilings chosen by pact_rays_autotune, per device and geometry: lanes per ray of the forward kernel
+// and segments per ray of the adjoint (0 = the built-in rule).
+using TuneKey = std::tuple<int, int, int, int, int, int>;     // device, N, n_elem, n_samples, ny, nx
+struct RayTiling {
+    int fwd = 0, adj = 0;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, RayTiling> g_tuned;
+
+TuneKey tune_key(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    return TuneKey(dev, N, ring.n_elem, n_samples, sosg.ny, sosg.nx);
+}
+
+RayTiling tuned_tiling(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tuned.find(tune_key(N, ring, n_samples, sosg));
+    return it == g_tuned.end() ? RayTiling() : it->second;
+}
+
+// Lanes per ray of the forward kernel by the built-in rule: the smallest power of two (at most 64, at
+// least 16 samples a segment) whose work items fill about two rounds of two workgroups per CU (measured
+// at 86,528 rays x 256 samples: K = 8 is 10% faster than one round with K = 4).
+int fwd_lanes_rule(long long n_rays, int n_samples) {
+    const long long lanes = 2LL * device_cu_count() * kThreads;
+    int K = 1;
+    while (K < 64 && n_rays * K < lanes && n_samples / (2 * K) >= 16) K *= 2;
+    return K;
+}
+
 }  // namespace
 }  // namespace pact
 
@@ -573,13 +610,10 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
         attr = true;
     }
-    // segments per ray: the smallest power of two (at most 64, at least 16 samples a segment) whose work
-    // items fill about two rounds of two workgroups per CU (measured at 86,528 rays x 256 samples: K = 8 is
-    // 10% faster than one round with K = 4)
+    // lanes per ray: the autotuned value for this geometry, else the built-in rule
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
-    const long long lanes = 2LL * device_cu_count() * kThreads;
-    int K = 1;
-    while (K < 64 && n_rays * K < lanes && n_samples / (2 * K) >= 16) K *= 2;
+    const int tuned = tuned_tiling(N, ring, n_samples, sosg).fwd;
+    const int K = tuned > 0 ? tuned : fwd_lanes_rule(n_rays, n_samples);
     PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "pact_sos_to_delays: too many rays");
     const int n_items = static_cast<int>(n_rays * K);
     const int blocks = static_cast<int>(std::min<long long>(ceil_div(n_items, kThreads), 2LL * device_cu_count()));
@@ -655,7 +689,8 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
             gattr = true;
         }
         const long long n_rays = static_cast<long long>(N) * ring.n_elem;
-        const int K = adj_segments(n_rays, n_samples, static_cast<long long>(blocks) * kGridThreads);
+        const int tuned = tuned_tiling(N, ring, n_samples, sosg).adj;
+        const int K = tuned > 0 ? tuned : adj_segments(n_rays, n_samples, static_cast<long long>(blocks) * kGridThreads);
         PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "pact_sos_to_delays_adjoint: too many ray segments");
         const int n_items = static_cast<int>(n_rays * K);
         const int per_block = ceil_div(n_items, blocks);
@@ -690,4 +725,116 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
         sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), tiles_x,
         dL_dw, scale, accumulate, dL_dsos);
     return launch_status("pact_sos_to_delays_adjoint");
+}
+
+namespace pact {
+namespace {
+
+void set_tiling(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg, RayTiling t) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned[tune_key(N, ring, n_samples, sosg)] = t;
+}
+
+// Median time (ms) of `reps` runs of fn on the stream, by HIP events; negative on an error, with the
+// call's own status in `status` (PACT_EHIP for an event failure).
+template <typename F>
+float time_ms(F fn, hipStream_t st, int reps, int& status) {
+    status = PACT_EHIP;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1.0f;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return -1.0f;
+    }
+    std::vector<float> t;
+    float out = -1.0f;
+    for (int r = 0; r <= reps; ++r) {                    // the first run warms up
+        if (hipEventRecord(a, st) != hipSuccess) break;
+        const int s = fn();
+        if (s != PACT_OK) {
+            status = s;
+            break;
+        }
+        if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) break;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, a, b) != hipSuccess) break;
+        if (r > 0) t.push_back(ms);
+    }
+    if (static_cast<int>(t.size()) == reps) {
+        std::sort(t.begin(), t.end());
+        out = t[t.size() / 2];
+        status = PACT_OK;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return out;
+}
+
+}  // namespace
+}  // namespace pact
+
+extern "C" int pact_rays_autotune(const float* sos, const pact_grid* sosg_, float v0, const float* centres, int N,
+                                  const pact_ring* ring_, int n_samples, const float* dL_dw, float* w,
+                                  float* dL_dsos, void* ws, size_t ws_bytes, int* tiling, void* stream) {
+    using namespace pact;
+    clear_error();
+    PACT_CHECK_ARG(sosg_ && ring_ && dL_dw && w && dL_dsos, "pact_rays_autotune: null pointer");
+    const pact_grid sosg = *sosg_;
+    const pact_ring ring = *ring_;
+    if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_rays_autotune")) return s;
+    hipStream_t st = as_stream(stream);
+    const long long n_rays = static_cast<long long>(N) * ring.n_elem;
+    const int reps = 5;
+    set_tiling(N, ring, n_samples, sosg, RayTiling());   // time every candidate from a clean table
+    // forward: powers of two from 1 to 64 lanes per ray with at least 8 samples a lane
+    RayTiling best;
+    float best_ms = -1.0f;
+    for (int K = 1; K <= 64 && n_samples / K >= 8; K *= 2) {
+        if (n_rays * K >= (1LL << 31)) break;
+        set_tiling(N, ring, n_samples, sosg, RayTiling{K, 0});
+        int status = PACT_OK;
+        const float ms = time_ms([&] { return pact_sos_to_delays(sos, &sosg, v0, centres, N, &ring, n_samples, w,
+                                                                 stream); }, st, reps, status);
+        if (ms < 0.0f) {
+            set_tiling(N, ring, n_samples, sosg, RayTiling());
+            if (status == PACT_EHIP) set_error("pact_rays_autotune: timing events failed");
+            return status;
+        }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best.fwd = K;
+        }
+    }
+    // adjoint (grid form only): segments per ray around the built-in rule
+    if (adj_grid_lds(sosg)) {
+        const int rule = adj_segments(n_rays, n_samples, static_cast<long long>(device_cu_count()) * kGridThreads);
+        std::vector<int> cand = {rule, rule - 1, rule + 1, rule / 2, rule * 2, 1, 2, 4, 8, 16};
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        best_ms = -1.0f;
+        for (int K : cand) {
+            if (K < 1 || K > std::max(1, n_samples / 4) || n_rays * K >= (1LL << 31)) continue;
+            set_tiling(N, ring, n_samples, sosg, RayTiling{best.fwd, K});
+            int status = PACT_OK;
+            const float ms = time_ms([&] { return pact_sos_to_delays_adjoint(sos, &sosg, v0, centres, N, &ring,
+                                                                             n_samples, dL_dw, nullptr, dL_dsos, 0,
+                                                                             ws, ws_bytes, stream); }, st, reps,
+                                     status);
+            if (ms < 0.0f) {
+                set_tiling(N, ring, n_samples, sosg, RayTiling());
+                if (status == PACT_EHIP) set_error("pact_rays_autotune: timing events failed");
+                return status;
+            }
+            if (best_ms < 0.0f || ms < best_ms) {
+                best_ms = ms;
+                best.adj = K;
+            }
+        }
+    }
+    set_tiling(N, ring, n_samples, sosg, best);
+    if (tiling) {
+        tiling[0] = best.fwd;
+        tiling[1] = best.adj;
+    }
+    return PACT_OK;
 }

@@ -78,6 +78,7 @@ _SIGS = {
     "pact_nf_sos_to_delays_adjoint_workspace_size": (_Z, [_I, _I]),
     "pact_nf_sos_to_delays_adjoint": (_I, [_P, _P, _P, _I, _I, _F, _F, _F, _P, _I, _PRING, _I, _P, _P, _P, _P,
                                            _Z, _P, _Z, _P]),
+    "pact_rays_autotune": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _P, _P, _P, _P, _Z, _P, _P]),
     "pact_conv3x3_packed_count": (_Z, [_I, _I]),
     "pact_conv3x3_pack": (_I, [_P, _I, _I, _P, _P, _P]),
     "pact_conv3x3_bf16": (_I, [_P, _I, _I, _I, _I, _P, _P, _I, _I, _P, _P, _P]),
@@ -252,6 +253,20 @@ def sos_to_delays_adjoint(sos, g: Geometry, v0, centres, n_samples, dL_dw, out=N
         _ptr(out, F32, "dL_dsos", g.sos_ny * g.sos_nx), int(accumulate), _ptr(ws, name="ws"), ws.numel(),
         _stream()), "pact_sos_to_delays_adjoint")
     return out
+
+
+def rays_autotune(sos, g: Geometry, v0, centres, n_samples, dL_dw, w, dL_dsos, ws):
+    """Time the ray tilings on this geometry and keep the fastest (see include/pact.h); returns
+    (forward lanes per ray, adjoint segments per ray).  w, dL_dsos and ws are overwritten."""
+    N = centres.shape[0]
+    n = g.sos_ny * g.sos_nx
+    out = (ctypes.c_int * 2)()
+    _check(load().pact_rays_autotune(_ptr(sos, F32, "sos", n), g.sosg, v0, _ptr(centres, F32, "centres", 2 * N), N,
+                                     g.ring, n_samples, _ptr(dL_dw, F32, "dL_dw", N * g.n_elem),
+                                     _ptr(w, F32, "w", N * g.n_elem), _ptr(dL_dsos, F32, "dL_dsos", n),
+                                     _ptr(ws, name="ws"), ws.numel(), ctypes.cast(out, ctypes.c_void_p), _stream()),
+           "pact_rays_autotune")
+    return out[0], out[1]
 
 
 def delays_to_psf(w, centres, g: Geometry, d, with_psf=False, H=None, h=None):

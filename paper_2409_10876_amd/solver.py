@@ -132,6 +132,14 @@ class PixelGridSolver:
         self.adjoint()
         self.tv_update()
 
+    def autotune(self):
+        """Time the ray tilings on this scan's geometry (at the current SOS and its loss gradient) and keep
+        the fastest for every later step of scans of the same shape; call before capture()."""
+        self.delays()
+        self.loss_grad()
+        return pact.rays_autotune(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
+                                  self.w, self.grad, self.ws_adj)
+
     def capture(self, steps: int):
         """Capture `steps` (even) consecutive steps into one HIP graph (run one eager step first).  The
         steps alternate the two SOS buffers, so a replay starts and ends on the same one."""
@@ -334,10 +342,12 @@ class BatchedSolver:
     fill the chip where one scan's small kernels and tails would leave it idle.  Each scan's results are the
     ones it gets alone (the kernels are deterministic and share no buffers)."""
 
-    def __init__(self, solvers, graph_steps: int = 10):
+    def __init__(self, solvers, graph_steps: int = 10, autotune: bool = False):
         self.solvers = list(solvers)
         self.graph_steps = graph_steps
         self.streams = [torch.cuda.Stream() for _ in self.solvers]
+        # ray tilings timed per scan shape before the graphs record them
+        self.tilings = [s.autotune() for s in self.solvers] if autotune else None
         for s in self.solvers:
             s.step()
         torch.cuda.synchronize()

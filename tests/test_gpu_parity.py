@@ -360,3 +360,32 @@ def test_stitch(lib, scan):
     e2 = rel_l2(img, img_want)
     print(f"X_hat -> image rel L2 {e2:.2e}")
     assert e2 < TOL_DECONV
+
+
+def test_rays_autotune(lib):
+    # a geometry no other test uses (the tuned tilings are kept per geometry for the process)
+    scan = RAGGED.with_(n_samples=90)
+    announce(f"rays autotune {scan.name} N_s={scan.n_samples}")
+    ov = OracleView(scan)
+    v = _random_sos(scan, 7)
+    rng = np.random.default_rng(8)
+    N = ov.centres.shape[0]
+    gw = rng.normal(size=(N, scan.n_elem)).astype(np.float32)
+    g = _geom(lib, scan)
+    w = torch.empty(N, scan.n_elem, device="cuda")
+    gs = torch.empty(scan.sos_n, scan.sos_n, device="cuda")
+    ws = torch.empty(max(1, lib.pact.sos_to_delays_adjoint_workspace_size(g, N)), dtype=torch.uint8, device="cuda")
+    kf, ka = lib.pact.rays_autotune(dev32(v), g, scan.v0, dev32(ov.centres), scan.n_samples, dev32(gw), w, gs, ws)
+    assert kf in (1, 2, 4, 8) and 1 <= ka <= scan.n_samples // 4, (kf, ka)
+    # the calls now run with the tuned tilings and still match the oracle
+    want = Orays.sos_to_delays(torch.tensor(v, dtype=torch.float64), ov.ds, ov.v0, ov.centres, scan.n_elem, ov.R,
+                               ov.phi0, scan.n_samples)
+    got = lib.pact.sos_to_delays(dev32(v), g, scan.v0, dev32(ov.centres), scan.n_samples)
+    fn = lambda vv: Orays.sos_to_delays(vv, ov.ds, ov.v0, ov.centres, scan.n_elem, ov.R, ov.phi0, scan.n_samples)
+    (gwant,) = Oloss.vjp(fn, (torch.tensor(v, dtype=torch.float64),), torch.tensor(gw, dtype=torch.float64))
+    ggot = lib.pact.sos_to_delays_adjoint(dev32(v), g, scan.v0, dev32(ov.centres), scan.n_samples, dev32(gw))
+    again = lib.pact.sos_to_delays_adjoint(dev32(v), g, scan.v0, dev32(ov.centres), scan.n_samples, dev32(gw))
+    torch.cuda.synchronize()
+    assert rel_l2(got, want) < TOL_DELAYS
+    assert rel_l2(ggot, gwant) < TOL_GRAD
+    assert torch.equal(ggot, again)
