@@ -667,14 +667,23 @@ struct NfBwdALds {
 // chunk's 32 points, and delta_{L-1} = (W_L^T delta_L) [h_{L-1} > 0] into the other buffer (its bias
 // gradient into gb).  Ends with a barrier.
 template <int L>
-__device__ __forceinline__ void nf_level_a(NfBwdALds& sm, const bf16x8 (&tw)[4], f32x4 (&gl)[8], float (&gb)[4],
+__device__ __forceinline__ void nf_level_a(NfBwdALds& sm, const bf16x8 (&tw)[4], f32x4 (&gl)[2][4], float (&gb)[4],
                                            int cur) {
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
     const int row0 = 16 * wv + 4 * q;
     const __bf16* hprev = sm.hT[L - 2];
-    const bf16x8 da = ld8(sm.dT[cur] + (16 * wv + r16) * kLdT + 8 * q);
+    // weight gradient: wave wv takes rows 32 (wv / 2) .. + 31 and columns 64 (wv % 2) .. + 63 of dW_L, so
+    // that each fragment read feeds two MFMAs
+    const int rg = wv >> 1, cg = wv & 1;
+    bf16x8 da[2];
 #pragma unroll
-    for (int kt = 0; kt < 8; ++kt) gl[kt] = mfma(da, ld8(hprev + (16 * kt + r16) * kLdT + 8 * q), gl[kt]);
+    for (int rt = 0; rt < 2; ++rt) da[rt] = ld8(sm.dT[cur] + (32 * rg + 16 * rt + r16) * kLdT + 8 * q);
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+        const bf16x8 hb = ld8(hprev + (64 * cg + 16 * kt + r16) * kLdT + 8 * q);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) gl[rt][kt] = mfma(da[rt], hb, gl[rt][kt]);
+    }
     const uint4 on = *reinterpret_cast<const uint4*>(&sm.on[L - 2][row0]);
     f32x4 d2[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
@@ -725,13 +734,15 @@ __global__ __launch_bounds__(kNT) void nf_bwd_a_kernel(NfArgs a, const __bf16* _
     load_rows<4>(a.packed, kOffT4, kH, t4);
     load_rows<4>(a.packed, kOffT3, kH, t3);
     load_rows<4>(a.packed, kOffT2, kH, t2);
-    f32x4 g2[8], g3[8], g4[8];
+    f32x4 g2[2][4], g3[2][4], g4[2][4];       // weight gradients: rows 32 (wv / 2) + 16 rt, columns 64 (wv % 2) + 16 kt
 #pragma unroll
-    for (int kt = 0; kt < 8; ++kt) {
-        g2[kt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        g3[kt] = g2[kt];
-        g4[kt] = g2[kt];
-    }
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+            g2[rt][kt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            g3[rt][kt] = g2[rt][kt];
+            g4[rt][kt] = g2[rt][kt];
+        }
     float gb[4][4] = {};                      // bias gradients of layers 1..4, rows row0 + i
     float gw5 = 0.0f, gb5 = 0.0f;             // w5 gradient of feature t / 4 (partial over its 8 points)
     const float sc = scale ? *scale : 1.0f;
@@ -825,11 +836,15 @@ __global__ __launch_bounds__(kNT) void nf_bwd_a_kernel(NfArgs a, const __bf16* _
     }
 
     float* out = partial + static_cast<size_t>(blockIdx.x) * kNParams;
-    auto put_w = [&](int off, const f32x4 (&gl)[8]) {
+    auto put_w = [&](int off, const f32x4 (&gl)[2][4]) {
+        const int rg = wv >> 1, cg = wv & 1;
 #pragma unroll
-        for (int kt = 0; kt < 8; ++kt)
+        for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) out[off + (row0 + i) * kH + 16 * kt + r16] = gl[kt][i];
+            for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    out[off + (32 * rg + 16 * rt + 4 * q + i) * kH + 64 * cg + 16 * kt + r16] = gl[rt][kt][i];
     };
     put_w(kPW2, g2);
     put_w(kPW3, g3);
