@@ -84,7 +84,6 @@ TRAFFIC = {
     "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "98180ee00314ac07", "bytes": 47640428},
     "tv_adam_step": {"source": "optim.hip", "sha256_16": "58740c5b3292f6bb", "bytes": 684341}
 }
-}
 
 
 def cpu_baseline(scan, inp, n_steps):
