@@ -107,11 +107,33 @@ def cpu_baseline(scan, inp, n_steps):
         _, gv, _, _ = Oloss.loss_and_grad(opt.p, inp.mask, Y, geom, scan.lam_tv)
         opt.step(gv)
     dt = time.perf_counter() - t0
-    return {"value": n_steps / dt, "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+    cores = torch.get_num_threads()
+    # the same on one core, one step
+    torch.set_num_threads(1)
+    t1 = time.perf_counter()
+    _, gv, _, _ = Oloss.loss_and_grad(opt.p, inp.mask, Y, geom, scan.lam_tv)
+    opt.step(gv)
+    dt1 = time.perf_counter() - t1
+    torch.set_num_threads(cores)
+    return {"value": n_steps / dt, "unit": "steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_steps} full FP64 oracle optimisation steps at the same workload "
                       f"({N} patches x {scan.M} delays, {scan.n_elem} elements, {scan.sos_n}^2 SOS grid, "
                       f"{scan.n_samples} samples/ray) in {dt:.1f} s; DAS/FFT not included",
-            "patches_x_delays_per_s": n_steps * N * scan.M / dt}
+            "patches_x_delays_per_s": n_steps * N * scan.M / dt,
+            "job_s_extrapolated": scan.steps * dt / n_steps,
+            "single_core": {"value": 1.0 / dt1, "unit": "steps/s", "cores": 1, "sample": f"1 step in {dt1:.1f} s"},
+            "host_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+# The paper's own end-to-end times (Table 1 and Fig. 3d), on its hardware and its data (five k-Wave
+# phantoms, 16 delays, a 200k-pixel SOS map): context, not a target, since the workloads differ.
+PAPER_CONTEXT = {
+    "hardware": "one NVIDIA RTX A6000, PyTorch, precision not stated",
+    "reconstruction_s": {"neural field (10 epochs)": 40.3, "pixel grid + TV (30 epochs)": 113.3},
+    "deconvolution_with_true_sos_s": 2.6, "das_s": 0.13,
+    "deconvolution_vs_channels_s": {"4": 0.9, "32": 5.0},
+    "source": "Table 1 and Fig. 3d of the paper",
+}
 
 
 def main():
@@ -269,6 +291,8 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, inp, args.cpu_steps)
+    out["paper_context"] = dict(PAPER_CONTEXT, this_job_s=elapsed / args.steps,
+                                this_job="das_stack + patch_fft + 500 pixel-grid steps on the paper-shaped scan")
     print(json.dumps(out), flush=True)
 
 
