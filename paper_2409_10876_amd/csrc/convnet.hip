@@ -23,10 +23,11 @@
 //
 // Weight gradient: dW[co][tap][ci] = sum over pixels g[p][co] x[p + tap][ci], a GEMM reduced over pixels.
 // Both operands need 8 consecutive pixels of one channel per lane, so the tile (4 rows x 16 columns) is
-// transposed into LDS: the output gradient channel-major, and the input halo channel-major in three
-// copies shifted by -1, 0, +1 columns, so that every fragment read is one aligned 16-byte read.  Each
-// workgroup accumulates its share of the pixels in registers and writes one partial gradient; two small
-// kernels sum the partials in a fixed order.
+// transposed into LDS channel-major.  The column shift of a tap is moved onto the output gradient (three
+// copies shifted by +1, 0, -1 columns) and the row shift stays on the input (one copy with a halo of one
+// row above and below), so that every fragment read is one aligned 16-byte read and every LDS write
+// packs two adjacent pixels.  Each workgroup accumulates its share of the pixels in registers and writes
+// one partial gradient; two small kernels sum the partials in a fixed order.
 #include "common.h"
 
 namespace pact {
@@ -53,9 +54,8 @@ constexpr int kTH = 8;                 // output rows of a convolution tile
 constexpr int kTW = 16;                // output columns of a tile (one MFMA N tile)
 constexpr int kHW = kTW + 2;           // halo columns
 constexpr int kWTH = 4;                // output rows of a weight-gradient tile (64 pixels, two K steps)
-constexpr int kXR = kTW + 8;           // row of a transposed halo copy (elements)
-constexpr int kXB = (kWTH + 2) * kXR + 8;   // one channel of a transposed halo copy
-constexpr int kGL = kWTH * kTW + 8;    // one channel of the transposed output gradient
+constexpr int kXB = (kWTH + 2) * kTW + 8;   // one channel of the transposed input tile (16-byte padding)
+constexpr int kGL = kWTH * kTW + 8;    // one channel of a transposed output-gradient copy
 constexpr int kSlices = 16;
 
 __host__ __device__ constexpr int kpad(int c) { return (9 * c + 31) / 32 * 32; }
@@ -164,14 +164,19 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const __bf16* __restr
     }
 }
 
+// Weight gradient.  With p' = p + (0, kx - 1) the sum becomes
+//   dW[co][ky][kx][ci] = sum_p' g[p'_y][p'_x + 1 - kx][co] x[p'_y + ky - 1][p'_x][ci],
+// so the input needs only row shifts (one transposed copy, rows y0 - 1 .. y0 + 4 of the tile's 16 columns)
+// and the output gradient the column shifts (three transposed copies, one per kx).  Both are filled from
+// pairs of adjacent pixels with 4-byte LDS writes.
 template <int CI, int CO>
 __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* __restrict__ x,
                                                                  const __bf16* __restrict__ g, int H, int W,
                                                                  int tiles_x, int tiles_y, int n_tiles,
                                                                  float* __restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) unsigned char cv_dyn[];
-    __bf16* xT = reinterpret_cast<__bf16*>(cv_dyn);      // [3 shifts][CI][kXB]
-    __bf16* gT = xT + 3 * CI * kXB;                       // [CO][kGL]
+    __bf16* xT = reinterpret_cast<__bf16*>(cv_dyn);      // [CI][kXB]: rows y0 - 1 .. y0 + 4, 16 columns
+    __bf16* gT = xT + CI * kXB;                           // [3 (kx)][CO][kGL]: column j holds g at x0 + j + 1 - kx
     constexpr int CT = CI / 16, OT = CO / 16, PAIRS = CT * OT / 4;
     constexpr int CHI = CI / 8, CHO = CO / 8;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
@@ -182,61 +187,70 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
         for (int t = 0; t < 9; ++t) acc[p][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float db[8] = {};
     const int per_img = tiles_x * tiles_y;
-    // the next tile's input halo and output gradient are loaded into registers while this tile is
-    // computed: input chunk c = threadIdx.x + kThreads k of (kWTH + 2) x kHW pixels x CI / 8 parts, output
-    // chunk c of kWTH x 16 pixels x CO / 8 parts
-    constexpr int NXC = (kWTH + 2) * kHW * CHI, NXP = (NXC + kThreads - 1) / kThreads;
-    constexpr int NGC = kWTH * kTW * CHO, NGP = (NGC + kThreads - 1) / kThreads;
-    bf16x8 px[NXP], pg[NGP];
+    // the next tile is loaded into registers while this one is computed.  Input item i = threadIdx.x +
+    // kThreads k: halo row, column pair, channel part (pixels x0 + 2 jp, + 1); output-gradient item: tile row,
+    // column pair, channel part (pixels x0 + 2 jp - 1 .. x0 + 2 jp + 2)
+    constexpr int NXI = (kWTH + 2) * (kTW / 2) * CHI, NXP = (NXI + kThreads - 1) / kThreads;
+    constexpr int NGI = kWTH * (kTW / 2) * CHO, NGP = (NGI + kThreads - 1) / kThreads;
+    bf16x8 px[NXP][2], pg[NGP][4];
     auto load_tile = [&](int tile) {
         const int img = tile / per_img, rem = tile - img * per_img;
         const int y0 = (rem / tiles_x) * kWTH, x0 = (rem % tiles_x) * kTW;
 #pragma unroll
         for (int k = 0; k < NXP; ++k) {
-            const int c = threadIdx.x + kThreads * k;
-            const int pix = c / CHI, part = c - pix * CHI;
-            const int hy = pix / kHW, hx = pix - hy * kHW;
-            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-            px[k] = zero8();
-            if (c < NXC && gy >= 0 && gy < H && gx >= 0 && gx < W)
-                px[k] = ld8(x + ((static_cast<size_t>(img) * H + gy) * W + gx) * CI + 8 * part);
-        }
+            const int it = threadIdx.x + kThreads * k;
+            const int part = it % CHI, pr = it / CHI, jp = pr % (kTW / 2), hy = pr / (kTW / 2);
+            const int gy = y0 - 1 + hy;
 #pragma unroll
-        for (int k = 0; k < NGP; ++k) {
-            const int c = threadIdx.x + kThreads * k;
-            const int pix = c / CHO, part = c - pix * CHO;
-            const int gy = y0 + pix / kTW, gx = x0 + pix % kTW;
-            pg[k] = zero8();
-            if (c < NGC && gy < H && gx < W) pg[k] = ld8(g + ((static_cast<size_t>(img) * H + gy) * W + gx) * CO + 8 * part);
-        }
-    };
-    if (static_cast<int>(blockIdx.x) < n_tiles) load_tile(blockIdx.x);
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        __syncthreads();
-        // input halo rows y0 - 1 .. y0 + kWTH, columns x0 - 1 .. x0 + 16; copy s holds column j + s - 1
-#pragma unroll
-        for (int k = 0; k < NXP; ++k) {
-            const int c = threadIdx.x + kThreads * k;
-            if (c >= NXC) continue;
-            const int pix = c / CHI, part = c - pix * CHI;
-            const int hy = pix / kHW, hx = pix - hy * kHW;
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                const int j = hx - s;
-                if (j < 0 || j >= kTW) continue;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) xT[(s * CI + 8 * part + e) * kXB + hy * kXR + j] = px[k][e];
+            for (int u = 0; u < 2; ++u) {
+                const int gx = x0 + 2 * jp + u;
+                px[k][u] = zero8();
+                if (it < NXI && gy >= 0 && gy < H && gx < W)
+                    px[k][u] = ld8(x + ((static_cast<size_t>(img) * H + gy) * W + gx) * CI + 8 * part);
             }
         }
 #pragma unroll
         for (int k = 0; k < NGP; ++k) {
-            const int c = threadIdx.x + kThreads * k;
-            if (c >= NGC) continue;
-            const int pix = c / CHO, part = c - pix * CHO;
+            const int it = threadIdx.x + kThreads * k;
+            const int part = it % CHO, pr = it / CHO, jp = pr % (kTW / 2), row = pr / (kTW / 2);
+            const int gy = y0 + row;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int gx = x0 + 2 * jp - 1 + u;
+                pg[k][u] = zero8();
+                if (it < NGI && gy < H && gx >= 0 && gx < W)
+                    pg[k][u] = ld8(g + ((static_cast<size_t>(img) * H + gy) * W + gx) * CO + 8 * part);
+            }
+        }
+    };
+    auto pair = [](__bf16 lo, __bf16 hi) {
+        return static_cast<unsigned>(__builtin_bit_cast(unsigned short, lo)) |
+               (static_cast<unsigned>(__builtin_bit_cast(unsigned short, hi)) << 16);
+    };
+    if (static_cast<int>(blockIdx.x) < n_tiles) load_tile(blockIdx.x);
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NXP; ++k) {
+            const int it = threadIdx.x + kThreads * k;
+            if (it >= NXI) continue;
+            const int part = it % CHI, pr = it / CHI, jp = pr % (kTW / 2), hy = pr / (kTW / 2);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *reinterpret_cast<unsigned*>(xT + (8 * part + e) * kXB + hy * kTW + 2 * jp) = pair(px[k][0][e], px[k][1][e]);
+        }
+#pragma unroll
+        for (int k = 0; k < NGP; ++k) {
+            const int it = threadIdx.x + kThreads * k;
+            if (it >= NGI) continue;
+            const int part = it % CHO, pr = it / CHO, jp = pr % (kTW / 2), row = pr / (kTW / 2);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                gT[(8 * part + e) * kGL + pix] = pg[k][e];
-                db[e] += static_cast<float>(pg[k][e]);
+                const int o = (8 * part + e) * kGL + row * kTW + 2 * jp;
+                *reinterpret_cast<unsigned*>(gT + o) = pair(pg[k][2][e], pg[k][3][e]);                   // kx = 0
+                *reinterpret_cast<unsigned*>(gT + CO * kGL + o) = pair(pg[k][1][e], pg[k][2][e]);        // kx = 1
+                *reinterpret_cast<unsigned*>(gT + 2 * CO * kGL + o) = pair(pg[k][0][e], pg[k][1][e]);    // kx = 2
+                db[e] += static_cast<float>(pg[k][1][e]) + static_cast<float>(pg[k][2][e]);
             }
         }
         __syncthreads();
@@ -249,12 +263,13 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
 #pragma unroll
             for (int p = 0; p < PAIRS; ++p) {
                 const int idx = wv * PAIRS + p, ot = idx / CT, ct = idx - ot * CT;
-                const bf16x8 av = ld8(gT + (16 * ot + r) * kGL + 32 * ks + 8 * q);
+                bf16x8 av[3], bv[3];
 #pragma unroll
-                for (int t = 0; t < 9; ++t) {
-                    const int ky = t / 3, kx = t % 3;
-                    acc[p][t] = mfma(av, ld8(xT + (kx * CI + 16 * ct + r) * kXB + (row + ky) * kXR + col), acc[p][t]);
-                }
+                for (int kx = 0; kx < 3; ++kx) av[kx] = ld8(gT + (kx * CO + 16 * ot + r) * kGL + 32 * ks + 8 * q);
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky) bv[ky] = ld8(xT + (16 * ct + r) * kXB + (row + ky) * kTW + col);
+#pragma unroll
+                for (int t = 0; t < 9; ++t) acc[p][t] = mfma(av[t % 3], bv[t / 3], acc[p][t]);
             }
         }
     }
@@ -267,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
 #pragma unroll
             for (int i = 0; i < 4; ++i) out[((16 * ot + 4 * q + i) * 9 + t) * CI + 16 * ct + r] = acc[p][t][i];
     }
-    // bias gradient: thread t always loaded channel chunk t % CHO
+    // bias gradient: thread t always loaded channel part t % CHO
     __syncthreads();
     float* red = reinterpret_cast<float*>(cv_dyn);
 #pragma unroll
@@ -283,7 +298,8 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
 
 template <int CI, int CO>
 constexpr size_t wgrad_lds() {
-    return static_cast<size_t>(3 * CI * kXB + CO * kGL) * sizeof(__bf16);
+    const size_t b = static_cast<size_t>(CI * kXB + 3 * CO * kGL) * sizeof(__bf16);
+    return b > kThreads * 8 * sizeof(float) ? b : kThreads * 8 * sizeof(float);
 }
 
 // out[j] = sum over partials b of partial[b][j], fixed order: kSlices runs, then the runs.
