@@ -169,15 +169,20 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const __bf16* __restr
 // so the input needs only row shifts (one transposed copy, rows y0 - 1 .. y0 + 4 of the tile's 16 columns)
 // and the output gradient the column shifts (three transposed copies, one per kx).  Both are filled from
 // pairs of adjacent pixels with 4-byte LDS writes.
+// threads of a weight-gradient workgroup: 8 waves when there are 16 (output, input) channel-tile pairs, so
+// that each wave holds the accumulators of two pairs (4 would take the registers of two waves per SIMD)
 template <int CI, int CO>
-__global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* __restrict__ x,
+constexpr int wgrad_threads() { return (CI / 16) * (CO / 16) >= 16 ? 512 : 256; }
+
+template <int CI, int CO>
+__global__ __launch_bounds__((wgrad_threads<CI, CO>())) void conv3x3_wgrad_kernel(const __bf16* __restrict__ x,
                                                                  const __bf16* __restrict__ g, int H, int W,
                                                                  int tiles_x, int tiles_y, int n_tiles,
                                                                  float* __restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) unsigned char cv_dyn[];
     __bf16* xT = reinterpret_cast<__bf16*>(cv_dyn);      // [CI][kXB]: rows y0 - 1 .. y0 + 4, 16 columns
     __bf16* gT = xT + CI * kXB;                           // [3 (kx)][CO][kGL]: column j holds g at x0 + j + 1 - kx
-    constexpr int CT = CI / 16, OT = CO / 16, PAIRS = CT * OT / 4;
+    constexpr int NT = wgrad_threads<CI, CO>(), CT = CI / 16, OT = CO / 16, PAIRS = CT * OT / (NT / 64);
     constexpr int CHI = CI / 8, CHO = CO / 8;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
     f32x4 acc[PAIRS][9];
@@ -188,17 +193,17 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
     float db[8] = {};
     const int per_img = tiles_x * tiles_y;
     // the next tile is loaded into registers while this one is computed.  Input item i = threadIdx.x +
-    // kThreads k: halo row, column pair, channel part (pixels x0 + 2 jp, + 1); output-gradient item: tile row,
+    // NT k: halo row, column pair, channel part (pixels x0 + 2 jp, + 1); output-gradient item: tile row,
     // column pair, channel part (pixels x0 + 2 jp - 1 .. x0 + 2 jp + 2)
-    constexpr int NXI = (kWTH + 2) * (kTW / 2) * CHI, NXP = (NXI + kThreads - 1) / kThreads;
-    constexpr int NGI = kWTH * (kTW / 2) * CHO, NGP = (NGI + kThreads - 1) / kThreads;
+    constexpr int NXI = (kWTH + 2) * (kTW / 2) * CHI, NXP = (NXI + NT - 1) / NT;
+    constexpr int NGI = kWTH * (kTW / 2) * CHO, NGP = (NGI + NT - 1) / NT;
     bf16x8 px[NXP][2], pg[NGP][4];
     auto load_tile = [&](int tile) {
         const int img = tile / per_img, rem = tile - img * per_img;
         const int y0 = (rem / tiles_x) * kWTH, x0 = (rem % tiles_x) * kTW;
 #pragma unroll
         for (int k = 0; k < NXP; ++k) {
-            const int it = threadIdx.x + kThreads * k;
+            const int it = threadIdx.x + NT * k;
             const int part = it % CHI, pr = it / CHI, jp = pr % (kTW / 2), hy = pr / (kTW / 2);
             const int gy = y0 - 1 + hy;
 #pragma unroll
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
         }
 #pragma unroll
         for (int k = 0; k < NGP; ++k) {
-            const int it = threadIdx.x + kThreads * k;
+            const int it = threadIdx.x + NT * k;
             const int part = it % CHO, pr = it / CHO, jp = pr % (kTW / 2), row = pr / (kTW / 2);
             const int gy = y0 + row;
 #pragma unroll
@@ -232,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NXP; ++k) {
-            const int it = threadIdx.x + kThreads * k;
+            const int it = threadIdx.x + NT * k;
             if (it >= NXI) continue;
             const int part = it % CHI, pr = it / CHI, jp = pr % (kTW / 2), hy = pr / (kTW / 2);
 #pragma unroll
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
         }
 #pragma unroll
         for (int k = 0; k < NGP; ++k) {
-            const int it = threadIdx.x + kThreads * k;
+            const int it = threadIdx.x + NT * k;
             if (it >= NGI) continue;
             const int part = it % CHO, pr = it / CHO, jp = pr % (kTW / 2), row = pr / (kTW / 2);
 #pragma unroll
@@ -291,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
     if (threadIdx.x < CO) {
         const int part = threadIdx.x / 8, e = threadIdx.x % 8;
         float s = 0.0f;
-        for (int t = part; t < kThreads; t += CHO) s += red[t * 8 + e];
+        for (int t = part; t < NT; t += CHO) s += red[t * 8 + e];
         out[CO * 9 * CI + threadIdx.x] = s;
     }
 }
@@ -299,7 +304,8 @@ __global__ __launch_bounds__(kThreads) void conv3x3_wgrad_kernel(const __bf16* _
 template <int CI, int CO>
 constexpr size_t wgrad_lds() {
     const size_t b = static_cast<size_t>(CI * kXB + 3 * CO * kGL) * sizeof(__bf16);
-    return b > kThreads * 8 * sizeof(float) ? b : kThreads * 8 * sizeof(float);
+    const size_t r = static_cast<size_t>(wgrad_threads<CI, CO>()) * 8 * sizeof(float);
+    return b > r ? b : r;
 }
 
 // out[j] = sum over partials b of partial[b][j], fixed order: kSlices runs, then the runs.
@@ -565,7 +571,7 @@ int launch_wgrad(const __bf16* x, const __bf16* g, int n, int H, int W, float* g
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         attr = true;
     }
-    conv3x3_wgrad_kernel<CI, CO><<<blocks, kThreads, lds, st>>>(x, g, H, W, tx, ty, static_cast<int>(tiles), ws);
+    conv3x3_wgrad_kernel<CI, CO><<<blocks, wgrad_threads<CI, CO>(), lds, st>>>(x, g, H, W, tx, ty, static_cast<int>(tiles), ws);
     if (int s = launch_status("pact_conv3x3_wgrad_bf16")) return s;
     float* part2 = ws + static_cast<size_t>(blocks) * nout;
     sum_partials1_kernel<<<dim3(ceil_div(nout, 256), kSlices), 256, 0, st>>>(ws, blocks, nout, part2);
