@@ -238,7 +238,7 @@ def main():
         "sos_to_delays": ("rays_fwd_kernel", "alu", samples * FLOPS_PER_SAMPLE_FWD, "flop"),
         "loss_and_grad": ("loss_grad_kernel + loss_finish_kernel", "hbm",
                           N * M * Pp * (Pp // 2 + 1) * 8 + 2 * rays_io + 4, "byte"),   # Y once, w in, dL/dw out
-        "sos_to_delays_adjoint": ("rays_adj_grid_kernel + rays_adj_reduce1_kernel + rays_adj_reduce2_kernel", "alu",
+        "sos_to_delays_adjoint": ("rays_adj_grid_kernel + rays_adj_reduce_kernel", "alu",
                                   samples * FLOPS_PER_SAMPLE_ADJ, "flop"),
         # sos in, sos out, m and v read and written, grad, mask
         "tv_adam_step": ("tv_adam_kernel", "hbm", G2 * (4 * 7 + 1) + 12, "byte"),

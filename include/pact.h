@@ -162,9 +162,8 @@ PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v
  * with dw/dv = dl v0 / v^2 at every sample spread by the bilinear weights.
  * scale: optional DEVICE scalar (NULL = 1).  accumulate != 0 adds to dL_dsos.
  * ws: DEVICE workspace of pact_sos_to_delays_adjoint_workspace_size() bytes,
- * which depends on the current device's CU count (one partial node grid per CU,
- * plus 16 for the second level of their sum, when 2 (G+2)^2 floats fit in LDS;
- * else 0 and ws may be NULL); not shared by two calls in flight.  The per-CU sums are exact integer sums at a fixed-point
+ * which depends on the current device's CU count (one partial node grid per CU
+ * when 2 (G+2)^2 floats fit in LDS; else 0 and ws may be NULL); not shared by two calls in flight.  The per-CU sums are exact integer sums at a fixed-point
  * scale and are combined in a fixed order, so the result is deterministic; a
  * non-finite SOS node, or one at or below zero, makes the result NaN. */
 PACT_API size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg, int N, const pact_ring* ring);

@@ -491,43 +491,42 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     }
 }
 
-// Sum of the per-workgroup partial grids in a fixed order, in two levels so that the 20 MB of partials
-// are read by many workgroups with many loads in flight: level 1 sums, for every node, each of kSlices
-// contiguous runs of partials (in order) into part2 [kSlices][n_nodes]; level 2 sums the slices in order
-// into out (= or +=).
+// Sum of the per-workgroup partial grids in a fixed order.  A workgroup owns 64 consecutive nodes; its
+// wave s sums, for those nodes, the s-th of kSlices contiguous runs of partials (in order), so that every
+// load of a wave is one 256-byte row and each lane has 16 loads in flight; the kSlices run sums then meet
+// in LDS and are added in order (= or += into out).
 constexpr int kSlices = 16;
+constexpr int kReduceNodes = 64;
 
-__global__ __launch_bounds__(256) void rays_adj_reduce1_kernel(const float* __restrict__ partial, int n_part,
-                                                              int n_nodes, float* __restrict__ part2) {
-    const int node = blockIdx.x * 256 + threadIdx.x;
-    const int slice = blockIdx.y;
-    if (node >= n_nodes) return;
-    const int per = (n_part + kSlices - 1) / kSlices;
-    const int p0 = slice * per, p1 = min(p0 + per, n_part);
+__global__ __launch_bounds__(kSlices * kReduceNodes) void rays_adj_reduce_kernel(const float* __restrict__ partial,
+                                                                                 int n_part, int n_nodes,
+                                                                                 int accumulate,
+                                                                                 float* __restrict__ out) {
+    __shared__ float run[kSlices][kReduceNodes];
+    const int j = threadIdx.x % kReduceNodes, slice = threadIdx.x / kReduceNodes;
+    const int node = blockIdx.x * kReduceNodes + j;
     float s = 0.0f;
-    int p = p0;
-    for (; p + 8 <= p1; p += 8) {
-        float v[8];
+    if (node < n_nodes) {
+        const int per = (n_part + kSlices - 1) / kSlices;
+        const int p0 = slice * per, p1 = min(p0 + per, n_part);
+        int p = p0;
+        for (; p + 8 <= p1; p += 8) {
+            float v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = partial[static_cast<size_t>(p + k) * n_nodes + node];
+            for (int k = 0; k < 8; ++k) v[k] = partial[static_cast<size_t>(p + k) * n_nodes + node];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s += v[k];
+            for (int k = 0; k < 8; ++k) s += v[k];
+        }
+        for (; p < p1; ++p) s += partial[static_cast<size_t>(p) * n_nodes + node];
     }
-    for (; p < p1; ++p) s += partial[static_cast<size_t>(p) * n_nodes + node];
-    part2[static_cast<size_t>(slice) * n_nodes + node] = s;
-}
-
-__global__ __launch_bounds__(256) void rays_adj_reduce2_kernel(const float* __restrict__ part2, int n_nodes,
-                                                              int accumulate, float* __restrict__ out) {
-    const int node = blockIdx.x * 256 + threadIdx.x;
-    if (node >= n_nodes) return;
-    float v[kSlices];
+    run[slice][j] = s;
+    __syncthreads();
+    if (slice == 0 && node < n_nodes) {
+        float t = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kSlices; ++k) v[k] = part2[static_cast<size_t>(k) * n_nodes + node];
-    float s = 0.0f;
-#pragma unroll
-    for (int k = 0; k < kSlices; ++k) s += v[k];
-    out[node] = accumulate ? out[node] + s : s;
+        for (int k = 0; k < kSlices; ++k) t += run[k][j];
+        out[node] = accumulate ? out[node] + t : t;
+    }
 }
 
 RayGeo make_geo(const pact_grid& sosg, int n_samples) {
@@ -658,7 +657,7 @@ extern "C" size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sos
     (void)ring_;
     if (!sosg_ || sosg_->ny <= 0 || sosg_->nx <= 0) return 0;
     if (!pact::adj_grid_lds(*sosg_)) return 0;
-    return static_cast<size_t>(pact::device_cu_count() + pact::kSlices) * sosg_->ny * sosg_->nx * sizeof(float);
+    return static_cast<size_t>(pact::device_cu_count()) * sosg_->ny * sosg_->nx * sizeof(float);
 }
 
 extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg_, float v0, const float* centres,
@@ -677,7 +676,7 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     PACT_CHECK_ARG(dL_dw && dL_dsos, "pact_sos_to_delays_adjoint: null pointer");
     if (const size_t glds = adj_grid_lds(sosg)) {
         const int blocks = device_cu_count();
-        const size_t need = static_cast<size_t>(blocks + kSlices) * sosg.ny * sosg.nx * sizeof(float);
+        const size_t need = static_cast<size_t>(blocks) * sosg.ny * sosg.nx * sizeof(float);
         if (!ws || ws_bytes < need) {
             set_error("pact_sos_to_delays_adjoint: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
             return PACT_EWORKSPACE;
@@ -700,12 +699,8 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
             n_items, per_block, dL_dw, scale, partial);
         if (int st = launch_status("pact_sos_to_delays_adjoint")) return st;
         const int n_nodes = sosg.ny * sosg.nx;
-        float* part2 = partial + static_cast<size_t>(blocks) * n_nodes;
-        rays_adj_reduce1_kernel<<<dim3(ceil_div(n_nodes, 256), kSlices), 256, 0, as_stream(stream)>>>(
-            partial, blocks, n_nodes, part2);
-        if (int st = launch_status("pact_sos_to_delays_adjoint")) return st;
-        rays_adj_reduce2_kernel<<<ceil_div(n_nodes, 256), 256, 0, as_stream(stream)>>>(part2, n_nodes, accumulate,
-                                                                                      dL_dsos);
+        rays_adj_reduce_kernel<<<ceil_div(n_nodes, kReduceNodes), kSlices * kReduceNodes, 0, as_stream(stream)>>>(
+            partial, blocks, n_nodes, accumulate, dL_dsos);
         return launch_status("pact_sos_to_delays_adjoint");
     }
     const size_t lds = static_cast<size_t>(kTile + 2) * (kTile + 2) * kAdjThreads * sizeof(float) +
