@@ -52,6 +52,10 @@ constexpr int kThreads = 1024;    // forward workgroup
 #endif
 constexpr int kTile = PACT_ADJ_TILE;  // adjoint tile side (nodes)
 constexpr int kAdjThreads = 256;      // adjoint workgroup
+// loads in flight per thread while a workgroup stages the contrast grid (the forward is slower with 8:
+// its 2 workgroups per CU then stage at once)
+constexpr int kStageFwd = 4;
+constexpr int kStageAdj = 8;
 
 struct RayGeo {
     float inv_ds;       // 1 / node spacing
@@ -87,6 +91,56 @@ __device__ __forceinline__ float block_max(float v, float* red) {
     const int nw = (blockDim.x + 63) >> 6;
     for (int i = 1; i < nw; ++i) t = fmaxf(t, red[i]);
     return t;
+}
+
+// q = idx / W and r = idx % W for 0 <= idx < 2^22: a float reciprocal gives q to within one, and one
+// correction step each way makes it exact (an integer division costs about 25 instructions here).
+__device__ __forceinline__ void divmod_small(int idx, int W, float invW, int& q, int& r) {
+    q = static_cast<int>((static_cast<float>(idx) + 0.5f) * invW);
+    r = idx - q * W;
+    if (r < 0) {
+        --q;
+        r += W;
+    } else if (r >= W) {
+        ++q;
+        r -= W;
+    }
+}
+
+// Stage the contrast sos - v0 of the Gy x Gx node grid into vs [(Gy + 2)][W] with a one-node ring of zeros
+// (padded node (r, c) is grid node (r - 1, c - 1)).  Each thread loads kStage nodes before it stores
+// any, so that those loads are in flight together (a load and its wait per node would serialise some
+// twenty round trips to L2 in every workgroup).  With acc, the same nodes of acc are cleared; vmin
+// and nan_check receive the smallest v and 0 * (every contrast) (NaN if any node is not finite).
+template <int kStage>
+__device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, float v0, const RayGeo& g, float* vs,
+                                               int* acc, float& vmin, float& nan_check) {
+    const int W = g.W, total = (g.Gy + 2) * W;
+    const float invW = 1.0f / static_cast<float>(W);
+    for (int idx0 = threadIdx.x; idx0 < total; idx0 += kStage * blockDim.x) {
+        float d[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = idx0 + u * static_cast<int>(blockDim.x);
+            int r, c;
+            divmod_small(idx, W, invW, r, c);
+            const int a = r - 1, b = c - 1;
+            // an unconditional load (of node 0 for the ring), so that no branch separates the loads
+            const bool in = idx < total && a >= 0 && a < g.Gy && b >= 0 && b < g.Gx;
+            const float x = sos[in ? a * g.Gx + b : 0];
+            d[u] = in ? x - v0 : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = idx0 + u * static_cast<int>(blockDim.x);
+            if (idx < total) {
+                vs[idx] = d[u];
+                if (acc) acc[idx] = 0;
+                vmin = fminf(vmin, v0 + d[u]);
+                nan_check += 0.0f * d[u];
+            }
+        }
+    }
 }
 
 // Geometry of ray (centre c, element e): padded node coordinates of the start point and their
@@ -129,10 +183,9 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
                                                             float R, float phi0, int Ns, RayGeo g, int K,
                                                             int n_items, float* __restrict__ w) {
     extern __shared__ float vs[];
-    const int total = (g.Gy + 2) * g.W;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int a = idx / g.W - 1, b = idx % g.W - 1;
-        vs[idx] = (a >= 0 && a < g.Gy && b >= 0 && b < g.Gx) ? sos[a * g.Gx + b] - v0 : 0.0f;
+    {
+        float vmin = v0, nan_check = 0.0f;   // not used by the forward
+        stage_contrast<kStageFwd>(sos, v0, g, vs, nullptr, vmin, nan_check);
     }
     __syncthreads();
     // K divides the workgroup size and n_items = rays * K, so the K lanes of a ray enter and leave the
@@ -401,14 +454,7 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     float* red = reinterpret_cast<float*>(acc + total);     // kGridThreads / 64 floats
     const int tid = threadIdx.x;
     float vmin = v0, nan_check = 0.0f;                     // nan_check turns NaN if any node is not finite
-    for (int idx = tid; idx < total; idx += blockDim.x) {
-        const int a = idx / W - 1, b = idx % W - 1;
-        const float d = (a >= 0 && a < g.Gy && b >= 0 && b < g.Gx) ? sos[a * g.Gx + b] - v0 : 0.0f;
-        vs[idx] = d;
-        acc[idx] = 0;
-        vmin = fminf(vmin, v0 + d);
-        nan_check += 0.0f * d;
-    }
+    stage_contrast<kStageAdj>(sos, v0, g, vs, acc, vmin, nan_check);
     vmin = -block_max(-vmin, red);
     const int it0 = blockIdx.x * per_block;
     const int it1 = min(it0 + per_block, n_items);
@@ -485,46 +531,42 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     const float invF = 1.0f / F;
     const float bad = __builtin_nanf("");
     float* part = partial + static_cast<size_t>(blockIdx.x) * g.Gy * g.Gx;
+    const float invGx = 1.0f / static_cast<float>(g.Gx);
     for (int idx = tid; idx < g.Gy * g.Gx; idx += blockDim.x) {
-        const int a = idx / g.Gx, b = idx - a * g.Gx;
+        int a, b;
+        divmod_small(idx, g.Gx, invGx, a, b);
         part[idx] = ok ? static_cast<float>(acc[(a + 1) * W + b + 1]) * invF : bad;
     }
 }
 
 // Sum of the per-workgroup partial grids in a fixed order.  A workgroup owns 64 consecutive nodes; its
-// wave s sums, for those nodes, the s-th of kSlices contiguous runs of partials (in order), so that every
-// load of a wave is one 256-byte row and each lane has 16 loads in flight; the kSlices run sums then meet
-// in LDS and are added in order (= or += into out).
-constexpr int kSlices = 16;
+// wave s sums, for those nodes, the s-th of kAdjSlices contiguous runs of partials (in order), so that
+// every load of a wave is one 256-byte row and each lane has 8 loads in flight; the run sums then meet in
+// LDS and are added in order (= or += into out).
+constexpr int kAdjSlices = 16;
+
+// Run `slice` of the kAdjSlices contiguous runs of the n_part partials at one node, added in order.
+__device__ __forceinline__ float adj_run_sum(const float* __restrict__ partial, int n_part, int n_nodes, int node,
+                                             int slice) {
+    const int per = (n_part + kAdjSlices - 1) / kAdjSlices;
+    const int p0 = slice * per, p1 = min(p0 + per, n_part);
+    return p1 > p0 ? ordered_strided_sum(partial + static_cast<size_t>(p0) * n_nodes + node, p1 - p0, n_nodes)
+                   : 0.0f;
+}
+
 constexpr int kReduceNodes = 64;
 
-__global__ __launch_bounds__(kSlices * kReduceNodes) void rays_adj_reduce_kernel(const float* __restrict__ partial,
-                                                                                 int n_part, int n_nodes,
-                                                                                 int accumulate,
-                                                                                 float* __restrict__ out) {
-    __shared__ float run[kSlices][kReduceNodes];
+__global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_kernel(
+    const float* __restrict__ partial, int n_part, int n_nodes, int accumulate, float* __restrict__ out) {
+    __shared__ float run[kAdjSlices][kReduceNodes];
     const int j = threadIdx.x % kReduceNodes, slice = threadIdx.x / kReduceNodes;
     const int node = blockIdx.x * kReduceNodes + j;
-    float s = 0.0f;
-    if (node < n_nodes) {
-        const int per = (n_part + kSlices - 1) / kSlices;
-        const int p0 = slice * per, p1 = min(p0 + per, n_part);
-        int p = p0;
-        for (; p + 8 <= p1; p += 8) {
-            float v[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = partial[static_cast<size_t>(p + k) * n_nodes + node];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) s += v[k];
-        }
-        for (; p < p1; ++p) s += partial[static_cast<size_t>(p) * n_nodes + node];
-    }
-    run[slice][j] = s;
+    run[slice][j] = node < n_nodes ? adj_run_sum(partial, n_part, n_nodes, node, slice) : 0.0f;
     __syncthreads();
     if (slice == 0 && node < n_nodes) {
         float t = 0.0f;
 #pragma unroll
-        for (int k = 0; k < kSlices; ++k) t += run[k][j];
+        for (int k = 0; k < kAdjSlices; ++k) t += run[k][j];
         out[node] = accumulate ? out[node] + t : t;
     }
 }
@@ -632,6 +674,7 @@ size_t adj_grid_lds(const pact_grid& sosg) {
     return lds <= kLdsBytes ? lds : 0;
 }
 
+
 // Segments per ray for rays_adj_grid_kernel: the K that minimises the critical path of one lane, rounds of
 // items times (segment length + a ray set-up worth about two samples), with at least 8 samples a segment.
 int adj_segments(long long n_rays, int n_samples, long long lanes) {
@@ -647,6 +690,36 @@ int adj_segments(long long n_rays, int n_samples, long long lanes) {
         }
     }
     return best;
+}
+
+// The grid adjoint into one partial node grid per CU (the caller sums them); *n_part = their count.
+int launch_adj_grid(const float* sos, const pact_grid& sosg, float v0, const float* centres, int N,
+                    const pact_ring& ring, int n_samples, const float* dL_dw, const float* scale, float* partial,
+                    size_t ws_bytes, hipStream_t st, int* n_part, const char* what) {
+    const size_t glds = adj_grid_lds(sosg);
+    const int blocks = device_cu_count();
+    const size_t need = static_cast<size_t>(blocks) * sosg.ny * sosg.nx * sizeof(float);
+    if (!partial || ws_bytes < need) {
+        set_error("%s: workspace of %zu bytes needed, %zu given", what, need, partial ? ws_bytes : 0);
+        return PACT_EWORKSPACE;
+    }
+    static bool gattr = false;
+    if (!gattr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        gattr = true;
+    }
+    const long long n_rays = static_cast<long long>(N) * ring.n_elem;
+    const int tuned = tuned_tiling(N, ring, n_samples, sosg).adj;
+    const int K = tuned > 0 ? tuned : adj_segments(n_rays, n_samples, static_cast<long long>(blocks) * kGridThreads);
+    PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "%s: too many ray segments", what);
+    const int n_items = static_cast<int>(n_rays * K);
+    const int per_block = ceil_div(n_items, blocks);
+    rays_adj_grid_kernel<<<blocks, kGridThreads, glds, st>>>(sos, v0, centres, N, ring.n_elem, ring.radius,
+                                                            ring.phi0, n_samples, make_geo(sosg, n_samples), K,
+                                                            n_items, per_block, dL_dw, scale, partial);
+    *n_part = blocks;
+    return launch_status(what);
 }
 
 }  // namespace
@@ -674,33 +747,15 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     clear_error();
     if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_sos_to_delays_adjoint")) return s;
     PACT_CHECK_ARG(dL_dw && dL_dsos, "pact_sos_to_delays_adjoint: null pointer");
-    if (const size_t glds = adj_grid_lds(sosg)) {
-        const int blocks = device_cu_count();
-        const size_t need = static_cast<size_t>(blocks) * sosg.ny * sosg.nx * sizeof(float);
-        if (!ws || ws_bytes < need) {
-            set_error("pact_sos_to_delays_adjoint: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
-            return PACT_EWORKSPACE;
-        }
-        static bool gattr = false;
-        if (!gattr) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
-            gattr = true;
-        }
-        const long long n_rays = static_cast<long long>(N) * ring.n_elem;
-        const int tuned = tuned_tiling(N, ring, n_samples, sosg).adj;
-        const int K = tuned > 0 ? tuned : adj_segments(n_rays, n_samples, static_cast<long long>(blocks) * kGridThreads);
-        PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "pact_sos_to_delays_adjoint: too many ray segments");
-        const int n_items = static_cast<int>(n_rays * K);
-        const int per_block = ceil_div(n_items, blocks);
+    if (adj_grid_lds(sosg)) {
         float* partial = static_cast<float*>(ws);
-        rays_adj_grid_kernel<<<blocks, kGridThreads, glds, as_stream(stream)>>>(
-            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), K,
-            n_items, per_block, dL_dw, scale, partial);
-        if (int st = launch_status("pact_sos_to_delays_adjoint")) return st;
+        int n_part = 0;
+        if (int st = launch_adj_grid(sos, sosg, v0, centres, N, ring, n_samples, dL_dw, scale, partial, ws_bytes,
+                                     as_stream(stream), &n_part, "pact_sos_to_delays_adjoint"))
+            return st;
         const int n_nodes = sosg.ny * sosg.nx;
-        rays_adj_reduce_kernel<<<ceil_div(n_nodes, kReduceNodes), kSlices * kReduceNodes, 0, as_stream(stream)>>>(
-            partial, blocks, n_nodes, accumulate, dL_dsos);
+        rays_adj_reduce_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(
+            partial, n_part, n_nodes, accumulate, dL_dsos);
         return launch_status("pact_sos_to_delays_adjoint");
     }
     const size_t lds = static_cast<size_t>(kTile + 2) * (kTile + 2) * kAdjThreads * sizeof(float) +
