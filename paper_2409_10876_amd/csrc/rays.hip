@@ -52,10 +52,9 @@ constexpr int kThreads = 1024;    // forward workgroup
 #endif
 constexpr int kTile = PACT_ADJ_TILE;  // adjoint tile side (nodes)
 constexpr int kAdjThreads = 256;      // adjoint workgroup
-// loads in flight per thread while a workgroup stages the contrast grid (the forward is slower with 8:
-// its 2 workgroups per CU then stage at once)
-constexpr int kStageFwd = 4;
-constexpr int kStageAdj = 8;
+// padded rows a wave loads before storing them while a workgroup stages the contrast grid (1, 2 and 3
+// time the same at 140^2 nodes)
+constexpr int kStageRows = 2;
 
 struct RayGeo {
     float inv_ds;       // 1 / node spacing
@@ -93,51 +92,54 @@ __device__ __forceinline__ float block_max(float v, float* red) {
     return t;
 }
 
-// q = idx / W and r = idx % W for 0 <= idx < 2^22: a float reciprocal gives q to within one, and one
-// correction step each way makes it exact (an integer division costs about 25 instructions here).
-__device__ __forceinline__ void divmod_small(int idx, int W, float invW, int& q, int& r) {
-    q = static_cast<int>((static_cast<float>(idx) + 0.5f) * invW);
-    r = idx - q * W;
-    if (r < 0) {
-        --q;
-        r += W;
-    } else if (r >= W) {
-        ++q;
-        r -= W;
-    }
-}
-
 // Stage the contrast sos - v0 of the Gy x Gx node grid into vs [(Gy + 2)][W] with a one-node ring of zeros
-// (padded node (r, c) is grid node (r - 1, c - 1)).  Each thread loads kStage nodes before it stores
-// any, so that those loads are in flight together (a load and its wait per node would serialise some
-// twenty round trips to L2 in every workgroup).  With acc, the same nodes of acc are cleared; vmin
-// and nan_check receive the smallest v and 0 * (every contrast) (NaN if any node is not finite).
-template <int kStage>
+// (padded node (r, c) is grid node (r - 1, c - 1)).  Wave w takes padded rows w, w + waves, ... and lane l
+// the columns l, l + 64, ... of each (at most kStageChunks, which covers every grid that fits in LDS), so
+// that rows and chunks are wave-uniform and no node needs a division.  kRows rows are loaded before any
+// is stored, so each lane has up to kRows * kStageChunks loads in flight (a load and its wait per node
+// would serialise some twenty round trips to L2 in every workgroup).  With acc, the same nodes of acc are
+// cleared; vmin and nan_check receive the smallest v and 0 * (every contrast) (NaN if any node is not
+// finite).
+constexpr int kStageChunks = 4;   // W <= 256; the padded grid fits in LDS only up to 202 columns
+
+template <int kRows>
 __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, float v0, const RayGeo& g, float* vs,
                                                int* acc, float& vmin, float& nan_check) {
-    const int W = g.W, total = (g.Gy + 2) * W;
-    const float invW = 1.0f / static_cast<float>(W);
-    for (int idx0 = threadIdx.x; idx0 < total; idx0 += kStage * blockDim.x) {
-        float d[kStage];
+    const int W = g.W, H = g.Gy + 2;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    for (int r0 = wave; r0 < H; r0 += kRows * nw) {
+        // every load is unconditional (node 0 for the ring and for columns beyond the grid) and its value is
+        // used only after all of them are issued
+        float x[kRows][kStageChunks];
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int idx = idx0 + u * static_cast<int>(blockDim.x);
-            int r, c;
-            divmod_small(idx, W, invW, r, c);
-            const int a = r - 1, b = c - 1;
-            // an unconditional load (of node 0 for the ring), so that no branch separates the loads
-            const bool in = idx < total && a >= 0 && a < g.Gy && b >= 0 && b < g.Gx;
-            const float x = sos[in ? a * g.Gx + b : 0];
-            d[u] = in ? x - v0 : 0.0f;
+        for (int k = 0; k < kRows; ++k) {
+            const int a = r0 + k * nw - 1;
+            const bool row_in = a >= 0 && a < g.Gy;
+#pragma unroll
+            for (int q = 0; q < kStageChunks; ++q) {
+                const int b = 64 * q + lane - 1;
+                const bool in = row_in && b >= 0 && b < g.Gx;
+                x[k][q] = sos[in ? a * g.Gx + b : 0];
+            }
         }
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int idx = idx0 + u * static_cast<int>(blockDim.x);
-            if (idx < total) {
-                vs[idx] = d[u];
-                if (acc) acc[idx] = 0;
-                vmin = fminf(vmin, v0 + d[u]);
-                nan_check += 0.0f * d[u];
+        for (int k = 0; k < kRows; ++k) {
+            const int r = r0 + k * nw, a = r - 1;
+            if (r < H) {
+                const bool row_in = a >= 0 && a < g.Gy;
+#pragma unroll
+                for (int q = 0; q < kStageChunks; ++q) {
+                    const int c = 64 * q + lane, b = c - 1;
+                    if (c < W) {
+                        const float d = (row_in && b >= 0 && b < g.Gx) ? x[k][q] - v0 : 0.0f;
+                        vs[r * W + c] = d;
+                        if (acc) acc[r * W + c] = 0;
+                        vmin = fminf(vmin, v0 + d);
+                        nan_check += 0.0f * d;
+                    }
+                }
             }
         }
     }
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
     extern __shared__ float vs[];
     {
         float vmin = v0, nan_check = 0.0f;   // not used by the forward
-        stage_contrast<kStageFwd>(sos, v0, g, vs, nullptr, vmin, nan_check);
+        stage_contrast<kStageRows>(sos, v0, g, vs, nullptr, vmin, nan_check);
     }
     __syncthreads();
     // K divides the workgroup size and n_items = rays * K, so the K lanes of a ray enter and leave the
@@ -454,7 +456,7 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     float* red = reinterpret_cast<float*>(acc + total);     // kGridThreads / 64 floats
     const int tid = threadIdx.x;
     float vmin = v0, nan_check = 0.0f;                     // nan_check turns NaN if any node is not finite
-    stage_contrast<kStageAdj>(sos, v0, g, vs, acc, vmin, nan_check);
+    stage_contrast<kStageRows>(sos, v0, g, vs, acc, vmin, nan_check);
     vmin = -block_max(-vmin, red);
     const int it0 = blockIdx.x * per_block;
     const int it1 = min(it0 + per_block, n_items);
@@ -531,11 +533,18 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     const float invF = 1.0f / F;
     const float bad = __builtin_nanf("");
     float* part = partial + static_cast<size_t>(blockIdx.x) * g.Gy * g.Gx;
-    const float invGx = 1.0f / static_cast<float>(g.Gx);
-    for (int idx = tid; idx < g.Gy * g.Gx; idx += blockDim.x) {
-        int a, b;
-        divmod_small(idx, g.Gx, invGx, a, b);
-        part[idx] = ok ? static_cast<float>(acc[(a + 1) * W + b + 1]) * invF : bad;
+    // rows per wave and 64-column chunks per lane, as in the staging
+    {
+        const int lane = tid & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        for (int a = wave; a < g.Gy; a += kGridThreads / 64) {
+#pragma unroll
+            for (int q = 0; q < kStageChunks; ++q) {
+                const int b = 64 * q + lane;
+                if (64 * q < g.Gx && b < g.Gx)
+                    part[a * g.Gx + b] = ok ? static_cast<float>(acc[(a + 1) * W + b + 1]) * invF : bad;
+            }
+        }
     }
 }
 
