@@ -164,20 +164,67 @@ __device__ __forceinline__ void ray_setup(float cx, float cy, float ex, float ey
     dgy = dl * uy * g.inv_ds;
 }
 
-__device__ __forceinline__ float contrast_sample(const float* vs, float sf, float gx0, float gy0, float dgx, float dgy,
-                                                 const RayGeo& g) {
+// Cell of sample sf of a ray: flat padded index c of its lower-left node and the fractions (fx, fy) inside
+// it.  With kClamp the cell is clamped into the padded grid whatever the input; without, the caller has
+// checked that it lies there (segment_inside).  The flat index is formed in float (exact: the padded grid
+// has far fewer than 2^24 nodes).
+template <bool kClamp>
+__device__ __forceinline__ int sample_cell(float sf, float gx0, float gy0, float dgx, float dgy, const RayGeo& g,
+                                           float& fx, float& fy) {
     const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
     const float bf = floorf(gx), af = floorf(gy);
-    const float fx = gx - bf, fy = gy - af;
-    // clamp so that the 2 x 2 stencil stays in the padded grid whatever the input; the flat index is
-    // formed in float (exact: the padded grid has far fewer than 2^24 nodes)
-    const float bc = __builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx));
-    const float ac = __builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy));
-    const int c = static_cast<int>(fmaf(ac, static_cast<float>(g.W), bc));
+    fx = gx - bf;
+    fy = gy - af;
+    const float bc = kClamp ? __builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx)) : bf;
+    const float ac = kClamp ? __builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy)) : af;
+    return static_cast<int>(fmaf(ac, static_cast<float>(g.W), bc));
+}
+
+// True when every sample s0 .. s1 - 1 (s1 > s0) has its cell inside the padded grid, so that clamping
+// would change nothing: the positions fma(sf, d, g0) are monotone in sf (fma rounds monotonically), so the
+// two end samples bound them all.  False for non-finite positions.
+__device__ __forceinline__ bool segment_inside(int s0, int s1, float gx0, float gy0, float dgx, float dgy,
+                                               const RayGeo& g) {
+    const float xmax = static_cast<float>(g.Gx + 1), ymax = static_cast<float>(g.Gy + 1);
+    bool in = true;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float sf = static_cast<float>(e ? s1 - 1 : s0) + 0.5f;
+        const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
+        in = in && gx >= 0.0f && gx < xmax && gy >= 0.0f && gy < ymax;
+    }
+    return in;
+}
+
+template <bool kClamp>
+__device__ __forceinline__ float contrast_sample(const float* vs, float sf, float gx0, float gy0, float dgx, float dgy,
+                                                 const RayGeo& g) {
+    float fx, fy;
+    const int c = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
     const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + g.W], v11 = vs[c + g.W + 1];
     const float top = fmaf(fx, v01 - v00, v00);
     const float bot = fmaf(fx, v11 - v10, v10);
     return fmaf(fy, bot - top, top);
+}
+
+// Sum of the integrand delta / (v0 + delta) over samples s0 .. s1 - 1, two at a time (two gathers in flight).
+template <bool kClamp>
+__device__ __forceinline__ float fwd_segment(const float* vs, int s0, int s1, float v0, float gx0, float gy0,
+                                             float dgx, float dgy, const RayGeo& g) {
+    float acc0 = 0.0f, acc1 = 0.0f;
+    float sf = static_cast<float>(s0) + 0.5f;
+    int s = s0;
+    for (; s + 1 < s1; s += 2, sf += 2.0f) {
+        const float d0 = contrast_sample<kClamp>(vs, sf, gx0, gy0, dgx, dgy, g);
+        const float d1 = contrast_sample<kClamp>(vs, sf + 1.0f, gx0, gy0, dgx, dgy, g);
+        acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
+        acc1 = fmaf(d1, __builtin_amdgcn_rcpf(v0 + d1), acc1);
+    }
+    if (s < s1) {
+        const float d0 = contrast_sample<kClamp>(vs, sf, gx0, gy0, dgx, dgy, g);
+        acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
+    }
+    return acc0 + acc1;
 }
 
 __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restrict__ sos, float v0,
@@ -200,20 +247,13 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
         float gx0, gy0, dgx, dgy, dl;
         ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
         const int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
-        float acc0 = 0.0f, acc1 = 0.0f;
-        float sf = static_cast<float>(s0) + 0.5f;
-        int s = s0;
-        for (; s + 1 < s1; s += 2, sf += 2.0f) {
-            const float d0 = contrast_sample(vs, sf, gx0, gy0, dgx, dgy, g);
-            const float d1 = contrast_sample(vs, sf + 1.0f, gx0, gy0, dgx, dgy, g);
-            acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
-            acc1 = fmaf(d1, __builtin_amdgcn_rcpf(v0 + d1), acc1);
+        float acc = 0.0f;
+        if (s1 > s0) {
+            // the clamp-free loop where the whole segment is inside the grid (the same bits)
+            acc = segment_inside(s0, s1, gx0, gy0, dgx, dgy, g)
+                      ? fwd_segment<false>(vs, s0, s1, v0, gx0, gy0, dgx, dgy, g)
+                      : fwd_segment<true>(vs, s0, s1, v0, gx0, gy0, dgx, dgy, g);
         }
-        if (s < s1) {
-            const float d0 = contrast_sample(vs, sf, gx0, gy0, dgx, dgy, g);
-            acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
-        }
-        float acc = acc0 + acc1;
         for (int off = K >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, K);
         if (k == 0) w[ray] = acc * dl;
     }
@@ -444,6 +484,46 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
 // the two reduce kernels add the partial grids in a fixed order.
 constexpr int kGridThreads = 1024;
 
+// Adjoint shares of samples s0 .. s1 - 1 (s1 > s0) of one ray, added into the fixed-point accumulator acc
+// (same layout as vs).  Consecutive samples in the same cell add into registers; a cell's four shares go to
+// LDS once, when the walk leaves it (truncation toward zero: at most one unit of 2^-30 of the bound per
+// flush).  q0 = dL/dw * dl * v0 * F.
+template <bool kClamp>
+__device__ __forceinline__ void adj_segment(const float* vs, int* acc, int s0, int s1, float v0, float q0, float gx0,
+                                            float gy0, float dgx, float dgy, const RayGeo& g) {
+    const int W = g.W;
+    float sf = static_cast<float>(s0) + 0.5f;
+    float fx, fy;
+    int cprev = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);   // the first sample's cell
+    float a00 = 0.0f, a01 = 0.0f, a10 = 0.0f, a11 = 0.0f;
+    for (int s = s0; s < s1; ++s, sf += 1.0f) {
+        const int c = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
+        const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
+        const float top = fmaf(fx, v01 - v00, v00);
+        const float bot = fmaf(fx, v11 - v10, v10);
+        const float r = __builtin_amdgcn_rcpf(v0 + fmaf(fy, bot - top, top));
+        const float qv = q0 * r * r;                     // dL/dw * dl * v0 / v^2, times F
+        const float qy1 = qv * fy, qy0 = qv - qy1;
+        if (c != cprev) {
+            atomicAdd(acc + cprev, static_cast<int>(a00));
+            atomicAdd(acc + cprev + 1, static_cast<int>(a01));
+            atomicAdd(acc + cprev + W, static_cast<int>(a10));
+            atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
+            cprev = c;
+            a00 = a01 = a10 = a11 = 0.0f;
+        }
+        a00 += qy0 - qy0 * fx;
+        a01 += qy0 * fx;
+        a10 += qy1 - qy1 * fx;
+        a11 += qy1 * fx;
+    }
+    atomicAdd(acc + cprev, static_cast<int>(a00));
+    atomicAdd(acc + cprev + 1, static_cast<int>(a01));
+    atomicAdd(acc + cprev + W, static_cast<int>(a10));
+    atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
+}
+
+
 __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     const float* __restrict__ sos, float v0, const float* __restrict__ centres, int N, int n_elem, float R, float phi0,
     int Ns, RayGeo g, int K, int n_items, int per_block, const float* __restrict__ dL_dw,
@@ -488,45 +568,12 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
         ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
         const float q0 = ok ? dL_dw[static_cast<size_t>(i) * n_elem + n] * dl * sc * F : 0.0f;
         const int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
-        float sf = static_cast<float>(s0) + 0.5f;
-        int cprev = -1;
-        float a00 = 0.0f, a01 = 0.0f, a10 = 0.0f, a11 = 0.0f;
-        for (int s = s0; s < s1; ++s, sf += 1.0f) {
-            const float gx = fmaf(sf, dgx, gx0), gy = fmaf(sf, dgy, gy0);
-            const float bf = floorf(gx), af = floorf(gy);
-            const float fx = gx - bf, fy = gy - af;
-            const float bc = __builtin_amdgcn_fmed3f(bf, 0.0f, static_cast<float>(g.Gx));
-            const float ac = __builtin_amdgcn_fmed3f(af, 0.0f, static_cast<float>(g.Gy));
-            const int c = static_cast<int>(fmaf(ac, static_cast<float>(W), bc));   // exact, as in the forward
-            const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
-            const float top = fmaf(fx, v01 - v00, v00);
-            const float bot = fmaf(fx, v11 - v10, v10);
-            const float r = __builtin_amdgcn_rcpf(v0 + fmaf(fy, bot - top, top));
-            const float qv = q0 * r * r;                     // dL/dw * dl * v0 / v^2, times F
-            const float qy1 = qv * fy, qy0 = qv - qy1;
-            // consecutive samples in the same cell add into registers; a cell's four shares go to LDS
-            // once, when the walk leaves it (truncation toward zero: at most one unit of 2^-30 of the
-            // bound per flush)
-            if (c != cprev) {
-                if (cprev >= 0) {
-                    atomicAdd(acc + cprev, static_cast<int>(a00));
-                    atomicAdd(acc + cprev + 1, static_cast<int>(a01));
-                    atomicAdd(acc + cprev + W, static_cast<int>(a10));
-                    atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
-                }
-                cprev = c;
-                a00 = a01 = a10 = a11 = 0.0f;
-            }
-            a00 += qy0 - qy0 * fx;
-            a01 += qy0 * fx;
-            a10 += qy1 - qy1 * fx;
-            a11 += qy1 * fx;
-        }
-        if (cprev >= 0) {
-            atomicAdd(acc + cprev, static_cast<int>(a00));
-            atomicAdd(acc + cprev + 1, static_cast<int>(a01));
-            atomicAdd(acc + cprev + W, static_cast<int>(a10));
-            atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
+        if (s1 > s0) {
+            // the clamp-free loop where the whole segment is inside the grid (the same bits)
+            if (segment_inside(s0, s1, gx0, gy0, dgx, dgy, g))
+                adj_segment<false>(vs, acc, s0, s1, v0, q0, gx0, gy0, dgx, dgy, g);
+            else
+                adj_segment<true>(vs, acc, s0, s1, v0, q0, gx0, gy0, dgx, dgy, g);
         }
     }
     __syncthreads();
