@@ -164,15 +164,22 @@ __global__ __launch_bounds__(kThreads) void conv3x3_kernel(const __bf16* __restr
     }
 }
 
-// Weight gradient.  With p' = p + (0, kx - 1) the sum becomes
+// Weight gradient: dW[co][ky][kx][ci] = sum over pixels p of g[p][co] x[p + (ky - 1, kx - 1)][ci].  The tap's
+// column shift is put on the operand with fewer channels.  For CI >= CO (conv3x3_wgrad_kernel), with
+// p' = p + (0, kx - 1) the sum becomes
 //   dW[co][ky][kx][ci] = sum_p' g[p'_y][p'_x + 1 - kx][co] x[p'_y + ky - 1][p'_x][ci],
 // so the input needs only row shifts (one transposed copy, rows y0 - 1 .. y0 + 4 of the tile's 16 columns)
-// and the output gradient the column shifts (three transposed copies, one per kx).  Both are filled from
-// pairs of adjacent pixels with 4-byte LDS writes.
-// threads of a weight-gradient workgroup: 8 waves when there are 16 (output, input) channel-tile pairs, so
-// that each wave holds the accumulators of two pairs (4 would take the registers of two waves per SIMD)
+// and the output gradient the column shifts (three transposed copies, one per kx).  For CI < CO
+// (conv3x3_wgrad_sx_kernel) the input is held in three copies, copy kx holding column j of the tile at
+// x0 + j + kx - 1, and the output gradient in one.  Every copy is filled from pairs of adjacent pixels with
+// 4-byte LDS writes.
+// Threads of a weight-gradient workgroup: 8 waves when there are 16 (output, input) channel-tile pairs, so
+// that each wave holds the accumulators of two pairs (4 would take the registers of two waves per SIMD).
 template <int CI, int CO>
 constexpr int wgrad_threads() { return (CI / 16) * (CO / 16) >= 16 ? 512 : 256; }
+
+template <int CI, int CO>
+constexpr bool wgrad_shift_x() { return CI < CO; }
 
 template <int CI, int CO>
 __global__ __launch_bounds__((wgrad_threads<CI, CO>())) void conv3x3_wgrad_kernel(const __bf16* __restrict__ x,
@@ -301,9 +308,141 @@ __global__ __launch_bounds__((wgrad_threads<CI, CO>())) void conv3x3_wgrad_kerne
     }
 }
 
+// The same weight gradient with the column shift on the input (used for CI < CO).
+template <int CI, int CO>
+__global__ __launch_bounds__((wgrad_threads<CI, CO>())) void conv3x3_wgrad_sx_kernel(const __bf16* __restrict__ x,
+                                                                 const __bf16* __restrict__ g, int H, int W,
+                                                                 int tiles_x, int tiles_y, int n_tiles,
+                                                                 float* __restrict__ partial) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char cv_dyn[];
+    __bf16* xT = reinterpret_cast<__bf16*>(cv_dyn);      // [3 (kx)][CI][kXB]: rows y0 - 1 .. y0 + 4; column j
+                                                          // holds x at x0 + j + kx - 1
+    __bf16* gT = xT + 3 * CI * kXB;                       // [CO][kGL]: rows y0 .. y0 + 3, 16 columns
+    constexpr int NT = wgrad_threads<CI, CO>(), CT = CI / 16, OT = CO / 16, PAIRS = CT * OT / (NT / 64);
+    constexpr int CHI = CI / 8, CHO = CO / 8;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    f32x4 acc[PAIRS][9];
+#pragma unroll
+    for (int p = 0; p < PAIRS; ++p)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[p][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float db[8] = {};
+    const int per_img = tiles_x * tiles_y;
+    // The next tile is loaded into registers while this one is computed.  Input item i = threadIdx.x +
+    // NT k: halo row, column pair jp, channel part (pixels x0 + 2 jp - 1 .. x0 + 2 jp + 2); output-gradient
+    // item: tile row, column pair, channel part (pixels x0 + 2 jp, + 1).
+    constexpr int XP = 4, GP = 2, XO = 1, GO = 0;
+    constexpr int NXI = (kWTH + 2) * (kTW / 2) * CHI, NXP = (NXI + NT - 1) / NT;
+    constexpr int NGI = kWTH * (kTW / 2) * CHO, NGP = (NGI + NT - 1) / NT;
+    bf16x8 px[NXP][XP], pg[NGP][GP];
+    auto load_tile = [&](int tile) {
+        const int img = tile / per_img, rem = tile - img * per_img;
+        const int y0 = (rem / tiles_x) * kWTH, x0 = (rem % tiles_x) * kTW;
+#pragma unroll
+        for (int k = 0; k < NXP; ++k) {
+            const int it = threadIdx.x + NT * k;
+            const int part = it % CHI, pr = it / CHI, jp = pr % (kTW / 2), hy = pr / (kTW / 2);
+            const int gy = y0 - 1 + hy;
+#pragma unroll
+            for (int u = 0; u < XP; ++u) {
+                const int gx = x0 + 2 * jp - XO + u;
+                px[k][u] = zero8();
+                if (it < NXI && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                    px[k][u] = ld8(x + ((static_cast<size_t>(img) * H + gy) * W + gx) * CI + 8 * part);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NGP; ++k) {
+            const int it = threadIdx.x + NT * k;
+            const int part = it % CHO, pr = it / CHO, jp = pr % (kTW / 2), row = pr / (kTW / 2);
+            const int gy = y0 + row;
+#pragma unroll
+            for (int u = 0; u < GP; ++u) {
+                const int gx = x0 + 2 * jp - GO + u;
+                pg[k][u] = zero8();
+                if (it < NGI && gy < H && gx >= 0 && gx < W)
+                    pg[k][u] = ld8(g + ((static_cast<size_t>(img) * H + gy) * W + gx) * CO + 8 * part);
+            }
+        }
+    };
+    auto pair = [](__bf16 lo, __bf16 hi) {
+        return static_cast<unsigned>(__builtin_bit_cast(unsigned short, lo)) |
+               (static_cast<unsigned>(__builtin_bit_cast(unsigned short, hi)) << 16);
+    };
+    if (static_cast<int>(blockIdx.x) < n_tiles) load_tile(blockIdx.x);
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NXP; ++k) {
+            const int it = threadIdx.x + NT * k;
+            if (it >= NXI) continue;
+            const int part = it % CHI, pr = it / CHI, jp = pr % (kTW / 2), hy = pr / (kTW / 2);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int o = (8 * part + e) * kXB + hy * kTW + 2 * jp;
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx)
+                    *reinterpret_cast<unsigned*>(xT + kx * CI * kXB + o) = pair(px[k][kx][e], px[k][kx + 1][e]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NGP; ++k) {
+            const int it = threadIdx.x + NT * k;
+            if (it >= NGI) continue;
+            const int part = it % CHO, pr = it / CHO, jp = pr % (kTW / 2), row = pr / (kTW / 2);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                *reinterpret_cast<unsigned*>(gT + (8 * part + e) * kGL + row * kTW + 2 * jp) = pair(pg[k][0][e], pg[k][1][e]);
+                db[e] += static_cast<float>(pg[k][0][e]) + static_cast<float>(pg[k][1][e]);
+            }
+        }
+        __syncthreads();
+        if (tile + static_cast<int>(gridDim.x) < n_tiles) load_tile(tile + gridDim.x);
+        // K step ks: pixels 32 ks .. 32 ks + 31 of the tile = rows 2 ks, 2 ks + 1; lane q takes row
+        // 2 ks + q / 2, columns 8 (q % 2) .. + 7
+#pragma unroll
+        for (int ks = 0; ks < kWTH / 2; ++ks) {
+            const int row = 2 * ks + (q >> 1), col = 8 * (q & 1);
+#pragma unroll
+            for (int p = 0; p < PAIRS; ++p) {
+                const int idx = wv * PAIRS + p, ot = idx / CT, ct = idx - ot * CT;
+                const bf16x8 av = ld8(gT + (16 * ot + r) * kGL + 32 * ks + 8 * q);
+                bf16x8 bv[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t)
+                    bv[t] = ld8(xT + ((t % 3) * CI + 16 * ct + r) * kXB + (row + t / 3) * kTW + col);
+#pragma unroll
+                for (int t = 0; t < 9; ++t) acc[p][t] = mfma(av, bv[t], acc[p][t]);
+            }
+        }
+    }
+    float* out = partial + static_cast<size_t>(blockIdx.x) * (CO * 9 * CI + CO);
+#pragma unroll
+    for (int p = 0; p < PAIRS; ++p) {
+        const int idx = wv * PAIRS + p, ot = idx / CT, ct = idx - ot * CT;
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[((16 * ot + 4 * q + i) * 9 + t) * CI + 16 * ct + r] = acc[p][t][i];
+    }
+    // bias gradient: thread t always loaded channel part t % CHO
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(cv_dyn);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[threadIdx.x * 8 + e] = db[e];
+    __syncthreads();
+    if (threadIdx.x < CO) {
+        const int part = threadIdx.x / 8, e = threadIdx.x % 8;
+        float s = 0.0f;
+        for (int t = part; t < NT; t += CHO) s += red[t * 8 + e];
+        out[CO * 9 * CI + threadIdx.x] = s;
+    }
+}
+
 template <int CI, int CO>
 constexpr size_t wgrad_lds() {
-    const size_t b = static_cast<size_t>(CI * kXB + 3 * CO * kGL) * sizeof(__bf16);
+    constexpr bool SX = wgrad_shift_x<CI, CO>();
+    const size_t b = static_cast<size_t>((SX ? 3 : 1) * CI * kXB + (SX ? 1 : 3) * CO * kGL) * sizeof(__bf16);
     const size_t r = static_cast<size_t>(wgrad_threads<CI, CO>()) * 8 * sizeof(float);
     return b > r ? b : r;
 }
@@ -566,12 +705,16 @@ int launch_wgrad(const __bf16* x, const __bf16* g, int n, int H, int W, float* g
     const int nout = CO * 9 * CI + CO;
     static bool attr = false;
     const size_t lds = wgrad_lds<CI, CO>();
+    auto kern = [] {
+        if constexpr (wgrad_shift_x<CI, CO>()) return conv3x3_wgrad_sx_kernel<CI, CO>;
+        else return conv3x3_wgrad_kernel<CI, CO>;
+    }();
     if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(conv3x3_wgrad_kernel<CI, CO>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(lds));
         attr = true;
     }
-    conv3x3_wgrad_kernel<CI, CO><<<blocks, wgrad_threads<CI, CO>(), lds, st>>>(x, g, H, W, tx, ty, static_cast<int>(tiles), ws);
+    kern<<<blocks, wgrad_threads<CI, CO>(), lds, st>>>(x, g, H, W, tx, ty, static_cast<int>(tiles), ws);
     if (int s = launch_status("pact_conv3x3_wgrad_bf16")) return s;
     float* part2 = ws + static_cast<size_t>(blocks) * nout;
     sum_partials1_kernel<<<dim3(ceil_div(nout, 256), kSlices), 256, 0, st>>>(ws, blocks, nout, part2);
