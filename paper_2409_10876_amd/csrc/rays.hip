@@ -94,13 +94,12 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 
 // Stage the contrast sos - v0 of the Gy x Gx node grid into vs [(Gy + 2)][W] with a one-node ring of zeros
 // (padded node (r, c) is grid node (r - 1, c - 1)).  Wave w takes padded rows w, w + waves, ... and lane l
-// the columns l, l + 64, ... of each (at most kStageChunks, which covers every grid that fits in LDS), so
-// that rows and chunks are wave-uniform and no node needs a division.  kRows rows are loaded before any
-// is stored, so each lane has up to kRows * kStageChunks loads in flight (a load and its wait per node
-// would serialise some twenty round trips to L2 in every workgroup).  With acc, the same nodes of acc are
-// cleared; vmin and nan_check receive the smallest v and 0 * (every contrast) (NaN if any node is not
-// finite).
-constexpr int kStageChunks = 4;   // W <= 256; the padded grid fits in LDS only up to 202 columns
+// the columns l, l + 64, ... of each, kStageChunks chunks of 64 columns at a time, so that rows and chunks
+// are wave-uniform and no node needs a division.  kRows rows are loaded before any is stored, so each
+// lane has up to kRows * kStageChunks loads in flight (a load and its wait per node would serialise some
+// twenty round trips to L2 in every workgroup).  With acc, the same nodes of acc are cleared; vmin and
+// nan_check receive the smallest v and 0 * (every contrast) (NaN if any node is not finite).
+constexpr int kStageChunks = 4;   // one pass covers W <= 256 (every square grid that fits in LDS)
 
 template <int kRows>
 __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, float v0, const RayGeo& g, float* vs,
@@ -109,6 +108,7 @@ __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, fl
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
+    for (int cb = 0; cb < W; cb += 64 * kStageChunks)
     for (int r0 = wave; r0 < H; r0 += kRows * nw) {
         // every load is unconditional (node 0 for the ring and for columns beyond the grid) and its value is
         // used only after all of them are issued
@@ -119,7 +119,7 @@ __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, fl
             const bool row_in = a >= 0 && a < g.Gy;
 #pragma unroll
             for (int q = 0; q < kStageChunks; ++q) {
-                const int b = 64 * q + lane - 1;
+                const int b = cb + 64 * q + lane - 1;
                 const bool in = row_in && b >= 0 && b < g.Gx;
                 x[k][q] = sos[in ? a * g.Gx + b : 0];
             }
@@ -131,7 +131,7 @@ __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, fl
                 const bool row_in = a >= 0 && a < g.Gy;
 #pragma unroll
                 for (int q = 0; q < kStageChunks; ++q) {
-                    const int c = 64 * q + lane, b = c - 1;
+                    const int c = cb + 64 * q + lane, b = c - 1;
                     if (c < W) {
                         const float d = (row_in && b >= 0 && b < g.Gx) ? x[k][q] - v0 : 0.0f;
                         vs[r * W + c] = d;
@@ -584,14 +584,9 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     {
         const int lane = tid & 63;
         const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-        for (int a = wave; a < g.Gy; a += kGridThreads / 64) {
-#pragma unroll
-            for (int q = 0; q < kStageChunks; ++q) {
-                const int b = 64 * q + lane;
-                if (64 * q < g.Gx && b < g.Gx)
-                    part[a * g.Gx + b] = ok ? static_cast<float>(acc[(a + 1) * W + b + 1]) * invF : bad;
-            }
-        }
+        for (int a = wave; a < g.Gy; a += kGridThreads / 64)
+            for (int b = lane; b < g.Gx; b += 64)
+                part[a * g.Gx + b] = ok ? static_cast<float>(acc[(a + 1) * W + b + 1]) * invF : bad;
     }
 }
 
