@@ -162,10 +162,14 @@ PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v
  * with dw/dv = dl v0 / v^2 at every sample spread by the bilinear weights.
  * scale: optional DEVICE scalar (NULL = 1).  accumulate != 0 adds to dL_dsos.
  * ws: DEVICE workspace of pact_sos_to_delays_adjoint_workspace_size() bytes,
- * which depends on the current device's CU count (one partial node grid per CU
- * when 2 (G+2)^2 floats fit in LDS; else 0 and ws may be NULL); not shared by two calls in flight.  The per-CU sums are exact integer sums at a fixed-point
- * scale and are combined in a fixed order, so the result is deterministic; a
- * non-finite SOS node, or one at or below zero, makes the result NaN. */
+ * which depends on the current device's CU count: one partial node grid per
+ * workgroup (about one per CU) when a band of at least 8 node rows, contrast
+ * and accumulator, fits in one CU's LDS (the whole grid in one band up to
+ * 141 x 141 nodes); else 0 and ws may be NULL (the tiled form).  Not shared by
+ * two calls in flight.  The per-workgroup sums are exact integer sums at a
+ * fixed-point scale and are combined in a fixed order, so the result is
+ * deterministic; a non-finite SOS node, or one at or below zero, makes the
+ * result NaN. */
 PACT_API size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg, int N, const pact_ring* ring);
 PACT_API int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
                                const pact_ring* ring, int n_samples, const float* dL_dw, const float* scale,

@@ -92,8 +92,9 @@ __device__ __forceinline__ float block_max(float v, float* red) {
     return t;
 }
 
-// Stage the contrast sos - v0 of the Gy x Gx node grid into vs [(Gy + 2)][W] with a one-node ring of zeros
-// (padded node (r, c) is grid node (r - 1, c - 1)).  Wave w takes padded rows w, w + waves, ... and lane l
+// Stage the contrast sos - v0 of padded rows R0 .. R0 + H - 1 of the Gy x Gx node grid with a one-node ring
+// of zeros (padded node (r, c) is grid node (r - 1, c - 1)) into vs [H][W] (all rows: R0 = 0,
+// H = Gy + 2).  Wave w takes rows w, w + waves, ... and lane l
 // the columns l, l + 64, ... of each, kStageChunks chunks of 64 columns at a time, so that rows and chunks
 // are wave-uniform and no node needs a division.  kRows rows are loaded before any is stored, so each
 // lane has up to kRows * kStageChunks loads in flight (a load and its wait per node would serialise some
@@ -103,8 +104,8 @@ constexpr int kStageChunks = 4;   // one pass covers W <= 256 (every square grid
 
 template <int kRows>
 __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, float v0, const RayGeo& g, float* vs,
-                                               int* acc, float& vmin, float& nan_check) {
-    const int W = g.W, H = g.Gy + 2;
+                                               int* acc, int R0, int H, float& vmin, float& nan_check) {
+    const int W = g.W;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
@@ -115,7 +116,7 @@ __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, fl
         float x[kRows][kStageChunks];
 #pragma unroll
         for (int k = 0; k < kRows; ++k) {
-            const int a = r0 + k * nw - 1;
+            const int a = R0 + r0 + k * nw - 1;
             const bool row_in = a >= 0 && a < g.Gy;
 #pragma unroll
             for (int q = 0; q < kStageChunks; ++q) {
@@ -126,7 +127,7 @@ __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, fl
         }
 #pragma unroll
         for (int k = 0; k < kRows; ++k) {
-            const int r = r0 + k * nw, a = r - 1;
+            const int r = r0 + k * nw, a = R0 + r - 1;
             if (r < H) {
                 const bool row_in = a >= 0 && a < g.Gy;
 #pragma unroll
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
     extern __shared__ float vs[];
     {
         float vmin = v0, nan_check = 0.0f;   // not used by the forward
-        stage_contrast<kStageRows>(sos, v0, g, vs, nullptr, vmin, nan_check);
+        stage_contrast<kStageRows>(sos, v0, g, vs, nullptr, 0, g.Gy + 2, vmin, nan_check);
     }
     __syncthreads();
     // K divides the workgroup size and n_items = rays * K, so the K lanes of a ray enter and leave the
@@ -488,16 +489,26 @@ constexpr int kGridThreads = 1024;
 // (same layout as vs).  Consecutive samples in the same cell add into registers; a cell's four shares go to
 // LDS once, when the walk leaves it (truncation toward zero: at most one unit of 2^-30 of the bound per
 // flush).  q0 = dL/dw * dl * v0 * F.
-template <bool kClamp>
+// Banded (kBanded): vs and acc hold padded rows R0 .. R0 + band_cells / W of the grid, and only samples whose
+// cell's lower row lies in R0 .. R0 + band_cells / W - 1 are taken (cbase = R0 W); the others belong to
+// another band.
+template <bool kClamp, bool kBanded>
 __device__ __forceinline__ void adj_segment(const float* vs, int* acc, int s0, int s1, float v0, float q0, float gx0,
-                                            float gy0, float dgx, float dgy, const RayGeo& g) {
+                                            float gy0, float dgx, float dgy, const RayGeo& g, int cbase,
+                                            int band_cells) {
     const int W = g.W;
     float sf = static_cast<float>(s0) + 0.5f;
     float fx, fy;
-    int cprev = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);   // the first sample's cell
+    // the first sample's cell (banded: none yet, so that the first taken sample opens its cell)
+    int cprev = kBanded ? -1 : sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
     float a00 = 0.0f, a01 = 0.0f, a10 = 0.0f, a11 = 0.0f;
     for (int s = s0; s < s1; ++s, sf += 1.0f) {
-        const int c = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
+        int c = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
+        if (kBanded) {
+            c -= cbase;
+            if (c < 0 || c >= band_cells) continue;
+            if (cprev < 0) cprev = c;
+        }
         const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
         const float top = fmaf(fx, v01 - v00, v00);
         const float bot = fmaf(fx, v11 - v10, v10);
@@ -517,28 +528,56 @@ __device__ __forceinline__ void adj_segment(const float* vs, int* acc, int s0, i
         a10 += qy1 - qy1 * fx;
         a11 += qy1 * fx;
     }
+    if (kBanded && cprev < 0) return;
     atomicAdd(acc + cprev, static_cast<int>(a00));
     atomicAdd(acc + cprev + 1, static_cast<int>(a01));
     atomicAdd(acc + cprev + W, static_cast<int>(a10));
     atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
 }
 
+// Samples of s0 .. s1 - 1 whose position row gy may lie in [R0, R1): a conservative range (one sample of
+// margin each side) from gy = gy0 + (s + 1/2) dgy; the per-sample test in adj_segment is exact.
+__device__ __forceinline__ void band_samples(int s0, int s1, float gy0, float dgy, int R0, int R1, int& sa, int& sb) {
+    sa = s0;
+    sb = s1;
+    if (!(dgy != 0.0f) || !isfinite(gy0) || !isfinite(dgy)) return;
+    const float t0 = (static_cast<float>(R0) - gy0) / dgy - 0.5f, t1 = (static_cast<float>(R1) - gy0) / dgy - 0.5f;
+    const float lo = fmaxf(fminf(t0, t1), static_cast<float>(s0) - 2.0f);
+    const float hi = fminf(fmaxf(t0, t1), static_cast<float>(s1) + 2.0f);
+    if (!(lo <= hi)) {
+        sb = sa;
+        return;
+    }
+    sa = max(s0, static_cast<int>(floorf(lo)) - 1);
+    sb = min(s1, static_cast<int>(ceilf(hi)) + 2);
+}
 
+
+// Banded form (kBanded), for grids whose contrast fits in LDS but not twice: workgroup b takes band
+// b % n_bands, cell rows R0 .. R1 - 1 (padded coordinates, R0 = band band_rows), stages padded rows
+// R0 .. R1 and accumulates the samples whose cells lie in its band; the workgroups of a band share out
+// every ray segment.  Bands overlap in one row of nodes, which both accumulate; the partial grids (zero
+// outside a workgroup's rows) are summed as before.
+template <bool kBanded>
 __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     const float* __restrict__ sos, float v0, const float* __restrict__ centres, int N, int n_elem, float R, float phi0,
-    int Ns, RayGeo g, int K, int n_items, int per_block, const float* __restrict__ dL_dw,
+    int Ns, RayGeo g, int K, int n_items, int per_block, int n_bands, int band_rows, const float* __restrict__ dL_dw,
     const float* __restrict__ scale, float* __restrict__ partial) {
     extern __shared__ float lds[];
     const int W = g.W;
-    const int total = (g.Gy + 2) * W;
+    const int band = kBanded ? static_cast<int>(blockIdx.x) % n_bands : 0;
+    const int bblock = kBanded ? static_cast<int>(blockIdx.x) / n_bands : static_cast<int>(blockIdx.x);
+    const int R0 = kBanded ? band * band_rows : 0;                        // cell rows R0 .. R1 - 1
+    const int R1 = kBanded ? min(R0 + band_rows, g.Gy + 1) : g.Gy + 1;
+    const int total = (R1 - R0 + 1) * W;                                  // staged padded rows R0 .. R1
     float* vs = lds;                                        // contrast with a ring of zeros
     int* acc = reinterpret_cast<int*>(vs + total);          // fixed-point sums, same layout
     float* red = reinterpret_cast<float*>(acc + total);     // kGridThreads / 64 floats
     const int tid = threadIdx.x;
     float vmin = v0, nan_check = 0.0f;                     // nan_check turns NaN if any node is not finite
-    stage_contrast<kStageRows>(sos, v0, g, vs, acc, vmin, nan_check);
+    stage_contrast<kStageRows>(sos, v0, g, vs, acc, R0, R1 - R0 + 1, vmin, nan_check);
     vmin = -block_max(-vmin, red);
-    const int it0 = blockIdx.x * per_block;
+    const int it0 = bblock * per_block;
     const int it1 = min(it0 + per_block, n_items);
     const float sc = (scale ? *scale : 1.0f) * v0;
     const float ds = 1.0f / g.inv_ds;
@@ -559,6 +598,7 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     const float F = (ok && bnd > 0.0f) ? ldexpf(1.0f, min(30 - (ilogbf(bnd) + 1), 126)) : 1.0f;
     __syncthreads();
 
+    const int cbase = R0 * W, band_cells = (R1 - R0) * W;
     for (int item = it0 + tid; item < it1; item += blockDim.x) {
         const int ray = item / K, k = item - ray * K;
         const int n = ray / N, i = ray - n * N;
@@ -567,26 +607,30 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
         float gx0, gy0, dgx, dgy, dl;
         ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
         const float q0 = ok ? dL_dw[static_cast<size_t>(i) * n_elem + n] * dl * sc * F : 0.0f;
-        const int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
+        int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
+        if (kBanded) band_samples(s0, s1, gy0, dgy, R0, R1, s0, s1);
         if (s1 > s0) {
             // the clamp-free loop where the whole segment is inside the grid (the same bits)
             if (segment_inside(s0, s1, gx0, gy0, dgx, dgy, g))
-                adj_segment<false>(vs, acc, s0, s1, v0, q0, gx0, gy0, dgx, dgy, g);
+                adj_segment<false, kBanded>(vs, acc, s0, s1, v0, q0, gx0, gy0, dgx, dgy, g, cbase, band_cells);
             else
-                adj_segment<true>(vs, acc, s0, s1, v0, q0, gx0, gy0, dgx, dgy, g);
+                adj_segment<true, kBanded>(vs, acc, s0, s1, v0, q0, gx0, gy0, dgx, dgy, g, cbase, band_cells);
         }
     }
     __syncthreads();
     const float invF = 1.0f / F;
     const float bad = __builtin_nanf("");
     float* part = partial + static_cast<size_t>(blockIdx.x) * g.Gy * g.Gx;
-    // rows per wave and 64-column chunks per lane, as in the staging
+    // rows per wave and columns per lane, as in the staging; grid row a is padded row a + 1, held in this
+    // workgroup's rows when R0 <= a + 1 <= R1 (zero otherwise)
     {
         const int lane = tid & 63;
         const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-        for (int a = wave; a < g.Gy; a += kGridThreads / 64)
+        for (int a = wave; a < g.Gy; a += kGridThreads / 64) {
+            const bool mine = !kBanded || (a + 1 >= R0 && a + 1 <= R1);
             for (int b = lane; b < g.Gx; b += 64)
-                part[a * g.Gx + b] = ok ? static_cast<float>(acc[(a + 1) * W + b + 1]) * invF : bad;
+                part[a * g.Gx + b] = !ok ? bad : (mine ? static_cast<float>(acc[(a + 1 - R0) * W + b + 1]) * invF : 0.0f);
+        }
     }
 }
 
@@ -718,13 +762,26 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
 namespace pact {
 namespace {
 
-// LDS bytes of rays_adj_grid_kernel; 0 if the grid does not fit (the tile kernel is used instead).
-size_t adj_grid_lds(const pact_grid& sosg) {
-    const size_t nodes = static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2);
-    const size_t lds = 2 * nodes * sizeof(float) + (kGridThreads / 64) * sizeof(float);
-    return lds <= kLdsBytes ? lds : 0;
+// Layout of rays_adj_grid_kernel for a grid: bands of band_rows cell rows (1 band: the whole grid) and the
+// LDS bytes of one band; bands == 0 if even bands of 8 rows do not fit (the tile kernel is used instead).
+struct AdjPlan {
+    int bands, band_rows;
+    size_t lds;
+};
+
+AdjPlan adj_plan(const pact_grid& sosg) {
+    const size_t W = static_cast<size_t>(sosg.nx) + 2, H = static_cast<size_t>(sosg.ny) + 2;
+    const size_t red = (kGridThreads / 64) * sizeof(float);
+    if (2 * H * W * sizeof(float) + red <= kLdsBytes) return {1, sosg.ny + 1, 2 * H * W * sizeof(float) + red};
+    const long long max_rows = static_cast<long long>((kLdsBytes - red) / (2 * W * sizeof(float))) - 1;
+    if (max_rows < 8) return {0, 0, 0};
+    const int bands = ceil_div(sosg.ny + 1, max_rows);
+    if (bands > 64) return {0, 0, 0};
+    const int rows = ceil_div(sosg.ny + 1, bands);             // balanced bands
+    return {bands, rows, 2 * (static_cast<size_t>(rows) + 1) * W * sizeof(float) + red};
 }
 
+size_t adj_grid_lds(const pact_grid& sosg) { return adj_plan(sosg).bands ? adj_plan(sosg).lds : 0; }
 
 // Segments per ray for rays_adj_grid_kernel: the K that minimises the critical path of one lane, rounds of
 // items times (segment length + a ray set-up worth about two samples), with at least 8 samples a segment.
@@ -743,12 +800,14 @@ int adj_segments(long long n_rays, int n_samples, long long lanes) {
     return best;
 }
 
-// The grid adjoint into one partial node grid per CU (the caller sums them); *n_part = their count.
+// The grid adjoint into one partial node grid per workgroup (the caller sums them); *n_part = their count.
 int launch_adj_grid(const float* sos, const pact_grid& sosg, float v0, const float* centres, int N,
                     const pact_ring& ring, int n_samples, const float* dL_dw, const float* scale, float* partial,
                     size_t ws_bytes, hipStream_t st, int* n_part, const char* what) {
-    const size_t glds = adj_grid_lds(sosg);
-    const int blocks = device_cu_count();
+    const AdjPlan plan = adj_plan(sosg);
+    const int cus = device_cu_count();
+    const int per_band = std::max(1, cus / plan.bands);           // workgroups per band
+    const int blocks = plan.bands * per_band;
     const size_t need = static_cast<size_t>(blocks) * sosg.ny * sosg.nx * sizeof(float);
     if (!partial || ws_bytes < need) {
         set_error("%s: workspace of %zu bytes needed, %zu given", what, need, partial ? ws_bytes : 0);
@@ -756,19 +815,26 @@ int launch_adj_grid(const float* sos, const pact_grid& sosg, float v0, const flo
     }
     static bool gattr = false;
     if (!gattr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel<false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel<true>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
         gattr = true;
     }
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
     const int tuned = tuned_tiling(N, ring, n_samples, sosg).adj;
-    const int K = tuned > 0 ? tuned : adj_segments(n_rays, n_samples, static_cast<long long>(blocks) * kGridThreads);
+    const int K = tuned > 0 ? tuned : adj_segments(n_rays, n_samples, static_cast<long long>(per_band) * kGridThreads);
     PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "%s: too many ray segments", what);
     const int n_items = static_cast<int>(n_rays * K);
-    const int per_block = ceil_div(n_items, blocks);
-    rays_adj_grid_kernel<<<blocks, kGridThreads, glds, st>>>(sos, v0, centres, N, ring.n_elem, ring.radius,
-                                                            ring.phi0, n_samples, make_geo(sosg, n_samples), K,
-                                                            n_items, per_block, dL_dw, scale, partial);
+    const int per_block = ceil_div(n_items, per_band);
+    if (plan.bands == 1)
+        rays_adj_grid_kernel<false><<<blocks, kGridThreads, plan.lds, st>>>(
+            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), K, n_items,
+            per_block, 1, sosg.ny + 1, dL_dw, scale, partial);
+    else
+        rays_adj_grid_kernel<true><<<blocks, kGridThreads, plan.lds, st>>>(
+            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), K, n_items,
+            per_block, plan.bands, plan.band_rows, dL_dw, scale, partial);
     *n_part = blocks;
     return launch_status(what);
 }
@@ -780,8 +846,10 @@ extern "C" size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sos
     (void)N;
     (void)ring_;
     if (!sosg_ || sosg_->ny <= 0 || sosg_->nx <= 0) return 0;
-    if (!pact::adj_grid_lds(*sosg_)) return 0;
-    return static_cast<size_t>(pact::device_cu_count()) * sosg_->ny * sosg_->nx * sizeof(float);
+    const pact::AdjPlan plan = pact::adj_plan(*sosg_);
+    if (!plan.bands) return 0;
+    const int blocks = plan.bands * std::max(1, pact::device_cu_count() / plan.bands);
+    return static_cast<size_t>(blocks) * sosg_->ny * sosg_->nx * sizeof(float);
 }
 
 extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg_, float v0, const float* centres,
@@ -907,8 +975,9 @@ extern "C" int pact_rays_autotune(const float* sos, const pact_grid* sosg_, floa
         }
     }
     // adjoint (grid form only): segments per ray around the built-in rule
-    if (adj_grid_lds(sosg)) {
-        const int rule = adj_segments(n_rays, n_samples, static_cast<long long>(device_cu_count()) * kGridThreads);
+    if (const AdjPlan plan = adj_plan(sosg); plan.bands) {
+        const long long per_band = std::max(1, device_cu_count() / plan.bands);
+        const int rule = adj_segments(n_rays, n_samples, per_band * kGridThreads);
         std::vector<int> cand = {rule, rule - 1, rule + 1, rule / 2, rule * 2, 1, 2, 4, 8, 16};
         std::sort(cand.begin(), cand.end());
         cand.erase(std::unique(cand.begin(), cand.end()), cand.end());

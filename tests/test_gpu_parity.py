@@ -141,6 +141,33 @@ def test_rays_on_a_wide_grid(lib):
     assert ea < TOL_GRAD
 
 
+@pytest.mark.parametrize("shape", [(300, 300), (8, 2300)], ids=["banded_300x300", "tiled_8x2300"])
+def test_rays_adjoint_beyond_one_cu(lib, shape):
+    """The ray adjoint on grids whose contrast and accumulator do not fit one CU's LDS together: 300 x 300
+    nodes run in bands of rows (5 bands, each workgroup holding its band), 8 x 2300 in the tiled form (a
+    band of 8 rows does not fit either).  Against the oracle's reverse mode, deterministic."""
+    Gy, Gx = shape
+    announce(f"ray adjoint on a {Gy} x {Gx} grid")
+    ds, v0, n_elem, R, phi0, Ns = (0.2, 1.5, 64, 90.0, 0.1, 64) if Gy > 8 else (0.05, 1.5, 64, 90.0, 0.1, 64)
+    g = lib.pact.Geometry(n_elem=n_elem, radius=R, phi0=phi0, ny=64, nx=64, px=0.1, P=16, stride=8, fwhm=1.0,
+                          sos_ny=Gy, sos_nx=Gx, sos_spacing=ds)
+    rng = np.random.default_rng(22)
+    v = np.asarray(synth.random_sos((Gy, Gx), v0, rng, amp=0.06, smooth=8), dtype=np.float32)
+    hy = 0.4 * (Gy + 1) * ds
+    centres = np.stack([np.linspace(-25.0, 25.0, 7), np.linspace(-hy, hy, 7)], axis=1).astype(np.float32)
+    c64 = torch.tensor(centres, dtype=torch.float64)
+    fn = lambda vv: Orays.sos_to_delays(vv, f32(ds), f32(v0), c64, n_elem, f32(R), f32(phi0), Ns)
+    gw = rng.standard_normal((centres.shape[0], n_elem)).astype(np.float32)
+    (want,) = Oloss.vjp(fn, (torch.tensor(v, dtype=torch.float64),), torch.tensor(gw, dtype=torch.float64))
+    got = lib.pact.sos_to_delays_adjoint(dev32(v), g, v0, dev32(centres), Ns, dev32(gw))
+    again = lib.pact.sos_to_delays_adjoint(dev32(v), g, v0, dev32(centres), Ns, dev32(gw))
+    torch.cuda.synchronize()
+    err = rel_l2(got, want)
+    print(f"adjoint on {Gy} x {Gx}: rel L2 {err:.2e}")
+    assert err < TOL_GRAD
+    assert torch.equal(got, again), "the adjoint is deterministic"
+
+
 def _wavefronts(scan, seed):
     """A plausible float32 wavefront table (oracle rays through a random SOS)."""
     ov = OracleView(scan)
