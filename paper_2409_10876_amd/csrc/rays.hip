@@ -14,8 +14,11 @@
 // integrand is evaluated as delta / (v0 + delta) = 1 - v0 / v, which keeps the
 // contrast exact instead of cancelling 1 against v0 / v.
 //
-// Adjoint (gather by tile).  dL/dv at a node collects dL/dw * dl * v0 / v^2 *
-// (bilinear weight) from every sample whose cell touches the node.  One
+// Adjoint.  dL/dv at a node collects dL/dw * dl * v0 / v^2 * (bilinear weight)
+// from every sample whose cell touches the node.  The main form scatters over
+// the whole grid, or over bands of its rows, held in one CU's LDS
+// (rays_adj_grid_kernel, described there).  The tiled form below gathers by
+// node tile and is used only where even a band of 8 rows does not fit.  One
 // workgroup owns a kTile x kTile tile of nodes: it stages the contrast of the
 // tile and its one-node halo, and for every patch it enumerates only the
 // elements whose ray direction falls in the angular sector the tile's cell
@@ -47,10 +50,7 @@ int device_cu_count();
 namespace {
 
 constexpr int kThreads = 1024;    // forward workgroup
-#ifndef PACT_ADJ_TILE
-#define PACT_ADJ_TILE 4
-#endif
-constexpr int kTile = PACT_ADJ_TILE;  // adjoint tile side (nodes)
+constexpr int kTile = 4;              // tile side (nodes) of the tiled adjoint
 constexpr int kAdjThreads = 256;      // adjoint workgroup
 // padded rows a wave loads before storing them while a workgroup stages the contrast grid (1, 2 and 3
 // time the same at 140^2 nodes)
