@@ -468,10 +468,10 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
     }
 }
 
-// Adjoint (scatter over the whole grid).  Used when the contrast grid and an integer accumulator of the
-// same shape both fit in one CU's LDS (G <= 141).  One 1024-thread workgroup per CU; the rays are cut
-// into K segments of consecutive samples (K chosen on the host so that the work is about one segment
-// per lane) and work item (ray, segment) goes to one lane, which walks its samples with the same
+// Adjoint (scatter over the whole grid, when the contrast grid and an integer accumulator of the same shape
+// both fit in one CU's LDS, G <= 141; else over bands of its rows, below).  One 1024-thread workgroup per
+// CU; the rays are cut into K segments of consecutive samples (K chosen on the host so that the work is
+// about one segment per lane) and work item (ray, segment) goes to one lane, which walks its samples with the same
 // position formula as the forward pass.  Rays are numbered element-major, so that the lanes of a wave
 // hold parallel rays from neighbouring patch centres and rarely hit the same node at once.  A lane sums
 // the four bilinear shares of consecutive samples in the same cell in registers and adds them to the
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
 // F = 2^30 / bound (rounded down to a power of two) keeps every partial sum inside int32 with room for
 // the truncation of each flushed term.  Integer sums do not depend on the order of the atomics, so the result is
 // deterministic.  The interior nodes are written, scaled back, to one partial grid per workgroup, and
-// the two reduce kernels add the partial grids in a fixed order.
+// a reduce kernel adds the partial grids in a fixed order.
 constexpr int kGridThreads = 1024;
 
 // Adjoint shares of samples s0 .. s1 - 1 (s1 > s0) of one ray, added into the fixed-point accumulator acc
