@@ -106,16 +106,17 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 
 // ---- Sums of partial results in a fixed order ----
 
-// sum_k p[k * stride] for k = 0 .. n - 1, added in order (loads issued 8 at a time).
+// sum_k p[k * stride] for k = 0 .. n - 1, added in order (loads issued B at a time).
+template <int B = 8>
 __device__ __forceinline__ float ordered_strided_sum(const float* __restrict__ p, int n, size_t stride) {
     float s = 0.0f;
     int k = 0;
-    for (; k + 8 <= n; k += 8) {
-        float v[8];
+    for (; k + B <= n; k += B) {
+        float v[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = p[static_cast<size_t>(k + u) * stride];
+        for (int u = 0; u < B; ++u) v[u] = p[static_cast<size_t>(k + u) * stride];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
+        for (int u = 0; u < B; ++u) s += v[u];
     }
     for (; k < n; ++k) s += p[static_cast<size_t>(k) * stride];
     return s;

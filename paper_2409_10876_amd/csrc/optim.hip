@@ -15,27 +15,32 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ float sgn(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
 
-// TV pairs of node (a, b): its value share (the pairs it starts) and its subgradient (all four pairs).
+// TV pairs of node (a, b): its value share (the pairs it starts) and its subgradient (all four pairs).  The
+// neighbours' values and masks are loaded unconditionally (the node itself stands in at the grid edge), so
+// that all the loads are in flight together; the pairs that exist are then taken as written.
 __device__ __forceinline__ void tv_node(const float* __restrict__ v, const unsigned char* __restrict__ mask, int idx,
                                         int a, int b, int Gy, int Gx, float& tv, float& g) {
-    const float x = v[idx];
-    const bool m = mask[idx] != 0;
+    const bool has_d = a + 1 < Gy, has_r = b + 1 < Gx, has_u = a > 0, has_l = b > 0;
+    const int id = has_d ? idx + Gx : idx, ir = has_r ? idx + 1 : idx;
+    const int iu = has_u ? idx - Gx : idx, il = has_l ? idx - 1 : idx;
+    const float x = v[idx], vd = v[id], vr = v[ir], vu = v[iu], vl = v[il];
+    const bool m = mask[idx] != 0, md = mask[id] != 0, mr = mask[ir] != 0, mu = mask[iu] != 0, ml = mask[il] != 0;
     tv = 0.0f;
     g = 0.0f;
     // pair (a, b)-(a+1, b) and (a, b)-(a, b+1): counted once, by their first node
-    if (a + 1 < Gy && (m || mask[idx + Gx])) {
-        const float dv = v[idx + Gx] - x;
+    if (has_d && (m || md)) {
+        const float dv = vd - x;
         tv += fabsf(dv);
         g -= sgn(dv);
     }
-    if (b + 1 < Gx && (m || mask[idx + 1])) {
-        const float dv = v[idx + 1] - x;
+    if (has_r && (m || mr)) {
+        const float dv = vr - x;
         tv += fabsf(dv);
         g -= sgn(dv);
     }
     // the same pairs seen from their second node
-    if (a > 0 && (m || mask[idx - Gx])) g += sgn(x - v[idx - Gx]);
-    if (b > 0 && (m || mask[idx - 1])) g += sgn(x - v[idx - 1]);
+    if (has_u && (m || mu)) g += sgn(x - vu);
+    if (has_l && (m || ml)) g += sgn(x - vl);
 }
 
 __global__ __launch_bounds__(kThreads) void tv_kernel(const float* __restrict__ v,
@@ -92,12 +97,14 @@ __global__ __launch_bounds__(kThreads) void tv_adam_kernel(const float* __restri
     float tv = 0.0f;
     if (idx < Gy * Gx) {
         const int a = idx / Gx, b = idx - a * Gx;
+        // every load up front (m, v and the gradient also for fixed nodes, which leave them unchanged)
+        const float gd = grad[idx];
+        float mm = m[idx], vv = v[idx];
         float g_tv = 0.0f;
         if (lambda != 0.0f) tv_node(sos_in, mask, idx, a, b, Gy, Gx, tv, g_tv);
         float p = sos_in[idx];
         if (mask[idx]) {
-            float mm = m[idx], vv = v[idx];
-            p = adam_node(p, fmaf(lambda, g_tv, grad[idx]), mm, vv, step, lr, b1, b2, eps);
+            p = adam_node(p, fmaf(lambda, g_tv, gd), mm, vv, step, lr, b1, b2, eps);
             m[idx] = mm;
             v[idx] = vv;
         }

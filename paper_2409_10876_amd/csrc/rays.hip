@@ -636,7 +636,7 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
 
 // Sum of the per-workgroup partial grids in a fixed order.  A workgroup owns 64 consecutive nodes; its
 // wave s sums, for those nodes, the s-th of kAdjSlices contiguous runs of partials (in order), so that
-// every load of a wave is one 256-byte row and each lane has 8 loads in flight; the run sums then meet in
+// every load of a wave is one 256-byte row and each lane has 16 loads in flight; the run sums then meet in
 // LDS and are added in order (= or += into out).
 constexpr int kAdjSlices = 16;
 
@@ -645,7 +645,8 @@ __device__ __forceinline__ float adj_run_sum(const float* __restrict__ partial, 
                                              int slice) {
     const int per = (n_part + kAdjSlices - 1) / kAdjSlices;
     const int p0 = slice * per, p1 = min(p0 + per, n_part);
-    return p1 > p0 ? ordered_strided_sum(partial + static_cast<size_t>(p0) * n_nodes + node, p1 - p0, n_nodes)
+    return p1 > p0 ? ordered_strided_sum<16>(partial + static_cast<size_t>(p0) * n_nodes + node, p1 - p0,
+                                                   n_nodes)
                    : 0.0f;
 }
 
