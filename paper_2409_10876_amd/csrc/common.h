@@ -106,7 +106,8 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 
 // ---- Sums of partial results in a fixed order ----
 
-// sum_k p[k * stride] for k = 0 .. n - 1, added in order (loads issued B at a time).
+// sum_k p[k * stride] for k = 0 .. n - 1 (n >= 1), added in order; loads are issued B at a time, the last
+// partial batch too (its missing entries load element n - 1 and are not added).
 template <int B = 8>
 __device__ __forceinline__ float ordered_strided_sum(const float* __restrict__ p, int n, size_t stride) {
     float s = 0.0f;
@@ -118,7 +119,13 @@ __device__ __forceinline__ float ordered_strided_sum(const float* __restrict__ p
 #pragma unroll
         for (int u = 0; u < B; ++u) s += v[u];
     }
-    for (; k < n; ++k) s += p[static_cast<size_t>(k) * stride];
+    if (k < n) {
+        float v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = p[static_cast<size_t>(min(k + u, n - 1)) * stride];
+#pragma unroll
+        for (int u = 0; u < B; ++u) s = k + u < n ? s + v[u] : s;
+    }
     return s;
 }
 
