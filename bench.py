@@ -79,10 +79,10 @@ def traffic_bytes(stage):
 # copy kernel read as 256 MiB; rocprofv3 counter runs recorded under profiles/), keyed to the kernel source
 # it was taken on.
 TRAFFIC = {
-    "sos_to_delays": {"source": "rays.hip", "sha256_16": "9a8da626ca2daaf8", "bytes": 1068942},
-    "loss_and_grad": {"source": "loss.hip", "sha256_16": "7e42a2837f607e5c", "bytes": 61940190},
-    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "9a8da626ca2daaf8", "bytes": 48828575},
-    "tv_adam_step": {"source": "optim.hip", "sha256_16": "58740c5b3292f6bb", "bytes": 684339}
+    "sos_to_delays": {"source": "rays.hip", "sha256_16": "b48d5d572b21af96", "bytes": 1068947},
+    "loss_and_grad": {"source": "loss.hip", "sha256_16": "387f46a72608b6aa", "bytes": 61953624},
+    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "b48d5d572b21af96", "bytes": 48847196},
+    "tv_adam_step": {"source": "optim.hip", "sha256_16": "d8c556e2161b22f0", "bytes": 749997}
 }
 
 
