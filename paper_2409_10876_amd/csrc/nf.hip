@@ -250,6 +250,7 @@ struct NfFwdLds {
     alignas(16) __bf16 hA[kPc * kLdH];
     alignas(16) __bf16 hB[kPc * kLdH];
     alignas(16) __bf16 hT[2][kH * kLdT];      // feature-major staging of the activations being stored
+    alignas(16) unsigned onw[4 * kH];         // the chunk's ReLU mask words, stored once per chunk
 };
 
 // Stored activations of one chunk: h1..h4 feature-major, [4][128][32] BF16 (32 KB), chunk = ray * n_chunks + ch.
@@ -400,25 +401,28 @@ __global__ __launch_bounds__(kNTF, 2) void nf_fwd_kernel(NfArgs a, float* __rest
             float h[2][2][4];
             nf_layer2<8>(w1, sm.feat, kLd1, acc);
             nf_activate2(acc, sm.tab.bias[0], sm.hA, dst ? sm.hT[0] : nullptr, h);
-            if (on) nf_store_on2(h, on);
+            if (on) nf_store_on2(h, sm.onw + 0 * kH);
             __syncthreads();
             if (dst) nf_store_layer256(sm.hT[0], dst);
             nf_layer2<4>(w2, sm.hA, kLdH, acc);
             nf_activate2(acc, sm.tab.bias[1], sm.hB, dst ? sm.hT[1] : nullptr, h);
-            if (on) nf_store_on2(h, on + kH);
+            if (on) nf_store_on2(h, sm.onw + 1 * kH);
             __syncthreads();
             if (dst) nf_store_layer256(sm.hT[1], dst + kH * kPc);
             nf_layer2<4>(w3, sm.hB, kLdH, acc);
             nf_activate2(acc, sm.tab.bias[2], sm.hA, dst ? sm.hT[0] : nullptr, h);
-            if (on) nf_store_on2(h, on + 2 * kH);
+            if (on) nf_store_on2(h, sm.onw + 2 * kH);
             __syncthreads();
             if (dst) nf_store_layer256(sm.hT[0], dst + 2 * kH * kPc);
             nf_layer2<4>(w4, sm.hA, kLdH, acc);
             nf_activate2(acc, sm.tab.bias[3], sm.hB, dst ? sm.hT[1] : nullptr, h);
-            if (on) nf_store_on2(h, on + 3 * kH);
+            if (on) nf_store_on2(h, sm.onw + 3 * kH);
             nf_head_partial2(h, sm.tab.w5, sm.headp);
             __syncthreads();
             if (dst) nf_store_layer256(sm.hT[1], dst + 3 * kH * kPc);
+            static_assert(2 * kNTF == 4 * kH, "one pair of mask words per thread");
+            if (on)      // the 4 layers' mask words, one coalesced store (written to LDS before the last barrier)
+                *reinterpret_cast<uint2*>(on + 2 * threadIdx.x) = *reinterpret_cast<const uint2*>(sm.onw + 2 * threadIdx.x);
             if (threadIdx.x < kPc) {
                 const float f = nf_head_sum(sm.headp, threadIdx.x, sm.tab.b5);
                 if (f_out) f_out[chunk * kPc + threadIdx.x] = f;
