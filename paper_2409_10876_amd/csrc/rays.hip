@@ -499,22 +499,23 @@ __device__ __forceinline__ void adj_segment(const float* vs, int* acc, int s0, i
     const int W = g.W;
     float sf = static_cast<float>(s0) + 0.5f;
     float fx, fy;
-    // the first sample's cell (banded: none yet, so that the first taken sample opens its cell)
+    // the first sample's cell (banded: none yet, so that the first taken sample opens its cell) and the
+    // contrast at its corners, loaded again only when a sample enters another cell (about every second
+    // sample at half a node per step)
     int cprev = kBanded ? -1 : sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
+    float v00 = 0.0f, v01 = 0.0f, v10 = 0.0f, v11 = 0.0f;
+    if (!kBanded) v00 = vs[cprev], v01 = vs[cprev + 1], v10 = vs[cprev + W], v11 = vs[cprev + W + 1];
     float a00 = 0.0f, a01 = 0.0f, a10 = 0.0f, a11 = 0.0f;
     for (int s = s0; s < s1; ++s, sf += 1.0f) {
         int c = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
         if (kBanded) {
             c -= cbase;
             if (c < 0 || c >= band_cells) continue;
-            if (cprev < 0) cprev = c;
+            if (cprev < 0) {
+                cprev = c;
+                v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
+            }
         }
-        const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
-        const float top = fmaf(fx, v01 - v00, v00);
-        const float bot = fmaf(fx, v11 - v10, v10);
-        const float r = __builtin_amdgcn_rcpf(v0 + fmaf(fy, bot - top, top));
-        const float qv = q0 * r * r;                     // dL/dw * dl * v0 / v^2, times F
-        const float qy1 = qv * fy, qy0 = qv - qy1;
         if (c != cprev) {
             atomicAdd(acc + cprev, static_cast<int>(a00));
             atomicAdd(acc + cprev + 1, static_cast<int>(a01));
@@ -522,7 +523,13 @@ __device__ __forceinline__ void adj_segment(const float* vs, int* acc, int s0, i
             atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
             cprev = c;
             a00 = a01 = a10 = a11 = 0.0f;
+            v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
         }
+        const float top = fmaf(fx, v01 - v00, v00);
+        const float bot = fmaf(fx, v11 - v10, v10);
+        const float r = __builtin_amdgcn_rcpf(v0 + fmaf(fy, bot - top, top));
+        const float qv = q0 * r * r;                     // dL/dw * dl * v0 / v^2, times F
+        const float qy1 = qv * fy, qy0 = qv - qy1;
         a00 += qy0 - qy0 * fx;
         a01 += qy0 * fx;
         a10 += qy1 - qy1 * fx;
