@@ -98,9 +98,12 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 // the columns l, l + 64, ... of each, kStageChunks chunks of 64 columns at a time, so that rows and chunks
 // are wave-uniform and no node needs a division.  kRows rows are loaded before any is stored, so each
 // lane has up to kRows * kStageChunks loads in flight (a load and its wait per node would serialise some
-// twenty round trips to L2 in every workgroup).  With acc, the same nodes of acc are cleared; vmin and
-// nan_check receive the smallest v and 0 * (every contrast) (NaN if any node is not finite).
-constexpr int kStageChunks = 4;   // one pass covers W <= 256 (every square grid that fits in LDS)
+// twenty round trips to L2 in every workgroup).  A lane's column offsets and column tests are formed once
+// per pass of chunks and its loads address the grid by 32-bit byte offsets from the base pointer (every grid
+// staged here has far fewer than 2^30 nodes: it, or each band of it, fits in LDS, and there are at most 64
+// bands).  With acc, the same nodes of acc are cleared; vmin and nan_check receive the smallest v and
+// 0 * (every contrast) (NaN if any node is not finite).
+constexpr int kStageChunks = 3;   // one pass covers W <= 192 (140^2 nodes: W = 142)
 
 template <int kRows>
 __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, float v0, const RayGeo& g, float* vs,
@@ -109,36 +112,44 @@ __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, fl
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
-    for (int cb = 0; cb < W; cb += 64 * kStageChunks)
-    for (int r0 = wave; r0 < H; r0 += kRows * nw) {
-        // every load is unconditional (node 0 for the ring and for columns beyond the grid) and its value is
-        // used only after all of them are issued
-        float x[kRows][kStageChunks];
+    const char* base = reinterpret_cast<const char*>(sos);
+    for (int cb = 0; cb < W; cb += 64 * kStageChunks) {
+        unsigned colb[kStageChunks];     // byte offset of the lane's grid column in a row (column 0 outside)
+        bool cin[kStageChunks];          // the column lies in the grid (not the ring, not beyond)
 #pragma unroll
-        for (int k = 0; k < kRows; ++k) {
-            const int a = R0 + r0 + k * nw - 1;
-            const bool row_in = a >= 0 && a < g.Gy;
-#pragma unroll
-            for (int q = 0; q < kStageChunks; ++q) {
-                const int b = cb + 64 * q + lane - 1;
-                const bool in = row_in && b >= 0 && b < g.Gx;
-                x[k][q] = sos[in ? a * g.Gx + b : 0];
-            }
+        for (int q = 0; q < kStageChunks; ++q) {
+            const int b = cb + 64 * q + lane - 1;
+            cin[q] = static_cast<unsigned>(b) < static_cast<unsigned>(g.Gx);
+            colb[q] = cin[q] ? static_cast<unsigned>(b) * 4u : 0u;
         }
+        for (int r0 = wave; r0 < H; r0 += kRows * nw) {
+            // every load is unconditional and in the grid (row 0 stands in for ring rows, column 0 for ring and
+            // outside columns, whose values are not used), and its value is used only after all are issued
+            float x[kRows][kStageChunks];
 #pragma unroll
-        for (int k = 0; k < kRows; ++k) {
-            const int r = r0 + k * nw, a = R0 + r - 1;
-            if (r < H) {
+            for (int k = 0; k < kRows; ++k) {
+                const int a = R0 + r0 + k * nw - 1;
                 const bool row_in = a >= 0 && a < g.Gy;
+                const unsigned rowb = row_in ? static_cast<unsigned>(a * g.Gx) * 4u : 0u;
 #pragma unroll
-                for (int q = 0; q < kStageChunks; ++q) {
-                    const int c = cb + 64 * q + lane, b = c - 1;
-                    if (c < W) {
-                        const float d = (row_in && b >= 0 && b < g.Gx) ? x[k][q] - v0 : 0.0f;
-                        vs[r * W + c] = d;
-                        if (acc) acc[r * W + c] = 0;
-                        vmin = fminf(vmin, v0 + d);
-                        nan_check += 0.0f * d;
+                for (int q = 0; q < kStageChunks; ++q)
+                    x[k][q] = *reinterpret_cast<const float*>(base + (rowb + colb[q]));
+            }
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                const int r = r0 + k * nw, a = R0 + r - 1;
+                if (r < H) {
+                    const bool row_in = a >= 0 && a < g.Gy;
+#pragma unroll
+                    for (int q = 0; q < kStageChunks; ++q) {
+                        const int c = cb + 64 * q + lane;
+                        if (c < W) {
+                            const float d = (row_in && cin[q]) ? x[k][q] - v0 : 0.0f;
+                            vs[r * W + c] = d;
+                            if (acc) acc[r * W + c] = 0;
+                            vmin = fminf(vmin, v0 + d);
+                            nan_check += 0.0f * d;
+                        }
                     }
                 }
             }
