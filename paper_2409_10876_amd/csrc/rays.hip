@@ -208,12 +208,18 @@ __device__ __forceinline__ bool segment_inside(int s0, int s1, float gx0, float 
     return in;
 }
 
+// The staged grid seen as an LDS pointer: a gather's address is then one shift-and-add of the cell index
+// (through a generic pointer the array's base is added by an instruction of its own).
+using LdsFloat = __attribute__((address_space(3))) const float;
+__device__ __forceinline__ LdsFloat* lds_view(const float* vs) { return (LdsFloat*)(vs); }
+
 template <bool kClamp>
 __device__ __forceinline__ float contrast_sample(const float* vs, float sf, float gx0, float gy0, float dgx, float dgy,
                                                  const RayGeo& g) {
     float fx, fy;
     const int c = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
-    const float v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + g.W], v11 = vs[c + g.W + 1];
+    LdsFloat* p = lds_view(vs) + c;
+    const float v00 = p[0], v01 = p[1], v10 = p[g.W], v11 = p[g.W + 1];
     const float top = fmaf(fx, v01 - v00, v00);
     const float bot = fmaf(fx, v11 - v10, v10);
     return fmaf(fy, bot - top, top);
@@ -224,15 +230,16 @@ template <bool kClamp>
 __device__ __forceinline__ float fwd_segment(const float* vs, int s0, int s1, float v0, float gx0, float gy0,
                                              float dgx, float dgy, const RayGeo& g) {
     float acc0 = 0.0f, acc1 = 0.0f;
+    // the loop runs on the sample's float coordinate alone (exact: sample counts are far below 2^24)
     float sf = static_cast<float>(s0) + 0.5f;
-    int s = s0;
-    for (; s + 1 < s1; s += 2, sf += 2.0f) {
+    const float sf_pair_end = static_cast<float>(s1) - 0.5f;     // a pair starting at sf fits while sf < this
+    for (; sf < sf_pair_end; sf += 2.0f) {
         const float d0 = contrast_sample<kClamp>(vs, sf, gx0, gy0, dgx, dgy, g);
         const float d1 = contrast_sample<kClamp>(vs, sf + 1.0f, gx0, gy0, dgx, dgy, g);
         acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
         acc1 = fmaf(d1, __builtin_amdgcn_rcpf(v0 + d1), acc1);
     }
-    if (s < s1) {
+    if (sf < static_cast<float>(s1)) {
         const float d0 = contrast_sample<kClamp>(vs, sf, gx0, gy0, dgx, dgy, g);
         acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
     }
@@ -513,18 +520,20 @@ __device__ __forceinline__ void adj_segment(const float* vs, int* acc, int s0, i
     // the first sample's cell (banded: none yet, so that the first taken sample opens its cell) and the
     // contrast at its corners, loaded again only when a sample enters another cell (about every second
     // sample at half a node per step)
+    LdsFloat* lv = lds_view(vs);
     int cprev = kBanded ? -1 : sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
     float v00 = 0.0f, v01 = 0.0f, v10 = 0.0f, v11 = 0.0f;
-    if (!kBanded) v00 = vs[cprev], v01 = vs[cprev + 1], v10 = vs[cprev + W], v11 = vs[cprev + W + 1];
+    if (!kBanded) v00 = lv[cprev], v01 = lv[cprev + 1], v10 = lv[cprev + W], v11 = lv[cprev + W + 1];
     float a00 = 0.0f, a01 = 0.0f, a10 = 0.0f, a11 = 0.0f;
-    for (int s = s0; s < s1; ++s, sf += 1.0f) {
+    const float sf1 = static_cast<float>(s1);    // the loop runs on sf alone (exact: counts far below 2^24)
+    for (; sf < sf1; sf += 1.0f) {
         int c = sample_cell<kClamp>(sf, gx0, gy0, dgx, dgy, g, fx, fy);
         if (kBanded) {
             c -= cbase;
             if (c < 0 || c >= band_cells) continue;
             if (cprev < 0) {
                 cprev = c;
-                v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
+                v00 = lv[c], v01 = lv[c + 1], v10 = lv[c + W], v11 = lv[c + W + 1];
             }
         }
         if (c != cprev) {
@@ -534,7 +543,7 @@ __device__ __forceinline__ void adj_segment(const float* vs, int* acc, int s0, i
             atomicAdd(acc + cprev + W + 1, static_cast<int>(a11));
             cprev = c;
             a00 = a01 = a10 = a11 = 0.0f;
-            v00 = vs[c], v01 = vs[c + 1], v10 = vs[c + W], v11 = vs[c + W + 1];
+            v00 = lv[c], v01 = lv[c + 1], v10 = lv[c + W], v11 = lv[c + W + 1];
         }
         const float top = fmaf(fx, v01 - v00, v00);
         const float bot = fmaf(fx, v11 - v10, v10);
