@@ -115,18 +115,20 @@ def test_sos_to_delays_adjoint(lib, scan):
     assert rel_l2(acc - 1.0, 2.0 * want) < TOL_GRAD
 
 
-def test_rays_on_a_wide_grid(lib):
-    """Forward and adjoint on a 6 x 300 node grid: its padded rows (302 nodes) are wider than one pass of
-    the kernels' 64-column chunks, so every row is staged and written in more than one pass."""
-    announce("rays on a 6 x 300 node grid")
-    Gy, Gx, ds, v0, n_elem, R, phi0, Ns = 6, 300, 0.5, 1.5, 64, 90.0, 0.1, 64
+@pytest.mark.parametrize("Gx", [300, 190, 191])
+def test_rays_on_a_wide_grid(lib, Gx):
+    """Forward and adjoint on 6-row grids whose padded rows are staged in passes of the kernels' 64-column
+    chunks: 302 nodes take several passes, 192 exactly one full pass, and 193 a second pass of one column."""
+    announce(f"rays on a 6 x {Gx} node grid")
+    Gy, ds, v0, n_elem, R, phi0, Ns = 6, 0.5, 1.5, 64, 90.0, 0.1, 64
     g = lib.pact.Geometry(n_elem=n_elem, radius=R, phi0=phi0, ny=64, nx=64, px=0.1, P=16, stride=8, fwhm=1.0,
                           sos_ny=Gy, sos_nx=Gx, sos_spacing=ds)
     rng = np.random.default_rng(21)
     # smoother than the other cases' fields: FP32 rounds positions at node coordinates up to 301, twice
     # those of the 140-node grids, and the delay error scales with the field's slope between nodes
     v = np.asarray(synth.random_sos((Gy, Gx), v0, rng, amp=0.06, smooth=8), dtype=np.float32)
-    centres = np.stack([np.linspace(-70.0, 70.0, 7), np.linspace(-1.5, 1.5, 7)], axis=1).astype(np.float32)
+    hx = 70.0 * Gx / 300.0
+    centres = np.stack([np.linspace(-hx, hx, 7), np.linspace(-1.5, 1.5, 7)], axis=1).astype(np.float32)
     c64 = torch.tensor(centres, dtype=torch.float64)
     fn = lambda vv: Orays.sos_to_delays(vv, f32(ds), f32(v0), c64, n_elem, f32(R), f32(phi0), Ns)
     want = fn(torch.tensor(v, dtype=torch.float64))
@@ -136,7 +138,7 @@ def test_rays_on_a_wide_grid(lib):
     got_adj = lib.pact.sos_to_delays_adjoint(dev32(v), g, v0, dev32(centres), Ns, dev32(gw))
     torch.cuda.synchronize()
     e, ea = rel_l2(got, want), rel_l2(got_adj, want_adj)
-    print(f"wide grid: delays rel L2 {e:.2e}, adjoint rel L2 {ea:.2e}")
+    print(f"6 x {Gx} grid: delays rel L2 {e:.2e}, adjoint rel L2 {ea:.2e}")
     assert e < TOL_DELAYS
     assert ea < TOL_GRAD
 
