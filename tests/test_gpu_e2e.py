@@ -86,16 +86,16 @@ def test_graph_replay_matches_eager(setup):
     a.step(); b.step()
     a.capture(4)                       # capturing does not run the steps
     torch.cuda.synchronize()
-    assert rel_l2(a.sos - sd.v0, b.sos - sd.v0) < 1e-5
+    assert torch.equal(a.sos, b.sos)
     for _ in range(3):
         a.run(4)
         torch.cuda.synchronize()       # eager work and syncs between replays
         b.run(4)
         torch.cuda.synchronize()
         assert a.t.tolist() == b.t.tolist()
-        err = rel_l2(a.sos - sd.v0, b.sos - sd.v0)
-        assert err < 1e-4, err
-        assert abs(a.loss.item() - b.loss.item()) <= 1e-4 * abs(b.loss.item())
+        # every kernel of the step is deterministic: the replayed state is the eager state, bit for bit
+        assert torch.equal(a.sos, b.sos) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+        assert abs(a.loss.item() - b.loss.item()) <= 1e-6 * abs(b.loss.item())
 
 
 def test_autograd_function(setup):
