@@ -25,9 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32 instructions (this build disables them): 256 CUs x 64 lanes x 2 flops
-# (FMA) x 2.4 GHz.  The published 157.3 TFLOP/s counts packed FP32.
-ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# MI355X published FP32 vector peak (it counts packed FP32 instructions); the roofline fractions of the
+# ALU-bound stages are quoted against it.
+FP32_PUBLISHED_PEAK_TFLOPS = 157.3
+# The issue-rate bound of this build, reported beside it: packed FP32 is disabled, so one wave64 FP32 FMA
+# per cycle per CU, 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+ALU_ISSUE_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 COPY_REF_BYTES = 256 << 20
 MFMA_BF16_PEAK_TFLOPS = 2500.0                            # dense BF16 MFMA, MI355X
 # Algorithmic FP32 operations per ray sample (FMA = 2), from the definitions of the two ray maps:
@@ -53,7 +56,7 @@ def parse():
     ap.add_argument("--nf-steps", type=int, default=3, help="neural-field optimisation steps timed (0: skip)")
     ap.add_argument("--warm-scans", type=int, default=4,
                     help="held-out scans of the learned warm-start comparison (0: skip)")
-    ap.add_argument("--batch-scans", type=int, default=0,
+    ap.add_argument("--batch-scans", type=int, default=32,
                     help="also time this many independent uneven scans solved together (0: skip)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run one plain 256 MiB device copy kernel first (the reference for HBM counter scaling)")
@@ -82,8 +85,37 @@ TRAFFIC = {
     "sos_to_delays": {"source": "rays.hip", "sha256_16": "54c341ee909d8aad", "bytes": 1067917},
     "loss_and_grad": {"source": "loss.hip", "sha256_16": "387f46a72608b6aa", "bytes": 61953624},
     "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "54c341ee909d8aad", "bytes": 48840806},
-    "tv_adam_step": {"source": "optim.hip", "sha256_16": "d8c556e2161b22f0", "bytes": 749997}
+    "tv_adam_step": {"source": "optim.hip", "sha256_16": "d8c556e2161b22f0", "bytes": 749997},
 }
+
+
+def active_samples(scan, support):
+    """Ray samples (all patches and elements) that can touch a node inside the support disc: those within the
+    support radius grown by a cell diagonal, at the midpoints of each ray's part inside the SOS box (all samples
+    without a support).  FP64, from the geometry alone."""
+    import numpy as np
+    from oracle.geometry import patch_centres
+    total = scan.n_patches * scan.n_elem * scan.n_samples
+    if not support > 0:
+        return total
+    c = patch_centres(scan.ny, scan.nx, scan.px, scan.P, scan.stride).numpy()
+    phi = scan.phi0 + 2 * np.pi * np.arange(scan.n_elem) / scan.n_elem
+    e = scan.radius * np.stack([np.cos(phi), np.sin(phi)], -1)
+    h = 0.5 * (scan.sos_n + 1) * scan.sos_spacing
+    rc = support + np.sqrt(2.0) * scan.sos_spacing
+    mid = (np.arange(scan.n_samples) + 0.5) / scan.n_samples
+    n = 0
+    for ci in c:
+        d = e - ci
+        L0 = np.linalg.norm(d, axis=-1)
+        u = d / L0[:, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tx = np.where(u[:, 0] != 0, (np.sign(u[:, 0]) * h - ci[0]) / u[:, 0], np.inf)
+            ty = np.where(u[:, 1] != 0, (np.sign(u[:, 1]) * h - ci[1]) / u[:, 1], np.inf)
+        L = np.minimum(np.minimum(L0, tx), ty)
+        p = ci[None, None, :] + (L[:, None] * mid[None, :])[..., None] * u[:, None, :]
+        n += int((np.linalg.norm(p, axis=-1) <= rc).sum())
+    return n
 
 
 def cpu_baseline(scan, inp, n_steps):
@@ -164,7 +196,9 @@ def main():
     print(f"[bench] inputs ready ({time.perf_counter() - t_setup:.1f} s): {synth.describe(scan)}", flush=True)
 
     sd = P.prepare_scan(scan, inp.S, np.asarray(scan.delays, dtype=np.float32), device=dev)
-    solver = P.PixelGridSolver(sd, inp.mask, eps=scan.eps, lam=scan.lam_tv, lr=scan.lr, n_samples=scan.n_samples)
+    # the mask is the disc of free nodes within mask_radius: the rays skip the samples that touch fixed nodes only
+    solver = P.PixelGridSolver(sd, inp.mask, eps=scan.eps, lam=scan.lam_tv, lr=scan.lr, n_samples=scan.n_samples,
+                               support_radius=scan.mask_radius)
     sos0 = solver.sos.clone()
 
     G = args.graph_steps
@@ -205,13 +239,15 @@ def main():
 
     # Per-stage timing, same process and data: HIP events on the launch stream around each stage of
     # optimisation steps run eagerly (ROCm does not allow timing events inside captured graphs).
-    stages = {"sos_to_delays": solver.delays, "loss_and_grad": solver.loss_grad,
-              "sos_to_delays_adjoint": solver.adjoint, "tv_adam_step": solver.tv_update}
+    # the step's launches as the captured graph runs them (the scalar loss only on a graph's last step), and the
+    # ray adjoint on its own (its kernels are the dominant ones)
+    stages = {"sos_to_delays": solver.delays, "loss_and_grad": lambda: solver.loss_grad(with_loss=False),
+              "adjoint_tv_adam": lambda: solver.adjoint_update(with_loss=False),
+              "sos_to_delays_adjoint": solver.adjoint}
     reps = args.timing_steps
     evs = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
            for k in stages}
-    das_ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-              torch.cuda.Event(enable_timing=True))
+    das_ev = tuple(torch.cuda.Event(enable_timing=True) for _ in range(4))
     # keep the GPU busy while Python enqueues the timing pass, so that each event pair brackets only the work
     # between them (no host launch gaps)
     torch.cuda._sleep(int(args.timing_steps * 2_000_000))
@@ -220,6 +256,8 @@ def main():
     das_ev[1].record()
     sd.Y = P.pact.patch_fft(sd.stack, sd.geom, half=True, out=sd.Y)
     das_ev[2].record()
+    sd.T = P.pact.project_spectra(sd.Y, sd.geom, sd.d, out=sd.T)
+    das_ev[3].record()
     for r in range(reps):
         for k, fn in stages.items():
             evs[k][r][0].record()
@@ -229,19 +267,22 @@ def main():
     breakdown = {k: 1e3 * sum(a.elapsed_time(b) for a, b in v) / reps for k, v in evs.items()}
     breakdown["das_stack_once"] = 1e3 * das_ev[0].elapsed_time(das_ev[1])
     breakdown["patch_fft_once"] = 1e3 * das_ev[1].elapsed_time(das_ev[2])
+    breakdown["project_spectra_once"] = 1e3 * das_ev[2].elapsed_time(das_ev[3])
     N, M, Pp = scan.n_patches, scan.M, scan.P
     G2 = scan.sos_n * scan.sos_n
-    samples = N * scan.n_elem * scan.n_samples
+    # the ray samples the method needs: those that can touch a free node (the others add exactly zero)
+    samples = active_samples(scan, solver.support)
     rays_io = N * scan.n_elem * 4
     # per stage: (kernels, bound, algorithmic work per launch, unit of the work)
     work = {
         "sos_to_delays": ("rays_fwd_kernel", "alu", samples * FLOPS_PER_SAMPLE_FWD, "flop"),
-        "loss_and_grad": ("loss_grad_kernel + loss_finish_kernel", "hbm",
-                          N * M * Pp * (Pp // 2 + 1) * 8 + 2 * rays_io + 4, "byte"),   # Y once, w in, dL/dw out
+        # the projected spectra (five floats per patch and bin) once, w in, dL/dw out
+        "loss_and_grad": ("loss_proj_kernel", "hbm", N * Pp * (Pp // 2 + 1) * 20 + 2 * rays_io, "byte"),
         "sos_to_delays_adjoint": ("rays_adj_grid_kernel + rays_adj_reduce_kernel", "alu",
                                   samples * FLOPS_PER_SAMPLE_ADJ, "flop"),
-        # sos in, sos out, m and v read and written, grad, mask
-        "tv_adam_step": ("tv_adam_kernel", "hbm", G2 * (4 * 7 + 1) + 12, "byte"),
+        # the step's last two launches: the grid adjoint, then its partials' sum fused with TV and Adam
+        "adjoint_tv_adam": ("rays_adj_grid_kernel + adj_reduce_tv_adam_kernel", "alu",
+                            samples * FLOPS_PER_SAMPLE_ADJ, "flop"),
     }
     rooflines = {}
     for k, (kern, bound, units, unit) in work.items():
@@ -249,10 +290,18 @@ def main():
         if unit == "byte":
             ach, peak, u = units / (us * 1e-6) / 1e9, HBM_PEAK_GBS, "GB/s"
         else:
-            ach, peak, u = units / (us * 1e-6) / 1e12, ALU_PEAK_TFLOPS, "TFLOP/s"
+            ach, peak, u = units / (us * 1e-6) / 1e12, FP32_PUBLISHED_PEAK_TFLOPS, "TFLOP/s"
         rooflines[k] = {"bound": bound, "kernel": kern, "achieved": ach, "peak": peak, "unit": u, "frac": ach / peak,
                         "traffic": traffic_bytes(k), "alg_" + unit + "s_per_launch": units, "avg_launch_us": us}
+        if unit == "flop":
+            rooflines[k]["issue_peak"] = ALU_ISSUE_PEAK_TFLOPS
+            rooflines[k]["frac_of_issue_peak"] = ach / ALU_ISSUE_PEAK_TFLOPS
     dominant = max(work, key=lambda k: breakdown[k])
+    # the step as a whole against the HBM roofline: the bytes one optimisation step must move (Y once, w and
+    # dL/dw written and read, the SOS read by both ray kernels and TV + Adam and written, the gradient written
+    # and read, Adam's m and v read and written, the mask) over the graph-replayed time per step
+    step_bytes = work["loss_and_grad"][2] + 2 * rays_io + G2 * 4 * (3 + 1 + 1 + 4) + G2
+    us_step = 1e6 * elapsed / opt_steps
     print("[bench] stage times (us): " + ", ".join(f"{k} {v:.1f}" for k, v in breakdown.items()), flush=True)
 
     out = {
@@ -268,9 +317,14 @@ def main():
         "roofline": dict(rooflines[dominant], stage=dominant,
                          timing=f"HIP events around {reps} eager launches on the launch stream"),
         "rooflines": rooflines,
+        "hbm_frac_step": step_bytes / (us_step * 1e-6) / (HBM_PEAK_GBS * 1e9),
+        "step_alg_bytes": step_bytes,
+        "ray_samples": {"needed": samples, "all": N * scan.n_elem * scan.n_samples,
+                        "note": "the rays skip the samples that touch only fixed nodes (SOS v0, outside the mask)"},
         "stage_us": breakdown,
     }
     out["reconstruction"] = reconstruction_quality(P, sd, solver, inp, scan, elapsed / args.steps)
+    out["precision"] = precision_leg(P, sd, solver, scan, inp.mask)
     out["delay_sweep"] = delay_sweep(P, sd, scan, solver)
     out["paper_neural_field"] = siren_leg(P, sd, scan, inp, reps=args.timing_steps)
     if args.nf_steps > 0:
@@ -287,13 +341,53 @@ def main():
                 "plain_s": sm["t_plain_to_rmse_s"], "warm_s": sm["t_warm_to_rmse_s"],
                 "speedup": sm["t_plain_to_rmse_s"] / sm["t_warm_to_rmse_s"],
                 "rmse_plain_m_per_s": sm["rmse_plain"], "rmse_warm_start_m_per_s": sm["rmse_net"],
-                "scans": sm["n_scans"], "reached_fraction": sm["rmse_target_reached_fraction"]}
+                "scans": sm["n_scans"], "reached_fraction": sm["rmse_target_reached_fraction"],
+                "equal_loss_reached_fraction": sm.get("equal_loss_reached_fraction")}
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, inp, args.cpu_steps)
     out["paper_context"] = dict(PAPER_CONTEXT, this_job_s=elapsed / args.steps,
                                 this_job="das_stack + patch_fft + 500 pixel-grid steps on the paper-shaped scan")
     print(json.dumps(out), flush=True)
+
+
+def precision_leg(P, sd, solver, scan, mask):
+    """FP32 error of every quantity the step produces, against the FP64 oracle at the same state (the SOS after
+    the timed jobs): the half spectra Y (oracle: FP64 windowed FFT of the GPU's DAS stack), and w, the data
+    loss, dL/dw and dL/dv (oracle: its own Y, rays, deconvolution loss and reverse-mode gradient).  Relative
+    L2 errors over every element (the loss: relative error)."""
+    import numpy as np
+    import torch
+    from oracle import loss as Oloss, patches as Opatch
+    from oracle.geometry import patch_centres
+    F64 = torch.float64
+    t0 = time.perf_counter()
+    g = sd.geom
+    sos = solver.sos.clone()
+    rho = solver.support
+    w = P.pact.sos_to_delays(sos, g, scan.v0, sd.centres, scan.n_samples, support=rho)
+    loss, gw = sd.loss_and_grad(w, scan.eps)
+    gv = P.pact.sos_to_delays_adjoint(sos, g, scan.v0, sd.centres, scan.n_samples, gw, support=rho)
+    torch.cuda.synchronize()
+    stack = sd.stack.cpu().double().numpy()
+    Y = Opatch.patch_spectra(stack, scan.P, scan.stride, scan.px, scan.fwhm)
+    geom = dict(sos_spacing=scan.sos_spacing, v0=scan.v0,
+                centres=patch_centres(scan.ny, scan.nx, scan.px, scan.P, scan.stride), n_elem=scan.n_elem,
+                radius=scan.radius, phi0=scan.phi0, n_samples=scan.n_samples, delays=np.asarray(scan.delays),
+                px=scan.px, eps=scan.eps)
+    ones = np.ones((scan.sos_n, scan.sos_n), dtype=bool)
+    L, gv_o, gw_o, w_o = Oloss.loss_and_grad(sos.cpu().to(F64), ones, Y, geom, 0.0)
+    rel = lambda a, b: (torch.linalg.vector_norm(a.cpu().to(b.dtype) - b) / torch.linalg.vector_norm(b)).item()
+    free = torch.as_tensor(np.asarray(mask)).bool()
+    out = {"Y_half": rel(sd.Y, Opatch.half_spectrum(Y)), "w": rel(w, w_o),
+           "loss": abs(loss.item() - L.item()) / abs(L.item()), "dL_dw": rel(gw, gw_o),
+           "dL_dsos": rel(gv.cpu()[free], gv_o[free]),
+           "measure": "relative L2 over every element (loss: relative error; dL/dsos: over the free nodes, the "
+                      "ones the step updates), FP32 GPU against the FP64 oracle",
+           "support_radius_mm": rho, "state": "the SOS after the timed jobs", "oracle_s": time.perf_counter() - t0}
+    print("[bench] precision vs FP64 oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()
+                                                           if isinstance(v, float) and k != "oracle_s"), flush=True)
+    return out
 
 
 def reconstruction_quality(P, sd, solver, inp, scan, job_s):
@@ -305,11 +399,11 @@ def reconstruction_quality(P, sd, solver, inp, scan, job_s):
     N = sd.centres.shape[0]
     X = torch.empty(N, g.P, g.P, dtype=torch.complex64, device=sd.S.device)
     solver.delays()
-    P.pact.loss_and_grad(sd.Y, solver.w, sd.centres, g, sd.d, solver.eps, X=X)
+    sd.loss_and_grad(solver.w, solver.eps, X=X)
     img = P.pact.stitch(P.pact.ifft2_real(X), g)
     # the same with no SOS correction (uniform v0): what the deconvolution alone gives
     w0 = torch.zeros_like(solver.w)
-    P.pact.loss_and_grad(sd.Y, w0, sd.centres, g, sd.d, solver.eps, X=X)
+    sd.loss_and_grad(w0, solver.eps, X=X)
     img0 = P.pact.stitch(P.pact.ifft2_real(X), g)
     das = sd.stack[len(scan.delays) // 2]                  # the d = 0 DAS image
     torch.cuda.synchronize()
@@ -327,30 +421,43 @@ def reconstruction_quality(P, sd, solver, inp, scan, job_s):
 
 
 def delay_sweep(P, sd, scan, solver, counts=(4, 8, 11, 16), reps=20):
-    """Fused loss-and-gradient time against the number of delay channels M (the paper's M-vs-time trend),
-    on spectra of the same patch geometry."""
+    """Fused loss-and-gradient time against the number of delay channels M (the paper's M-vs-time trend), on
+    spectra of the same patch geometry: the direct form, which reads the M spectra at every step, and the
+    projected form the step uses (its per-step work does not depend on M; the projection runs once per scan)."""
     import torch
     g = sd.geom
     N = sd.centres.shape[0]
     out = {}
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(1_000_000)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return 1e3 * a.elapsed_time(b) / reps
+
     for M in counts:
         d = torch.linspace(-0.8, 0.8, M, device=sd.S.device)
         Y = torch.randn(N, M, g.P, g.P // 2 + 1, dtype=torch.complex64, device=sd.S.device)
         ws = torch.empty(max(1, P.pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)), dtype=torch.uint8,
                          device=sd.S.device)
-        loss = torch.zeros(1, device=sd.S.device)
         gw = torch.empty_like(solver.w)
-        P.pact.loss_and_grad(Y, solver.w, sd.centres, g, d, solver.eps, loss=loss, dL_dw=gw, ws=ws)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda._sleep(1_000_000)
-        a.record()
-        for _ in range(reps):
-            P.pact.loss_and_grad(Y, solver.w, sd.centres, g, d, solver.eps, loss=loss, dL_dw=gw, ws=ws)
-        b.record()
-        torch.cuda.synchronize()
-        us = 1e3 * a.elapsed_time(b) / reps
-        out[str(M)] = {"loss_and_grad_us": us, "GB_per_s": N * M * g.P * (g.P // 2 + 1) * 8 / (us * 1e-6) / 1e9}
-        del Y, ws
+        T = P.pact.project_spectra(Y, g, d)
+        us_direct = timed(lambda: P.pact.loss_and_grad(Y, solver.w, sd.centres, g, d, solver.eps, dL_dw=gw, ws=ws,
+                                                       want_loss=False))
+        us_proj = timed(lambda: P.pact.loss_and_grad_projected(T, M, solver.w, sd.centres, g, solver.eps, dL_dw=gw,
+                                                               ws=ws, want_loss=False))
+        us_once = timed(lambda: P.pact.project_spectra(Y, g, d, out=T))
+        out[str(M)] = {"direct_us": us_direct, "direct_GB_per_s": N * M * g.P * (g.P // 2 + 1) * 8 / (us_direct * 1e-6) / 1e9,
+                       "projected_us": us_proj, "project_once_us": us_once}
+        del Y, ws, T
+    print("[bench] delay sweep (us, direct / projected / projection once): " + ", ".join(
+        f"M={k} {v['direct_us']:.1f}/{v['projected_us']:.1f}/{v['project_once_us']:.0f}" for k, v in out.items()),
+        flush=True)
     return out
 
 
@@ -361,6 +468,7 @@ def siren_leg(P, sd, scan, inp, reps=100, graph_steps=50):
     import torch
     import synth
     solver = P.SirenSolver(sd, inp.mask, synth.nf.siren_params(256, 30.0), 256, 30.0, scan.mask_radius, lr=5e-3,
+                           support_radius=scan.mask_radius,
                            eps=scan.eps, n_samples=scan.n_samples)
     solver.step()
     torch.cuda.synchronize()
@@ -405,7 +513,8 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
     for k, sc in enumerate(scans):
         inp = synth.make_inputs(sc, seed=sc.seed)
         sd = P.prepare_scan(sc, inp.S, np.asarray(sc.delays, dtype=np.float32))
-        solvers.append(P.PixelGridSolver(sd, inp.mask, eps=sc.eps, lam=sc.lam_tv, lr=sc.lr, n_samples=sc.n_samples))
+        solvers.append(P.PixelGridSolver(sd, inp.mask, eps=sc.eps, lam=sc.lam_tv, lr=sc.lr, n_samples=sc.n_samples,
+                                         support_radius=sc.mask_radius))
     print(f"[bench] batch: {n_scans} scans prepared in {time.perf_counter() - t0:.1f} s", flush=True)
     t0 = time.perf_counter()
     batch = P.BatchedSolver(solvers, graph_steps=graph_steps, autotune=True)
@@ -570,6 +679,35 @@ def nf_oracle_rate(scan, cfg, n_centres=4, n_elem=32):
                                         f"in {dt:.2f} s"}
 
 
+def nf_bf16_error(solver, scan, cfg, n_centres=4, n_elem=32):
+    """The BF16 error of the neural-field delays at the initial parameters, on a sample of rays: relative L2
+    of the GPU's w against the plain FP64 network (the workload's own precision error) and against the
+    oracle with the same BF16 rounding points (the logic)."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import nf as Onf
+    F64 = torch.float64
+    solver.pack()
+    solver.delays()
+    stride = scan.n_elem // n_elem
+    w = solver.w[:n_centres, ::stride][:, :n_elem].cpu().double()
+    B = torch.tensor(synth.nf.frequencies(cfg), dtype=F64)
+    params = torch.tensor(synth.nf.init_params(cfg), dtype=F64)
+    c = solver.scan.centres[:n_centres].cpu().double()
+    phi = scan.phi0 + 2 * np.pi * np.arange(0, scan.n_elem, stride)[:n_elem] / scan.n_elem
+    ring = torch.tensor(np.stack([scan.radius * np.cos(phi), scan.radius * np.sin(phi)], -1), dtype=F64)
+    rel = lambda a, b: (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()  # noqa: E731
+    out = {}
+    for name, bf in (("w_vs_fp64_network", False), ("w_vs_bf16_rounding_oracle", True)):
+        out[name] = rel(w, Onf.sos_to_delays(params, B, c, ring, scan.mask_radius, scan.v0, cfg.amp,
+                                             scan.n_samples, bf16=bf))
+    out["sample"] = f"{n_centres} patch centres x {n_elem} elements (every {stride}th), initial parameters"
+    print(f"[bench] neural field BF16 error: w rel L2 {out['w_vs_fp64_network']:.2e} vs FP64, "
+          f"{out['w_vs_bf16_rounding_oracle']:.2e} vs the BF16-rounding oracle", flush=True)
+    return out
+
+
 def nf_leg(P, sd, scan, steps):
     """The neural-field workload on the same scan: Fourier features (128 frequencies) -> 4 x 128 ReLU -> SOS at
     every ray sample, BF16 MFMA.  Times `steps` optimisation steps and each stage (HIP events on the launch
@@ -580,6 +718,7 @@ def nf_leg(P, sd, scan, steps):
     net = P.pact.NfNet(cfg.n_freq, cfg.width, cfg.amp, scan.mask_radius)
     solver = P.NeuralFieldSolver(sd, synth.nf.frequencies(cfg), synth.nf.init_params(cfg), net, lr=scan.lr,
                                  eps=scan.eps, n_samples=scan.n_samples)
+    bf16_error = nf_bf16_error(solver, scan, cfg)
     solver.step()
     torch.cuda.synchronize()
     stages = {"nf_pack": solver.pack, "nf_sos_to_delays": solver.delays, "loss_and_grad": solver.loss_grad,
@@ -622,7 +761,7 @@ def nf_leg(P, sd, scan, steps):
     gpu_pts = pts / ((us["nf_sos_to_delays"] + us["nf_sos_to_delays_adjoint"]) * 1e-6)
     return {"steps_per_s": 1e3 / step_ms, "ms_per_step": step_ms, "steps_timed": steps, "stage_us": us,
             "rooflines": roof, "dtype": "bf16 MFMA, f32 accumulate",
-            "points_per_s_fwd_adj": gpu_pts, "cpu_oracle": nf_oracle_rate(scan, cfg),
+            "points_per_s_fwd_adj": gpu_pts, "cpu_oracle": nf_oracle_rate(scan, cfg), "bf16_error": bf16_error,
             "config": f"Fourier features {cfg.n_freq} (sigma {cfg.sigma} /mm) -> {cfg.depth} x {cfg.width} ReLU -> "
                       f"SOS, {pts} ray samples per step"}
 

@@ -154,12 +154,20 @@ PACT_API int pact_ifft2_real(const float* X, int B, int P, float* x, void* strea
  * of the node grid sos [sosg.ny][sosg.nx] (node centres placed like pixel
  * centres), every node outside the grid being v0 (interpolated pixel grid,
  * Sec. 3.3).  centres [N][2] (x, y) must lie inside that box.  w [N][n_elem].
- * (sosg.ny + 2) * (sosg.nx + 2) * 4 bytes must fit in 160 KiB of LDS. */
+ * (sosg.ny + 2) * (sosg.nx + 2) * 4 bytes must fit in 160 KiB of LDS.
+ * support_radius (mm, >= 0; 0 = none): the user's circular mask of Sec. 3.3,
+ * outside which the SOS is the fixed background.  Nodes whose centre lies
+ * farther than support_radius (1 + 1e-6) from the origin are taken as v0
+ * whatever sos holds there, and only the samples that can touch a node inside
+ * are evaluated (those within the radius grown by a cell diagonal; the others
+ * add exactly zero). */
 PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
-                       const pact_ring* ring, int n_samples, float* w, void* stream);
+                       const pact_ring* ring, int n_samples, float support_radius, float* w, void* stream);
 
 /* Adjoint of pact_sos_to_delays: dL_dsos[a][b] = scale * sum_{i,n} dL_dw[i][n] dw[i][n]/dsos[a][b],
  * with dw/dv = dl v0 / v^2 at every sample spread by the bilinear weights.
+ * With support_radius > 0 the nodes outside the support do not enter w, so
+ * their gradient is exactly zero (as written).
  * scale: optional DEVICE scalar (NULL = 1).  accumulate != 0 adds to dL_dsos.
  * ws: DEVICE workspace of pact_sos_to_delays_adjoint_workspace_size() bytes,
  * which depends on the current device's CU count: one partial node grid per
@@ -172,8 +180,9 @@ PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v
  * result NaN. */
 PACT_API size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg, int N, const pact_ring* ring);
 PACT_API int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
-                               const pact_ring* ring, int n_samples, const float* dL_dw, const float* scale,
-                               float* dL_dsos, int accumulate, void* ws, size_t ws_bytes, void* stream);
+                               const pact_ring* ring, int n_samples, float support_radius, const float* dL_dw,
+                               const float* scale, float* dL_dsos, int accumulate, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* Transfer functions, Eq. TF (Sec. 3.1), under the e^{-j k.r} forward transform:
  *   H[i][j](k) = 1/2 (e^{+j|k|(d_j - W_i(th))} + e^{-j|k|(d_j - W_i(th + pi))}),  th = atan2(k_y, k_x),
@@ -213,18 +222,39 @@ PACT_API int pact_residual_loss(const float* Y, const float* H, const float* X, 
  * gradient with respect to the wavefront table, in one pass over the half
  * spectra Y_half [N][M][P][P/2+1] (the spectra of real patches), without
  * storing any transfer function:
- *   loss  (DEVICE scalar, overwritten) = sum over all P x P bins as in pact_residual_loss
- *         with H from w and X the deconvolution of Y by H,
+ *   loss  (DEVICE scalar, overwritten; may be NULL, which saves a small second
+ *         launch when only the gradient is wanted) = sum over all P x P bins as
+ *         in pact_residual_loss with H from w and X the deconvolution of Y by H,
  *   dL_dw [N][n_elem] (overwritten; may be NULL),
  *   X_opt (may be NULL): the deconvolved full spectra [N][P][P].
- * ws: pact_loss_and_grad_workspace_size() bytes of scratch for per-workgroup
- * partial sums (not shared by two calls in flight).  Partial sums are combined
+ * ws: pact_loss_and_grad_workspace_size() bytes (the N patch losses; not shared
+ * by two calls in flight).  One workgroup per patch; the patch losses are added
  * in a fixed order and the gradient scatter uses exact integer arithmetic, so
- * the result is deterministic.  M <= 16. */
+ * the result is deterministic.  M <= 16, P <= 128. */
 PACT_API size_t pact_loss_and_grad_workspace_size(int N, int M, int P, int n_elem);
 PACT_API int pact_loss_and_grad(const float* Y_half, const float* w, const float* centres, int N, const pact_ring* ring,
                        const float* d, int M, int P, float px, float eps, float* loss, float* dL_dw,
                        float* X_opt, void* ws, size_t ws_bytes, void* stream);
+
+/* The same step from projected spectra.  At a bin k every transfer function of
+ * Eq. TF is a cosine of one shifted argument, |k| (d_j - wbar) = phi + delta_j
+ * with phi = -|k| wbar and delta_j = |k| d_j, so the delay sums of the closed
+ * form need only five step-invariant values per patch and bin,
+ *   Pc = sum_j cos(delta_j) Y_j,  Ps = sum_j sin(delta_j) Y_j  (complex),  S = sum_j |Y_j|^2,
+ * and two per bin, C2 = sum_j cos(2 delta_j), S2 = sum_j sin(2 delta_j).
+ * pact_project_spectra computes them once per scan (in FP64, stored in FP32)
+ * into T, pact_projected_spectra_floats(N, P) floats:
+ *   T[(i*5 + c) * nb + bin], c = Pc.re, Pc.im, Ps.re, Ps.im, S;  T[(N*5 + c) * nb + bin], c = C2, S2,
+ * nb = P (P/2 + 1), bins in the order of Y_half.  pact_loss_and_grad_projected
+ * then reads 20 bytes per patch and bin instead of 8 M, and gives what
+ * pact_loss_and_grad gives on Y_half (same arguments, workspace and limits; M is
+ * the number of delays the spectra were projected with). */
+PACT_API size_t pact_projected_spectra_floats(int N, int P);
+PACT_API int pact_project_spectra(const float* Y_half, int N, int M, int P, float px, const float* d, float* T,
+                                  void* stream);
+PACT_API int pact_loss_and_grad_projected(const float* T, const float* w, const float* centres, int N,
+                                          const pact_ring* ring, int M, int P, float px, float eps, float* loss,
+                                          float* dL_dw, float* X_opt, void* ws, size_t ws_bytes, void* stream);
 
 /* Total-variation term of Eq. jr (reading: anisotropic, over node pairs with at
  * least one free node, subgradient sign(0) = 0):
@@ -247,7 +277,7 @@ PACT_API int pact_adam_step(float* sos, float* m, float* v, int* t, const unsign
                    float lr, float b1, float b2, float eps, void* stream);
 
 /* TV and Adam in one pass (the last two steps of an optimisation step, Eq. jr and Sec. 3.3):
- *   g = grad + lambda dTV/dsos (TV as in pact_tv_grad, at sos_in),  loss += lambda TV(sos_in),
+ *   g = grad + lambda dTV/dsos (TV as in pact_tv_grad, at sos_in),  loss += lambda TV(sos_in) (loss may be NULL),
  *   sos_out = Adam(sos_in, g) on the free nodes (as pact_adam_step), sos_out = sos_in on fixed nodes.
  * grad is read only.  sos_out must be a different buffer from sos_in (every node's TV reads its
  * neighbours' old values); callers alternate two buffers.  m, v [G] and t (DEVICE int[2]) as in
@@ -255,6 +285,20 @@ PACT_API int pact_adam_step(float* sos, float* m, float* v, int* t, const unsign
 PACT_API int pact_tv_adam_step(const float* sos_in, float* sos_out, float* m, float* v, int* t,
                                const unsigned char* mask, const pact_grid* sosg, const float* grad, float lambda,
                                float* loss, float lr, float b1, float b2, float eps, void* stream);
+
+/* The end of an optimisation step in two launches instead of three: the ray adjoint of dL_dw
+ * (pact_sos_to_delays_adjoint, scale 1, same support_radius and workspace), then the sum of its
+ * per-workgroup partials fused with TV and Adam (pact_tv_adam_step on that gradient; loss may be
+ * NULL).  grad (may be NULL) receives the data term's dL/dsos on the free nodes inside the support
+ * (0 on the others, whose partials are not read).  Only for grids that take the whole-grid or banded
+ * adjoint (pact_sos_to_delays_adjoint_workspace_size() > 0); else PACT_EUNSUPPORTED.  The same
+ * results as the three calls, bit for bit, on the free nodes. */
+PACT_API int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out, float* m, float* v, int* t,
+                                           const unsigned char* mask, const pact_grid* sosg, float v0,
+                                           const float* centres, int N, const pact_ring* ring, int n_samples,
+                                           float support_radius, const float* dL_dw, float lambda, float* loss,
+                                           float lr, float b1, float b2, float eps, float* grad, void* ws,
+                                           size_t ws_bytes, void* stream);
 
 /* ---- The paper's neural-field SOS: a sinusoidal network on the SOS-grid nodes (Sec. 3.3) ----
  *
@@ -324,17 +368,16 @@ PACT_API int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, 
                                   size_t act_bytes, void* ws, size_t ws_bytes, void* stream);
 
 /* Autotuned ray tilings (for scans of many shapes, e.g. batched solves): times the lanes per ray of
- * pact_sos_to_delays (1, 2, 4, .. 64) and the segments per ray of pact_sos_to_delays_adjoint (around its
- * built-in rule) on this geometry, with HIP events on `stream`, and keeps the fastest for every later
- * call on this device with the same N, ring element count, n_samples and SOS grid size (the built-in
- * rules apply otherwise).  The choice changes only how each ray's sum is split, so results move in the
- * last bits.  Synchronises the stream; do not call it while a graph is being captured.  w, dL_dsos, ws:
- * DEVICE scratch as for the two calls (overwritten); dL_dw: a DEVICE gradient to time the adjoint with.
- * tiling (HOST, 2 ints, or NULL) receives {forward lanes per ray, adjoint segments per ray} (0: not
- * tuned, the tile form of the adjoint). */
+ * pact_sos_to_delays (1, 2, 4, .. 64) on this geometry, with HIP events on `stream`, and keeps the
+ * fastest for every later call on this device with the same N, ring element count, n_samples, SOS grid
+ * size and support radius (the built-in rule applies otherwise).  The choice changes only how each ray's
+ * sum is split, so results move in the last bits.  Synchronises the stream; do not call it while a graph
+ * is being captured.  w: DEVICE scratch [N][n_elem] (overwritten).  dL_dw, dL_dsos and ws are not used
+ * (the adjoint's work items have a fixed length and need no tuning) and may be NULL.  tiling (HOST, 2
+ * ints, or NULL) receives {forward lanes per ray, 0}. */
 PACT_API int pact_rays_autotune(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
-                                const pact_ring* ring, int n_samples, const float* dL_dw, float* w, float* dL_dsos,
-                                void* ws, size_t ws_bytes, int* tiling, void* stream);
+                                const pact_ring* ring, int n_samples, float support_radius, const float* dL_dw,
+                                float* w, float* dL_dsos, void* ws, size_t ws_bytes, int* tiling, void* stream);
 
 /* ---- Learned warm start: convolutional SOS initialiser ----
  *

@@ -58,7 +58,7 @@ extern "C" {
 
 const char* pact_last_error(void) { return pact::g_err; }
 
-int pact_version(void) { return 1; }
+int pact_version(void) { return 2; }
 
 int pact_patch_count(const pact_grid* img_, const pact_patches* pp_, int* npy, int* npx) {
     pact::clear_error();

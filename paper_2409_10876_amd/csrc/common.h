@@ -129,4 +129,112 @@ __device__ __forceinline__ float ordered_strided_sum(const float* __restrict__ p
     return s;
 }
 
+// ---- Short polynomials (coefficients fitted by gen_poly.py beside the sources) ----
+
+// sin2pi: max abs error 1.21e-09 (float64)
+constexpr float k_sin2pi[4] = {6.283185005187988f, -41.34162902832031f, 81.58812713623047f, -75.24005889892578f};
+// cos2pi: max abs error 4.74e-11 (float64)
+constexpr float k_cos2pi[5] = {1.0f, -19.739208221435547f, 64.93931579589844f, -85.4428482055664f, 59.220401763916016f};
+
+// Block maximum (deterministic; every thread gets it); `red` must hold blockDim.x / 64 floats.
+__device__ __forceinline__ float block_max(float v, float* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float t = red[0];
+    for (int k = 1; k < static_cast<int>(blockDim.x >> 6); ++k) t = fmaxf(t, red[k]);
+    __syncthreads();
+    return t;
+}
+
+template <int K>
+__device__ __forceinline__ float horner(const float (&c)[K], float z) {
+    float p = c[K - 1];
+#pragma unroll
+    for (int k = K - 2; k >= 0; --k) p = fmaf(p, z, c[k]);
+    return p;
+}
+
+// sin and cos of 2 pi r (r in revolutions): remove whole quarter turns, then the polynomials on |f| <= 1/8.
+__device__ __forceinline__ void sincos_rev(float r, float& s, float& c) {
+    const float q = rintf(4.0f * r);
+    const float f = fmaf(q, -0.25f, r);
+    const float z = f * f;
+    const float sf = f * horner(k_sin2pi, z);
+    const float cf = horner(k_cos2pi, z);
+    const int iq = static_cast<int>(q);
+    const bool swap = (iq & 1) != 0;
+    const float ss = swap ? cf : sf, cc = swap ? sf : cf;
+    s = __int_as_float(__float_as_int(ss) ^ ((iq & 2) << 30));
+    c = __int_as_float(__float_as_int(cc) ^ (((iq + 1) & 2) << 30));
+}
+
+// q = n / d for 0 <= n < 2^24 and d >= 1, given inv_d = 1 / d (rounded): the float quotient is off by at most two,
+// which the two corrections remove.
+__device__ __forceinline__ int div_small(int n, int d, float inv_d) {
+    int q = static_cast<int>(static_cast<float>(n) * inv_d);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int r = n - q * d;
+        q = r < 0 ? q - 1 : (r >= d ? q + 1 : q);
+    }
+    return q;
+}
+
+// ---- TV subgradient and Adam (Eq. jr, Sec. 3.3), shared by the optimiser kernels ----
+
+__device__ __forceinline__ float sgn(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
+
+// TV pairs of node (a, b): its value share (the pairs it starts) and its subgradient (all four pairs).  The
+// neighbours' values and masks are loaded unconditionally (the node itself stands in at the grid edge), so
+// that all the loads are in flight together; the pairs that exist are then taken as written.
+__device__ __forceinline__ void tv_node(const float* __restrict__ v, const unsigned char* __restrict__ mask, int idx,
+                                        int a, int b, int Gy, int Gx, float& tv, float& g) {
+    const bool has_d = a + 1 < Gy, has_r = b + 1 < Gx, has_u = a > 0, has_l = b > 0;
+    const int id = has_d ? idx + Gx : idx, ir = has_r ? idx + 1 : idx;
+    const int iu = has_u ? idx - Gx : idx, il = has_l ? idx - 1 : idx;
+    const float x = v[idx], vd = v[id], vr = v[ir], vu = v[iu], vl = v[il];
+    const bool m = mask[idx] != 0, md = mask[id] != 0, mr = mask[ir] != 0, mu = mask[iu] != 0, ml = mask[il] != 0;
+    tv = 0.0f;
+    g = 0.0f;
+    // pair (a, b)-(a+1, b) and (a, b)-(a, b+1): counted once, by their first node
+    if (has_d && (m || md)) {
+        const float dv = vd - x;
+        tv += fabsf(dv);
+        g -= sgn(dv);
+    }
+    if (has_r && (m || mr)) {
+        const float dv = vr - x;
+        tv += fabsf(dv);
+        g -= sgn(dv);
+    }
+    // the same pairs seen from their second node
+    if (has_u && (m || mu)) g += sgn(x - vu);
+    if (has_l && (m || ml)) g += sgn(x - vl);
+}
+
+// One Adam update of p with gradient g at step `step` (PyTorch's rule); returns the new parameter.
+__device__ __forceinline__ float adam_node(float p, float g, float& m, float& v, int step, float lr, float b1,
+                                           float b2, float eps) {
+    const float bc1 = 1.0f - powf(b1, static_cast<float>(step));
+    const float bc2 = 1.0f - powf(b2, static_cast<float>(step));
+    m = fmaf(b1, m, (1.0f - b1) * g);
+    v = fmaf(b2, v, (1.0f - b2) * g * g);
+    return p - (lr / bc1) * m / fmaf(sqrtf(v), 1.0f / sqrtf(bc2), eps);
+}
+
+// Every workgroup has read t[0] (above its barrier); the last workgroup to arrive advances it.
+__device__ __forceinline__ void advance_step(int* t, int step) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(reinterpret_cast<unsigned*>(t + 1), 1u);
+        if (prev == gridDim.x - 1) {
+            t[0] = step;
+            t[1] = 0;
+        }
+    }
+}
+
 }  // namespace pact

@@ -13,36 +13,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ float sgn(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
-
-// TV pairs of node (a, b): its value share (the pairs it starts) and its subgradient (all four pairs).  The
-// neighbours' values and masks are loaded unconditionally (the node itself stands in at the grid edge), so
-// that all the loads are in flight together; the pairs that exist are then taken as written.
-__device__ __forceinline__ void tv_node(const float* __restrict__ v, const unsigned char* __restrict__ mask, int idx,
-                                        int a, int b, int Gy, int Gx, float& tv, float& g) {
-    const bool has_d = a + 1 < Gy, has_r = b + 1 < Gx, has_u = a > 0, has_l = b > 0;
-    const int id = has_d ? idx + Gx : idx, ir = has_r ? idx + 1 : idx;
-    const int iu = has_u ? idx - Gx : idx, il = has_l ? idx - 1 : idx;
-    const float x = v[idx], vd = v[id], vr = v[ir], vu = v[iu], vl = v[il];
-    const bool m = mask[idx] != 0, md = mask[id] != 0, mr = mask[ir] != 0, mu = mask[iu] != 0, ml = mask[il] != 0;
-    tv = 0.0f;
-    g = 0.0f;
-    // pair (a, b)-(a+1, b) and (a, b)-(a, b+1): counted once, by their first node
-    if (has_d && (m || md)) {
-        const float dv = vd - x;
-        tv += fabsf(dv);
-        g -= sgn(dv);
-    }
-    if (has_r && (m || mr)) {
-        const float dv = vr - x;
-        tv += fabsf(dv);
-        g -= sgn(dv);
-    }
-    // the same pairs seen from their second node
-    if (has_u && (m || mu)) g += sgn(x - vu);
-    if (has_l && (m || ml)) g += sgn(x - vl);
-}
-
 __global__ __launch_bounds__(kThreads) void tv_kernel(const float* __restrict__ v,
                                                       const unsigned char* __restrict__ mask, int Gy, int Gx,
                                                       float lambda, float* __restrict__ grad,
@@ -58,28 +28,6 @@ __global__ __launch_bounds__(kThreads) void tv_kernel(const float* __restrict__ 
     }
     tv = block_sum(tv, red);
     if (threadIdx.x == 0 && tv != 0.0f) atomicAdd(loss, lambda * tv);
-}
-
-// One Adam update of p with gradient g at step `step` (PyTorch's rule); returns the new parameter.
-__device__ __forceinline__ float adam_node(float p, float g, float& m, float& v, int step, float lr, float b1,
-                                           float b2, float eps) {
-    const float bc1 = 1.0f - powf(b1, static_cast<float>(step));
-    const float bc2 = 1.0f - powf(b2, static_cast<float>(step));
-    m = fmaf(b1, m, (1.0f - b1) * g);
-    v = fmaf(b2, v, (1.0f - b2) * g * g);
-    return p - (lr / bc1) * m / fmaf(sqrtf(v), 1.0f / sqrtf(bc2), eps);
-}
-
-// Every workgroup has read t[0] (above its barrier); the last workgroup to arrive advances it.
-__device__ __forceinline__ void advance_step(int* t, int step) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(reinterpret_cast<unsigned*>(t + 1), 1u);
-        if (prev == gridDim.x - 1) {
-            t[0] = step;
-            t[1] = 0;
-        }
-    }
 }
 
 // TV subgradient added to the data gradient, then Adam, reading sos_in and writing sos_out (so that every
@@ -110,8 +58,10 @@ __global__ __launch_bounds__(kThreads) void tv_adam_kernel(const float* __restri
         }
         sos_out[idx] = p;
     }
-    tv = block_sum(tv, red);
-    if (threadIdx.x == 0 && tv != 0.0f) atomicAdd(loss, lambda * tv);
+    if (loss) {
+        tv = block_sum(tv, red);
+        if (threadIdx.x == 0 && tv != 0.0f) atomicAdd(loss, lambda * tv);
+    }
     advance_step(t, step);
 }
 
@@ -174,7 +124,7 @@ extern "C" int pact_tv_adam_step(const float* sos_in, float* sos_out, float* m, 
     const pact_grid sosg = *sosg_;
     using namespace pact;
     clear_error();
-    PACT_CHECK_ARG(sos_in && sos_out && m && v && t && mask && grad && loss, "pact_tv_adam_step: null pointer");
+    PACT_CHECK_ARG(sos_in && sos_out && m && v && t && mask && grad, "pact_tv_adam_step: null pointer");
     PACT_CHECK_ARG(sos_in != sos_out, "pact_tv_adam_step: sos_out must not be sos_in");
     if (int s = check_grid(sosg, "pact_tv_adam_step")) return s;
     PACT_CHECK_ARG(std::isfinite(lambda), "pact_tv_adam_step: lambda must be finite");

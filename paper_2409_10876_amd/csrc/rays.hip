@@ -38,6 +38,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -63,33 +64,34 @@ struct RayGeo {
     float hx, hy;       // half-extent of the box where v differs from v0
     float inv_ns;       // 1 / n_samples
     int Gx, Gy, W;      // W = Gx + 2 (padded row length)
+    // support disc (0: none): nodes whose centre lies farther than sqrt(rho2) (mm) from the origin are taken
+    // as v0 and get no gradient; samples farther than sqrt(rc2) touch no node of the disc
+    float rho2, rc2;
+    float ds;           // node spacing (mm)
 };
 
-// Element positions, computed by the same code in every kernel that traces rays.
+// Node (padded row r, padded column c) lies in the support disc.  y2 is the squared y coordinate of row r.
+__device__ __forceinline__ bool node_in_support(int c, float y2, const RayGeo& g) {
+    const float x = (static_cast<float>(c) - g.off_x) * g.ds;
+    return !(g.rho2 > 0.0f) || fmaf(x, x, y2) <= g.rho2;
+}
+
+__device__ __forceinline__ float row_y2(int r, const RayGeo& g) {
+    const float y = (static_cast<float>(r) - g.off_y) * g.ds;
+    return y * y;
+}
+
+// Element positions, computed by the same code in every kernel that traces rays: the angle in revolutions,
+// n / n_elem + phi0 / (2 pi), through the short sin / cos polynomials.
 __device__ __forceinline__ void element_position(int n, int n_elem, float R, float phi0, float& ex, float& ey) {
     float sn, cs;
-    sincosf(phi0 + kTwoPi * (static_cast<float>(n) / n_elem), &sn, &cs);
+    sincos_rev(fmaf(phi0, 0.159154943091895335769f, static_cast<float>(n) / static_cast<float>(n_elem)), sn, cs);
     ex = R * cs;
     ey = R * sn;
 }
 
 __device__ __forceinline__ void load_elements(float* ex, float* ey, int n_elem, float R, float phi0) {
     for (int n = threadIdx.x; n < n_elem; n += blockDim.x) element_position(n, n_elem, R, phi0, ex[n], ey[n]);
-}
-
-// Block maximum (deterministic); `red` must hold blockDim.x / 64 floats.  Result valid in every thread.
-__device__ __forceinline__ float block_max(float v, float* red) {
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    __syncthreads();
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    float t = red[0];
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int i = 1; i < nw; ++i) t = fmaxf(t, red[i]);
-    return t;
 }
 
 // Stage the contrast sos - v0 of padded rows R0 .. R0 + H - 1 of the Gy x Gx node grid with a one-node ring
@@ -140,11 +142,13 @@ __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, fl
                 const int r = r0 + k * nw, a = R0 + r - 1;
                 if (r < H) {
                     const bool row_in = a >= 0 && a < g.Gy;
+                    const float y2 = row_y2(R0 + r, g);
 #pragma unroll
                     for (int q = 0; q < kStageChunks; ++q) {
                         const int c = cb + 64 * q + lane;
                         if (c < W) {
-                            const float d = (row_in && cin[q]) ? x[k][q] - v0 : 0.0f;
+                            const bool in = row_in && cin[q] && node_in_support(c, y2, g);
+                            const float d = in ? x[k][q] - v0 : 0.0f;
                             vs[r * W + c] = d;
                             if (acc) acc[r * W + c] = 0;
                             vmin = fminf(vmin, v0 + d);
@@ -158,9 +162,13 @@ __device__ __forceinline__ void stage_contrast(const float* __restrict__ sos, fl
 }
 
 // Geometry of ray (centre c, element e): padded node coordinates of the start point and their
-// increment per sample step, and the step length dl = L / n_samples.
-__device__ __forceinline__ void ray_setup(float cx, float cy, float ex, float ey, const RayGeo& g, float& gx0,
-                                          float& gy0, float& dgx, float& dgy, float& dl) {
+// increment per sample step, and the step length dl = L / n_samples.  With a support disc, [sa, sb) are the
+// samples that can touch one of its nodes: those within sqrt(rc2) of the origin, found from the ray's chord
+// through that disc with one sample of margin at each end (empty if the ray misses it); else all samples.
+// The samples outside add exactly zero to the forward sum (every node of their cell is v0) and their adjoint
+// shares would land on nodes outside the support only.
+__device__ __forceinline__ void ray_setup(float cx, float cy, float ex, float ey, const RayGeo& g, int Ns, float& gx0,
+                                          float& gy0, float& dgx, float& dgy, float& dl, int& sa, int& sb) {
     const float dx = ex - cx, dy = ey - cy;
     const float d2 = fmaf(dx, dx, dy * dy);
     const float inv = rsqrtf(d2);
@@ -174,6 +182,27 @@ __device__ __forceinline__ void ray_setup(float cx, float cy, float ex, float ey
     gy0 = fmaf(cy, g.inv_ds, g.off_y);
     dgx = dl * ux * g.inv_ds;
     dgy = dl * uy * g.inv_ds;
+    sa = 0;
+    sb = Ns;
+    if (g.rc2 > 0.0f) {
+        const float b = fmaf(cx, ux, cy * uy);
+        const float disc = fmaf(b, b, g.rc2 - fmaf(cx, cx, cy * cy));
+        if (disc > 0.0f && dl > 0.0f) {
+            // sample s sits at (s + 1/2) dl from the centre: inside for ta <= s <= tb (the one-sample margins
+            // cover the rounding of the hardware square root and reciprocal)
+            const float root = __builtin_amdgcn_sqrtf(disc);
+            const float idl = __builtin_amdgcn_rcpf(dl);
+            const float ta = fmaf(-b - root, idl, -0.5f), tb = fmaf(-b + root, idl, -0.5f);
+            const float nsf = static_cast<float>(Ns);
+            sa = static_cast<int>(floorf(fminf(fmaxf(ta, -2.0f), nsf + 2.0f)));
+            sb = static_cast<int>(floorf(fminf(fmaxf(tb, -2.0f), nsf + 2.0f))) + 2;
+            sa = max(sa, 0);
+            sb = min(sb, Ns);
+            if (sb < sa) sb = sa;
+        } else {
+            sb = 0;
+        }
+    }
 }
 
 // Cell of sample sf of a ray: flat padded index c of its lower-left node and the fractions (fx, fy) inside
@@ -225,56 +254,115 @@ __device__ __forceinline__ float contrast_sample(const float* vs, float sf, floa
     return fmaf(fy, bot - top, top);
 }
 
-// Sum of the integrand delta / (v0 + delta) over samples s0 .. s1 - 1, two at a time (two gathers in flight).
+// Sum of the integrand delta / (v0 + delta) over the samples first, first + stride, ... below end, two at a time
+// (two gathers in flight).
 template <bool kClamp>
-__device__ __forceinline__ float fwd_segment(const float* vs, int s0, int s1, float v0, float gx0, float gy0,
-                                             float dgx, float dgy, const RayGeo& g) {
+__device__ __forceinline__ float fwd_samples(const float* vs, int first, int stride, int end, float v0, float gx0,
+                                             float gy0, float dgx, float dgy, const RayGeo& g) {
     float acc0 = 0.0f, acc1 = 0.0f;
     // the loop runs on the sample's float coordinate alone (exact: sample counts are far below 2^24)
-    float sf = static_cast<float>(s0) + 0.5f;
-    const float sf_pair_end = static_cast<float>(s1) - 0.5f;     // a pair starting at sf fits while sf < this
-    for (; sf < sf_pair_end; sf += 2.0f) {
+    const float st = static_cast<float>(stride);
+    float sf = static_cast<float>(first) + 0.5f;
+    const float sf_end = static_cast<float>(end);
+    for (; sf + st < sf_end; sf += 2.0f * st) {
         const float d0 = contrast_sample<kClamp>(vs, sf, gx0, gy0, dgx, dgy, g);
-        const float d1 = contrast_sample<kClamp>(vs, sf + 1.0f, gx0, gy0, dgx, dgy, g);
+        const float d1 = contrast_sample<kClamp>(vs, sf + st, gx0, gy0, dgx, dgy, g);
         acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
         acc1 = fmaf(d1, __builtin_amdgcn_rcpf(v0 + d1), acc1);
     }
-    if (sf < static_cast<float>(s1)) {
+    if (sf < sf_end) {
         const float d0 = contrast_sample<kClamp>(vs, sf, gx0, gy0, dgx, dgy, g);
         acc0 = fmaf(d0, __builtin_amdgcn_rcpf(v0 + d0), acc0);
     }
     return acc0 + acc1;
 }
 
+// Ray-length classes used to order a workgroup's rays (counting sort by the number of samples inside the support).
+constexpr int kLenBuckets = 33;
+
+// Workgroup b takes rays b * per_block .. (element-major: ray = n * N + i, so every workgroup holds the rays of
+// about one element from every patch, and all workgroups carry about the same work).  Its rays are ordered by
+// their sample counts inside the support (longest first, when the order fits in LDS) and each goes to K adjacent
+// lanes (K a power of two) that take its samples in turn: the lanes of a wave then walk rays of similar length,
+// and the lanes of a ray read neighbouring cells.
 __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restrict__ sos, float v0,
                                                             const float* __restrict__ centres, int N, int n_elem,
-                                                            float R, float phi0, int Ns, RayGeo g, int K,
-                                                            int n_items, float* __restrict__ w) {
+                                                            float R, float phi0, int Ns, RayGeo g, int log2K,
+                                                            int n_rays, int per_block, int sorted,
+                                                            float* __restrict__ w) {
     extern __shared__ float vs[];
+    const int K = 1 << log2K;
+    const int total = (g.Gy + 2) * g.W;
+    int* hist = reinterpret_cast<int*>(vs + total);        // [kLenBuckets]
+    int* order = hist + kLenBuckets;                       // [n_loc] when sorted
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kLenBuckets; k += blockDim.x) hist[k] = 0;
     {
         float vmin = v0, nan_check = 0.0f;   // not used by the forward
         stage_contrast<kStageRows>(sos, v0, g, vs, nullptr, 0, g.Gy + 2, vmin, nan_check);
     }
-    __syncthreads();
-    // K divides the workgroup size and n_items = rays * K, so the K lanes of a ray enter and leave the
-    // loop together
-    for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < n_items; item += gridDim.x * blockDim.x) {
-        const int ray = item / K, k = item - ray * K;
-        const int i = ray / n_elem, n = ray - i * n_elem;
+    const int r0 = blockIdx.x * per_block;
+    const int n_loc = max(min(per_block, n_rays - r0), 0);
+    const float inv_N = 1.0f / static_cast<float>(N);
+    auto setup = [&](int ray, int& i, int& n, float& gx0, float& gy0, float& dgx, float& dgy, float& dl, int& sa,
+                     int& sb) {
+        n = div_small(ray, N, inv_N);
+        i = ray - n * N;
         float ex, ey;
         element_position(n, n_elem, R, phi0, ex, ey);
-        float gx0, gy0, dgx, dgy, dl;
-        ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
-        const int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
-        float acc = 0.0f;
-        if (s1 > s0) {
-            // the clamp-free loop where the whole segment is inside the grid (the same bits)
-            acc = segment_inside(s0, s1, gx0, gy0, dgx, dgy, g)
-                      ? fwd_segment<false>(vs, s0, s1, v0, gx0, gy0, dgx, dgy, g)
-                      : fwd_segment<true>(vs, s0, s1, v0, gx0, gy0, dgx, dgy, g);
+        ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, Ns, gx0, gy0, dgx, dgy, dl, sa, sb);
+    };
+    auto bucket_of = [&](int cnt) { return min(cnt * kLenBuckets / (Ns + 1), kLenBuckets - 1); };
+    if (sorted) {
+        __syncthreads();
+        for (int lr = tid; lr < n_loc; lr += blockDim.x) {
+            int i, n, sa, sb;
+            float gx0, gy0, dgx, dgy, dl;
+            setup(r0 + lr, i, n, gx0, gy0, dgx, dgy, dl, sa, sb);
+            atomicAdd(&hist[bucket_of(max(sb - sa, 0))], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int run = 0;
+            for (int k = kLenBuckets - 1; k >= 0; --k) {
+                const int c = hist[k];
+                hist[k] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        for (int lr = tid; lr < n_loc; lr += blockDim.x) {
+            int i, n, sa, sb;
+            float gx0, gy0, dgx, dgy, dl;
+            setup(r0 + lr, i, n, gx0, gy0, dgx, dgy, dl, sa, sb);
+            order[atomicAdd(&hist[bucket_of(max(sb - sa, 0))], 1)] = r0 + lr;
+        }
+    }
+    __syncthreads();
+    // the K lanes of a ray are adjacent and aligned, so they enter and leave the loop together and add their
+    // sums with K-wide shuffles
+    const int n_items = n_loc * K;
+    for (int base = 0; base < n_items; base += blockDim.x) {
+        const int it = base + tid;
+        const int lr = it >> log2K, k = it & (K - 1);
+        float acc = 0.0f, dl = 0.0f;
+        int i = 0, n = 0;
+        if (it < n_items) {
+            const int ray = sorted ? order[lr] : r0 + lr;
+            int sa, sb;
+            float gx0, gy0, dgx, dgy;
+            setup(ray, i, n, gx0, gy0, dgx, dgy, dl, sa, sb);
+            // lane k of the ray takes samples sa + k, sa + k + K, ...: the K lanes of a ray read neighbouring
+            // cells at the same time (shared LDS words are broadcast)
+            if (sa + k < sb) {
+                // the clamp-free loop where the whole ray is inside the grid (the same bits)
+                acc = segment_inside(sa, sb, gx0, gy0, dgx, dgy, g)
+                          ? fwd_samples<false>(vs, sa + k, K, sb, v0, gx0, gy0, dgx, dgy, g)
+                          : fwd_samples<true>(vs, sa + k, K, sb, v0, gx0, gy0, dgx, dgy, g);
+            }
         }
         for (int off = K >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, K);
-        if (k == 0) w[ray] = acc * dl;
+        if (it < n_items && k == 0) w[static_cast<size_t>(i) * n_elem + n] = acc * dl;
     }
 }
 
@@ -366,7 +454,8 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
     // local node (la, lb) is grid node (a_lo - 1 + la, b_lo - 1 + lb); interior nodes have la, lb in 1..kTile
     for (int idx = tid; idx < NN; idx += blockDim.x) {
         const int a = a_lo - 1 + idx / L, b = b_lo - 1 + idx % L;
-        dv[idx] = (a >= 0 && a < g.Gy && b >= 0 && b < g.Gx) ? sos[a * g.Gx + b] - v0 : 0.0f;
+        const bool in = a >= 0 && a < g.Gy && b >= 0 && b < g.Gx && node_in_support(b + 1, row_y2(a + 1, g), g);
+        dv[idx] = in ? sos[a * g.Gx + b] - v0 : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < NN; ++j) acc[j * kAdjThreads + tid] = 0.0f;
@@ -435,9 +524,12 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
         const int i = lo;
         const int n = (first[i] + (k - offs[i])) % n_elem;
         float gx0, gy0, dgx, dgy, dl;
-        ray_setup(centres[2 * i], centres[2 * i + 1], ex[n], ey[n], g, gx0, gy0, dgx, dgy, dl);
+        int sa, sb;
+        ray_setup(centres[2 * i], centres[2 * i + 1], ex[n], ey[n], g, Ns, gx0, gy0, dgx, dgy, dl, sa, sb);
         int s0, s1;
         clip_samples(gx0, gy0, dgx, dgy, a_lo, a_hi, b_lo, b_hi, Ns, s0, s1);
+        s0 = max(s0, sa);
+        s1 = min(s1, sb - 1);
         const float q0 = dL_dw[static_cast<size_t>(i) * n_elem + n] * dl * sc;
         // every sample is tested: margin samples, and samples of rays grazing an edge of the region, can
         // fall outside it; they add zero to node 0
@@ -481,6 +573,7 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
         for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 16);
         if (part == 0 && la < th && lb < tw) {
             const size_t o = static_cast<size_t>(a_lo + la) * g.Gx + (b_lo + lb);
+            if (!node_in_support(b_lo + lb + 1, row_y2(a_lo + la + 1, g), g)) sum = 0.0f;
             out[o] = accumulate ? out[o] + sum : sum;
         }
     }
@@ -588,8 +681,8 @@ __device__ __forceinline__ void band_samples(int s0, int s1, float gy0, float dg
 template <bool kBanded>
 __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     const float* __restrict__ sos, float v0, const float* __restrict__ centres, int N, int n_elem, float R, float phi0,
-    int Ns, RayGeo g, int K, int n_items, int per_block, int n_bands, int band_rows, const float* __restrict__ dL_dw,
-    const float* __restrict__ scale, float* __restrict__ partial) {
+    int Ns, RayGeo g, int n_rays, int per_block, int K, int sorted, int n_bands, int band_rows,
+    const float* __restrict__ dL_dw, const float* __restrict__ scale, float* __restrict__ partial) {
     extern __shared__ float lds[];
     const int W = g.W;
     const int band = kBanded ? static_cast<int>(blockIdx.x) % n_bands : 0;
@@ -604,38 +697,78 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     float vmin = v0, nan_check = 0.0f;                     // nan_check turns NaN if any node is not finite
     stage_contrast<kStageRows>(sos, v0, g, vs, acc, R0, R1 - R0 + 1, vmin, nan_check);
     vmin = -block_max(-vmin, red);
-    const int it0 = bblock * per_block;
-    const int it1 = min(it0 + per_block, n_items);
+    const int r0 = bblock * per_block;                      // this workgroup's rays r0 .. r1 - 1 (element-major)
+    const int r1 = min(r0 + per_block, n_rays);
+    const int n_loc = max(r1 - r0, 0);
+    const float inv_N = 1.0f / static_cast<float>(N), inv_K = 1.0f / static_cast<float>(K);
     const float sc = (scale ? *scale : 1.0f) * v0;
     const float ds = 1.0f / g.inv_ds;
-    // bound on any node's sum over this workgroup's rays
+    // LDS after the grid arrays: the bucket counters and, if they fit, this workgroup's rays in order of length
+    int* hist = reinterpret_cast<int*>(red + kGridThreads / 64);     // [kLenBuckets]
+    int* order = hist + kLenBuckets;                                   // [n_loc] when sorted
+    for (int k = tid; k < kLenBuckets; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    // bound on any node's sum over this workgroup's rays, and a histogram of the rays' sample counts inside the
+    // support (and band)
+    auto ray_count = [&](int ray, float& contrib) {
+        const int n = div_small(ray, N, inv_N), i = ray - n * N;
+        float ex, ey;
+        element_position(n, n_elem, R, phi0, ex, ey);
+        float gx0, gy0, dgx, dgy, dl;
+        int sa, sb;
+        ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, Ns, gx0, gy0, dgx, dgy, dl, sa, sb);
+        contrib = fabsf(dL_dw[static_cast<size_t>(i) * n_elem + n] * sc) * (2.8285f * ds + dl);
+        if (kBanded) band_samples(sa, sb, gy0, dgy, R0, R1, sa, sb);
+        return max(sb - sa, 0);
+    };
+    auto bucket_of = [&](int cnt) { return min(cnt * kLenBuckets / (Ns + 1), kLenBuckets - 1); };
     float bnd = 0.0f;
-    if (it1 > it0) {
-        for (int ray = it0 / K + tid; ray <= (it1 - 1) / K; ray += blockDim.x) {
-            const int n = ray / N, i = ray - n * N;
-            float ex, ey;
-            element_position(n, n_elem, R, phi0, ex, ey);
-            float gx0, gy0, dgx, dgy, dl;
-            ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
-            bnd += fabsf(dL_dw[static_cast<size_t>(i) * n_elem + n] * sc) * (2.8285f * ds + dl);
-        }
+    for (int lr = tid; lr < n_loc; lr += blockDim.x) {
+        float c;
+        const int cnt = ray_count(r0 + lr, c);
+        bnd += c;
+        if (sorted) atomicAdd(&hist[bucket_of(cnt)], 1);
     }
     bnd = block_sum(bnd + nan_check, red) / (vmin * vmin);
     const bool ok = vmin > 0.0f && bnd <= 3.0e38f;        // false for NaN or infinite bounds too
     const float F = (ok && bnd > 0.0f) ? ldexpf(1.0f, min(30 - (ilogbf(bnd) + 1), 126)) : 1.0f;
+    if (sorted) {
+        // longest first: bucket b starts after every longer bucket (exclusive prefix from the top)
+        if (tid == 0) {
+            int run = 0;
+            for (int k = kLenBuckets - 1; k >= 0; --k) {
+                const int c = hist[k];
+                hist[k] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        for (int lr = tid; lr < n_loc; lr += blockDim.x) {
+            float c;
+            const int cnt = ray_count(r0 + lr, c);
+            order[atomicAdd(&hist[bucket_of(cnt)], 1)] = r0 + lr;
+        }
+    }
     __syncthreads();
 
+    // Work items: K segments of each ray's samples inside the support (and band), dealt to the lanes in the order
+    // of the rays' lengths (with the order not stored, in element-major order), so that the lanes of a wave walk
+    // segments of similar length; neighbouring lanes still walk parallel rays from different patch centres, which
+    // rarely meet at one node.  The order within a bucket varies between runs; the integer sums do not depend on it.
     const int cbase = R0 * W, band_cells = (R1 - R0) * W;
-    for (int item = it0 + tid; item < it1; item += blockDim.x) {
-        const int ray = item / K, k = item - ray * K;
-        const int n = ray / N, i = ray - n * N;
+    for (int it = tid; it < n_loc * K; it += blockDim.x) {
+        const int lr = div_small(it, K, inv_K), k = it - lr * K;
+        const int ray = sorted ? order[lr] : r0 + lr;
+        const int n = div_small(ray, N, inv_N), i = ray - n * N;
         float ex, ey;
         element_position(n, n_elem, R, phi0, ex, ey);
         float gx0, gy0, dgx, dgy, dl;
-        ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, gx0, gy0, dgx, dgy, dl);
+        int sa, sb;
+        ray_setup(centres[2 * i], centres[2 * i + 1], ex, ey, g, Ns, gx0, gy0, dgx, dgy, dl, sa, sb);
         const float q0 = ok ? dL_dw[static_cast<size_t>(i) * n_elem + n] * dl * sc * F : 0.0f;
-        int s0 = (k * Ns) / K, s1 = ((k + 1) * Ns) / K;
-        if (kBanded) band_samples(s0, s1, gy0, dgy, R0, R1, s0, s1);
+        if (kBanded) band_samples(sa, sb, gy0, dgy, R0, R1, sa, sb);
+        const int cnt = max(sb - sa, 0);
+        const int s0 = sa + div_small(k * cnt, K, inv_K), s1 = sa + div_small((k + 1) * cnt, K, inv_K);
         if (s1 > s0) {
             // the clamp-free loop where the whole segment is inside the grid (the same bits)
             if (segment_inside(s0, s1, gx0, gy0, dgx, dgy, g))
@@ -655,8 +788,13 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
         const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
         for (int a = wave; a < g.Gy; a += kGridThreads / 64) {
             const bool mine = !kBanded || (a + 1 >= R0 && a + 1 <= R1);
-            for (int b = lane; b < g.Gx; b += 64)
-                part[a * g.Gx + b] = !ok ? bad : (mine ? static_cast<float>(acc[(a + 1 - R0) * W + b + 1]) * invF : 0.0f);
+            const float y2 = row_y2(a + 1, g);
+            for (int b = lane; b < g.Gx; b += 64) {
+                // nodes outside the support are not written: the readers of the partials take them as zero
+                if (!node_in_support(b + 1, y2, g)) continue;
+                part[a * g.Gx + b] =
+                    !ok ? bad : (mine ? static_cast<float>(acc[(a + 1 - R0) * W + b + 1]) * invF : 0.0f);
+            }
         }
     }
 }
@@ -679,12 +817,20 @@ __device__ __forceinline__ float adj_run_sum(const float* __restrict__ partial, 
 
 constexpr int kReduceNodes = 64;
 
+// Node `node` of the Gy x Gx grid lies in the support disc.
+__device__ __forceinline__ bool grid_node_in_support(int node, const RayGeo& g) {
+    const int a = node / g.Gx;
+    return node_in_support(node - a * g.Gx + 1, row_y2(a + 1, g), g);
+}
+
 __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_kernel(
-    const float* __restrict__ partial, int n_part, int n_nodes, int accumulate, float* __restrict__ out) {
+    const float* __restrict__ partial, int n_part, RayGeo g, int accumulate, float* __restrict__ out) {
     __shared__ float run[kAdjSlices][kReduceNodes];
+    const int n_nodes = g.Gy * g.Gx;
     const int j = threadIdx.x % kReduceNodes, slice = threadIdx.x / kReduceNodes;
     const int node = blockIdx.x * kReduceNodes + j;
-    run[slice][j] = node < n_nodes ? adj_run_sum(partial, n_part, n_nodes, node, slice) : 0.0f;
+    run[slice][j] = node < n_nodes && grid_node_in_support(node, g)
+                        ? adj_run_sum(partial, n_part, n_nodes, node, slice) : 0.0f;
     __syncthreads();
     if (slice == 0 && node < n_nodes) {
         float t = 0.0f;
@@ -694,8 +840,67 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_ker
     }
 }
 
-RayGeo make_geo(const pact_grid& sosg, int n_samples) {
+// The end of an optimisation step in one launch: the partial grids of the ray adjoint summed in the fixed order
+// of rays_adj_reduce_kernel (the data gradient), plus the TV subgradient at sos_in, then Adam from sos_in into
+// sos_out, as tv_adam_kernel does.  Only the free nodes inside the support read their partials (fixed nodes keep
+// their value, and the partials of nodes outside the support are not written).  The TV value is added to the
+// loss with one float atomic per workgroup (loss may be null); the last workgroup to arrive advances the step.
+__global__ __launch_bounds__(kAdjSlices * kReduceNodes) void adj_reduce_tv_adam_kernel(
+    const float* __restrict__ partial, int n_part, RayGeo g, const float* __restrict__ sos_in,
+    float* __restrict__ sos_out, float* __restrict__ m, float* __restrict__ v, int* __restrict__ t,
+    const unsigned char* __restrict__ mask, float lambda, float* __restrict__ loss, float lr, float b1, float b2,
+    float eps, float* __restrict__ grad_out) {
+    __shared__ float run[kAdjSlices][kReduceNodes];
+    __shared__ float red[kAdjSlices * kReduceNodes / 64];
+    const int step = t[0] + 1;
+    const int n_nodes = g.Gy * g.Gx;
+    const int j = threadIdx.x % kReduceNodes, slice = threadIdx.x / kReduceNodes;
+    const int node = blockIdx.x * kReduceNodes + j;
+    const bool valid = node < n_nodes;
+    const bool is_free = valid && mask[node] != 0;
+    // the update's own loads go out before the partial sums, so that their latency is hidden behind them
+    const int nd = valid ? node : 0;
+    const int a = nd / g.Gx, b = nd - a * g.Gx;
+    float tv = 0.0f, g_tv = 0.0f, mm = 0.0f, vv = 0.0f, p = 0.0f;
+    if (slice == 0) {
+        mm = m[nd];
+        vv = v[nd];
+        p = sos_in[nd];
+        if (lambda != 0.0f) tv_node(sos_in, mask, nd, a, b, g.Gy, g.Gx, tv, g_tv);
+        if (!valid) tv = 0.0f;
+    }
+    run[slice][j] = is_free && grid_node_in_support(node, g) ? adj_run_sum(partial, n_part, n_nodes, node, slice)
+                                                             : 0.0f;
+    __syncthreads();
+    if (slice == 0 && valid) {
+        float gd = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kAdjSlices; ++k) gd += run[k][j];
+        if (grad_out) grad_out[node] = gd;
+        if (is_free) {
+            p = adam_node(p, fmaf(lambda, g_tv, gd), mm, vv, step, lr, b1, b2, eps);
+            m[node] = mm;
+            v[node] = vv;
+        }
+        sos_out[node] = p;
+    }
+    if (loss) {
+        tv = block_sum(tv, red);
+        if (threadIdx.x == 0 && tv != 0.0f) atomicAdd(loss, lambda * tv);
+    }
+    advance_step(t, step);
+}
+
+RayGeo make_geo(const pact_grid& sosg, int n_samples, float support) {
     RayGeo g;
+    // support disc: a node counts as inside within a relative margin of 1e-6 (so that a node the caller places
+    // exactly on the radius is inside whatever the rounding); a sample can touch an inside node when it lies
+    // within the disc grown by the cell diagonal (and a margin for rounding)
+    const double rho = support > 0.0f ? static_cast<double>(support) * (1.0 + 1e-6) : 0.0;
+    g.rho2 = static_cast<float>(rho * rho);
+    const double rc = rho > 0.0 ? rho + std::sqrt(2.0) * sosg.spacing * 1.001 : 0.0;
+    g.rc2 = static_cast<float>(rc * rc);
+    g.ds = sosg.spacing;
     g.inv_ds = 1.0f / sosg.spacing;
     g.off_x = 0.5f * (sosg.nx + 1);
     g.off_y = 0.5f * (sosg.ny + 1);
@@ -709,7 +914,8 @@ RayGeo make_geo(const pact_grid& sosg, int n_samples) {
 }
 
 int check_rays(const float* sos, pact_grid sosg, float v0, const float* centres, int N, pact_ring ring,
-               int n_samples, const char* what) {
+               int n_samples, float support, const char* what) {
+    PACT_CHECK_ARG(support >= 0.0f && std::isfinite(support), "%s: support_radius must be finite and >= 0", what);
     PACT_CHECK_ARG(sos && centres, "%s: null pointer", what);
     PACT_CHECK_ARG(N > 0 && n_samples > 0, "%s: N and n_samples must be positive", what);
     PACT_CHECK_ARG(v0 > 0.0f && std::isfinite(v0), "%s: v0 must be positive", what);
@@ -719,34 +925,35 @@ int check_rays(const float* sos, pact_grid sosg, float v0, const float* centres,
     return PACT_OK;
 }
 
-// Ray tilings chosen by pact_rays_autotune, per device and geometry: lanes per ray of the forward kernel
-// and segments per ray of the adjoint (0 = the built-in rule).
-using TuneKey = std::tuple<int, int, int, int, int, int>;     // device, N, n_elem, n_samples, ny, nx
+// Ray tilings chosen by pact_rays_autotune, per device and geometry: lanes per ray of the forward kernel (0 = the
+// built-in rule).  The adjoint's work items have a fixed length and need no tuning.
+// device, N, n_elem, n_samples, ny, nx, support radius (bits)
+using TuneKey = std::tuple<int, int, int, int, int, int, unsigned>;
 struct RayTiling {
-    int fwd = 0, adj = 0;
+    int fwd = 0;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, RayTiling> g_tuned;
 
-TuneKey tune_key(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg) {
+TuneKey tune_key(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg, float support) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    return TuneKey(dev, N, ring.n_elem, n_samples, sosg.ny, sosg.nx);
+    unsigned bits = 0;
+    std::memcpy(&bits, &support, sizeof(bits));
+    return TuneKey(dev, N, ring.n_elem, n_samples, sosg.ny, sosg.nx, bits);
 }
 
-RayTiling tuned_tiling(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg) {
+RayTiling tuned_tiling(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg, float support) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    const auto it = g_tuned.find(tune_key(N, ring, n_samples, sosg));
+    const auto it = g_tuned.find(tune_key(N, ring, n_samples, sosg, support));
     return it == g_tuned.end() ? RayTiling() : it->second;
 }
 
-// Lanes per ray of the forward kernel by the built-in rule: the smallest power of two (at most 64, at
-// least 16 samples a segment) whose work items fill about two rounds of two workgroups per CU (measured
-// at 86,528 rays x 256 samples: K = 8 is 10% faster than one round with K = 4).
-int fwd_lanes_rule(long long n_rays, int n_samples) {
-    const long long lanes = 2LL * device_cu_count() * kThreads;
+// Lanes per ray of the forward kernel by the built-in rule: the largest power of two (at most 64, at least 8
+// samples a segment) with which a workgroup's rays fill its lanes in one round.
+int fwd_lanes_rule(int per_block, int n_samples) {
     int K = 1;
-    while (K < 64 && n_rays * K < lanes && n_samples / (2 * K) >= 16) K *= 2;
+    while (K < 64 && 2 * K * per_block <= kThreads && n_samples / (2 * K) >= 8) K *= 2;
     return K;
 }
 
@@ -754,7 +961,8 @@ int fwd_lanes_rule(long long n_rays, int n_samples) {
 }  // namespace pact
 
 extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, float v0, const float* centres, int N,
-                                  const pact_ring* ring_, int n_samples, float* w, void* stream) {
+                                  const pact_ring* ring_, int n_samples, float support_radius, float* w,
+                                  void* stream) {
     if (!sosg_ || !ring_) {
         pact::set_error("pact_sos_to_delays: null geometry pointer");
         return PACT_EINVAL;
@@ -763,27 +971,37 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
     const pact_ring ring = *ring_;
     using namespace pact;
     clear_error();
-    if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_sos_to_delays")) return s;
+    if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, support_radius, "pact_sos_to_delays"))
+        return s;
     PACT_CHECK_ARG(w, "pact_sos_to_delays: null output");
     const size_t lds = static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2) * sizeof(float);
-    PACT_CHECK_SUPPORTED(lds <= kLdsBytes, "pact_sos_to_delays: SOS grid %d x %d does not fit in LDS", sosg.ny,
-                         sosg.nx);
+    PACT_CHECK_SUPPORTED(lds + kLenBuckets * sizeof(int) <= kLdsBytes,
+                         "pact_sos_to_delays: SOS grid %d x %d does not fit in LDS", sosg.ny, sosg.nx);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_fwd_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
         attr = true;
     }
-    // lanes per ray: the autotuned value for this geometry, else the built-in rule
+    // two workgroups per CU, each with about the same number of rays (element-major, so about one element's
+    // rays from every patch); lanes per ray: the autotuned value for this geometry, else the built-in rule
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
-    const int tuned = tuned_tiling(N, ring, n_samples, sosg).fwd;
-    const int K = tuned > 0 ? tuned : fwd_lanes_rule(n_rays, n_samples);
-    PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "pact_sos_to_delays: too many rays");
-    const int n_items = static_cast<int>(n_rays * K);
-    const int blocks = static_cast<int>(std::min<long long>(ceil_div(n_items, kThreads), 2LL * device_cu_count()));
-    rays_fwd_kernel<<<blocks, kThreads, lds, as_stream(stream)>>>(sos, v0, centres, N, ring.n_elem, ring.radius,
-                                                                 ring.phi0, n_samples, make_geo(sosg, n_samples), K,
-                                                                 n_items, w);
+    // ray indices are split by float quotients, exact below 2^24
+    PACT_CHECK_SUPPORTED(n_rays < (1LL << 24), "pact_sos_to_delays: too many rays");
+    const int blocks = static_cast<int>(std::min<long long>(2LL * device_cu_count(), n_rays));
+    const int per_block = ceil_div(n_rays, blocks);
+    const int tuned = tuned_tiling(N, ring, n_samples, sosg, support_radius).fwd;
+    const int K = tuned > 0 ? tuned : fwd_lanes_rule(per_block, n_samples);
+    int log2K = 0;
+    while ((1 << log2K) < K) ++log2K;
+    PACT_CHECK_ARG((1 << log2K) == K, "pact_sos_to_delays: lanes per ray must be a power of two");
+    // the rays' order by length, if it fits beside the staged grid (with two workgroups per CU when it can)
+    const size_t base = lds + kLenBuckets * sizeof(int);
+    const size_t with_order = base + static_cast<size_t>(per_block) * sizeof(int);
+    const int sorted = with_order <= kLdsBytes ? 1 : 0;
+    rays_fwd_kernel<<<blocks, kThreads, sorted ? with_order : base, as_stream(stream)>>>(
+        sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support_radius),
+        log2K, static_cast<int>(n_rays), per_block, sorted, w);
     return launch_status("pact_sos_to_delays");
 }
 
@@ -799,7 +1017,8 @@ struct AdjPlan {
 
 AdjPlan adj_plan(const pact_grid& sosg) {
     const size_t W = static_cast<size_t>(sosg.nx) + 2, H = static_cast<size_t>(sosg.ny) + 2;
-    const size_t red = (kGridThreads / 64) * sizeof(float);
+    // after the grid arrays: the block reduction's slots and the ray-length buckets
+    const size_t red = (kGridThreads / 64) * sizeof(float) + kLenBuckets * sizeof(int);
     if (2 * H * W * sizeof(float) + red <= kLdsBytes) return {1, sosg.ny + 1, 2 * H * W * sizeof(float) + red};
     const long long max_rows = static_cast<long long>((kLdsBytes - red) / (2 * W * sizeof(float))) - 1;
     if (max_rows < 8) return {0, 0, 0};
@@ -811,27 +1030,10 @@ AdjPlan adj_plan(const pact_grid& sosg) {
 
 size_t adj_grid_lds(const pact_grid& sosg) { return adj_plan(sosg).bands ? adj_plan(sosg).lds : 0; }
 
-// Segments per ray for rays_adj_grid_kernel: the K that minimises the critical path of one lane, rounds of
-// items times (segment length + a ray set-up worth about two samples), with at least 8 samples a segment.
-int adj_segments(long long n_rays, int n_samples, long long lanes) {
-    int best = 1;
-    long long best_cost = -1;
-    const int kmax = std::max(1, std::min(n_samples / 8, 256));
-    for (int K = 1; K <= kmax; ++K) {
-        const long long rounds = (n_rays * K + lanes - 1) / lanes;
-        const long long cost = rounds * ((n_samples + K - 1) / K + 2);
-        if (best_cost < 0 || cost < best_cost) {
-            best_cost = cost;
-            best = K;
-        }
-    }
-    return best;
-}
-
 // The grid adjoint into one partial node grid per workgroup (the caller sums them); *n_part = their count.
 int launch_adj_grid(const float* sos, const pact_grid& sosg, float v0, const float* centres, int N,
-                    const pact_ring& ring, int n_samples, const float* dL_dw, const float* scale, float* partial,
-                    size_t ws_bytes, hipStream_t st, int* n_part, const char* what) {
+                    const pact_ring& ring, int n_samples, float support, const float* dL_dw, const float* scale,
+                    float* partial, size_t ws_bytes, hipStream_t st, int* n_part, const char* what) {
     const AdjPlan plan = adj_plan(sosg);
     const int cus = device_cu_count();
     const int per_band = std::max(1, cus / plan.bands);           // workgroups per band
@@ -850,19 +1052,23 @@ int launch_adj_grid(const float* sos, const pact_grid& sosg, float v0, const flo
         gattr = true;
     }
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
-    const int tuned = tuned_tiling(N, ring, n_samples, sosg).adj;
-    const int K = tuned > 0 ? tuned : adj_segments(n_rays, n_samples, static_cast<long long>(per_band) * kGridThreads);
-    PACT_CHECK_SUPPORTED(n_rays * K < (1LL << 31), "%s: too many ray segments", what);
-    const int n_items = static_cast<int>(n_rays * K);
-    const int per_block = ceil_div(n_items, per_band);
+    // ray and item indices are split by float quotients, exact below 2^24
+    PACT_CHECK_SUPPORTED(n_rays < (1LL << 24), "%s: too many rays", what);
+    const int per_block = ceil_div(n_rays, per_band);
+    // segments per ray: as many as fill the workgroup's lanes in one round (at least 8 samples a segment)
+    const int K = std::max(1, std::min(kGridThreads / std::max(per_block, 1), std::max(1, n_samples / 8)));
+    // the rays in order of length, if the workgroup's list fits beside the grid arrays
+    const size_t order_bytes = static_cast<size_t>(per_block) * sizeof(int);
+    const int sorted = plan.lds + order_bytes <= kLdsBytes ? 1 : 0;
+    const size_t lds = plan.lds + (sorted ? order_bytes : 0);
     if (plan.bands == 1)
-        rays_adj_grid_kernel<false><<<blocks, kGridThreads, plan.lds, st>>>(
-            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), K, n_items,
-            per_block, 1, sosg.ny + 1, dL_dw, scale, partial);
+        rays_adj_grid_kernel<false><<<blocks, kGridThreads, lds, st>>>(
+            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
+            static_cast<int>(n_rays), per_block, K, sorted, 1, sosg.ny + 1, dL_dw, scale, partial);
     else
-        rays_adj_grid_kernel<true><<<blocks, kGridThreads, plan.lds, st>>>(
-            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), K, n_items,
-            per_block, plan.bands, plan.band_rows, dL_dw, scale, partial);
+        rays_adj_grid_kernel<true><<<blocks, kGridThreads, lds, st>>>(
+            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
+            static_cast<int>(n_rays), per_block, K, sorted, plan.bands, plan.band_rows, dL_dw, scale, partial);
     *n_part = blocks;
     return launch_status(what);
 }
@@ -881,9 +1087,9 @@ extern "C" size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sos
 }
 
 extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg_, float v0, const float* centres,
-                                          int N, const pact_ring* ring_, int n_samples, const float* dL_dw,
-                                          const float* scale, float* dL_dsos, int accumulate, void* ws,
-                                          size_t ws_bytes, void* stream) {
+                                          int N, const pact_ring* ring_, int n_samples, float support_radius,
+                                          const float* dL_dw, const float* scale, float* dL_dsos, int accumulate,
+                                          void* ws, size_t ws_bytes, void* stream) {
     if (!sosg_ || !ring_) {
         pact::set_error("pact_sos_to_delays_adjoint: null geometry pointer");
         return PACT_EINVAL;
@@ -892,17 +1098,18 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     const pact_ring ring = *ring_;
     using namespace pact;
     clear_error();
-    if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_sos_to_delays_adjoint")) return s;
+    if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, support_radius, "pact_sos_to_delays_adjoint"))
+        return s;
     PACT_CHECK_ARG(dL_dw && dL_dsos, "pact_sos_to_delays_adjoint: null pointer");
     if (adj_grid_lds(sosg)) {
         float* partial = static_cast<float*>(ws);
         int n_part = 0;
-        if (int st = launch_adj_grid(sos, sosg, v0, centres, N, ring, n_samples, dL_dw, scale, partial, ws_bytes,
-                                     as_stream(stream), &n_part, "pact_sos_to_delays_adjoint"))
+        if (int st = launch_adj_grid(sos, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, scale, partial,
+                                     ws_bytes, as_stream(stream), &n_part, "pact_sos_to_delays_adjoint"))
             return st;
         const int n_nodes = sosg.ny * sosg.nx;
         rays_adj_reduce_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(
-            partial, n_part, n_nodes, accumulate, dL_dsos);
+            partial, n_part, make_geo(sosg, n_samples, support_radius), accumulate, dL_dsos);
         return launch_status("pact_sos_to_delays_adjoint");
     }
     const size_t lds = static_cast<size_t>(kTile + 2) * (kTile + 2) * kAdjThreads * sizeof(float) +
@@ -919,17 +1126,53 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     }
     const int tiles_x = ceil_div(sosg.nx, kTile), tiles_y = ceil_div(sosg.ny, kTile);
     rays_adj_tile_kernel<<<tiles_x * tiles_y, kAdjThreads, lds, as_stream(stream)>>>(
-        sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples), tiles_x,
+        sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support_radius),
+        tiles_x,
         dL_dw, scale, accumulate, dL_dsos);
     return launch_status("pact_sos_to_delays_adjoint");
+}
+
+extern "C" int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out, float* m, float* v, int* t,
+                                             const unsigned char* mask, const pact_grid* sosg_, float v0,
+                                             const float* centres, int N, const pact_ring* ring_, int n_samples,
+                                             float support_radius, const float* dL_dw, float lambda, float* loss,
+                                             float lr, float b1, float b2, float eps, float* grad, void* ws,
+                                             size_t ws_bytes, void* stream) {
+    if (!sosg_ || !ring_) {
+        pact::set_error("pact_sos_adjoint_tv_adam_step: null geometry pointer");
+        return PACT_EINVAL;
+    }
+    const pact_grid sosg = *sosg_;
+    const pact_ring ring = *ring_;
+    using namespace pact;
+    clear_error();
+    const char* what = "pact_sos_adjoint_tv_adam_step";
+    if (int s = check_rays(sos_in, sosg, v0, centres, N, ring, n_samples, support_radius, what)) return s;
+    PACT_CHECK_ARG(sos_out && m && v && t && mask && dL_dw, "%s: null pointer", what);
+    PACT_CHECK_ARG(sos_in != sos_out, "%s: sos_out must not be sos_in", what);
+    PACT_CHECK_ARG(std::isfinite(lambda), "%s: lambda must be finite", what);
+    PACT_CHECK_ARG(b1 >= 0.0f && b1 < 1.0f && b2 >= 0.0f && b2 < 1.0f, "%s: betas must be in [0, 1)", what);
+    PACT_CHECK_ARG(eps > 0.0f && std::isfinite(lr), "%s: eps must be positive and lr finite", what);
+    PACT_CHECK_SUPPORTED(adj_grid_lds(sosg) > 0, "%s: the %d x %d grid takes the tiled adjoint; use "
+                         "pact_sos_to_delays_adjoint and pact_tv_adam_step", what, sosg.ny, sosg.nx);
+    float* partial = static_cast<float*>(ws);
+    int n_part = 0;
+    if (int st = launch_adj_grid(sos_in, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, nullptr,
+                                 partial, ws_bytes, as_stream(stream), &n_part, what))
+        return st;
+    const int n_nodes = sosg.ny * sosg.nx;
+    adj_reduce_tv_adam_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(
+        partial, n_part, make_geo(sosg, n_samples, support_radius), sos_in, sos_out, m, v, t, mask, lambda, loss, lr,
+        b1, b2, eps, grad);
+    return launch_status(what);
 }
 
 namespace pact {
 namespace {
 
-void set_tiling(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg, RayTiling t) {
+void set_tiling(int N, const pact_ring& ring, int n_samples, const pact_grid& sosg, float support, RayTiling t) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tuned[tune_key(N, ring, n_samples, sosg)] = t;
+    g_tuned[tune_key(N, ring, n_samples, sosg, support)] = t;
 }
 
 // Median time (ms) of `reps` runs of fn on the stream, by HIP events; negative on an error, with the
@@ -971,29 +1214,35 @@ float time_ms(F fn, hipStream_t st, int reps, int& status) {
 }  // namespace pact
 
 extern "C" int pact_rays_autotune(const float* sos, const pact_grid* sosg_, float v0, const float* centres, int N,
-                                  const pact_ring* ring_, int n_samples, const float* dL_dw, float* w,
+                                  const pact_ring* ring_, int n_samples, float support_radius, const float* dL_dw,
+                                  float* w,
                                   float* dL_dsos, void* ws, size_t ws_bytes, int* tiling, void* stream) {
     using namespace pact;
     clear_error();
-    PACT_CHECK_ARG(sosg_ && ring_ && dL_dw && w && dL_dsos, "pact_rays_autotune: null pointer");
+    (void)dL_dw;
+    (void)dL_dsos;
+    (void)ws;
+    (void)ws_bytes;
+    PACT_CHECK_ARG(sosg_ && ring_ && w, "pact_rays_autotune: null pointer");
     const pact_grid sosg = *sosg_;
     const pact_ring ring = *ring_;
-    if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, "pact_rays_autotune")) return s;
+    if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, support_radius, "pact_rays_autotune"))
+        return s;
     hipStream_t st = as_stream(stream);
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
     const int reps = 5;
-    set_tiling(N, ring, n_samples, sosg, RayTiling());   // time every candidate from a clean table
+    set_tiling(N, ring, n_samples, sosg, support_radius, RayTiling());   // time every candidate from a clean table
     // forward: powers of two from 1 to 64 lanes per ray with at least 8 samples a lane
     RayTiling best;
     float best_ms = -1.0f;
     for (int K = 1; K <= 64 && n_samples / K >= 8; K *= 2) {
-        if (n_rays * K >= (1LL << 31)) break;
-        set_tiling(N, ring, n_samples, sosg, RayTiling{K, 0});
+        if (n_rays * K >= (1LL << 24)) break;
+        set_tiling(N, ring, n_samples, sosg, support_radius, RayTiling{K});
         int status = PACT_OK;
-        const float ms = time_ms([&] { return pact_sos_to_delays(sos, &sosg, v0, centres, N, &ring, n_samples, w,
-                                                                 stream); }, st, reps, status);
+        const float ms = time_ms([&] { return pact_sos_to_delays(sos, &sosg, v0, centres, N, &ring, n_samples,
+                                                                 support_radius, w, stream); }, st, reps, status);
         if (ms < 0.0f) {
-            set_tiling(N, ring, n_samples, sosg, RayTiling());
+            set_tiling(N, ring, n_samples, sosg, support_radius, RayTiling());
             if (status == PACT_EHIP) set_error("pact_rays_autotune: timing events failed");
             return status;
         }
@@ -1002,37 +1251,10 @@ extern "C" int pact_rays_autotune(const float* sos, const pact_grid* sosg_, floa
             best.fwd = K;
         }
     }
-    // adjoint (grid form only): segments per ray around the built-in rule
-    if (const AdjPlan plan = adj_plan(sosg); plan.bands) {
-        const long long per_band = std::max(1, device_cu_count() / plan.bands);
-        const int rule = adj_segments(n_rays, n_samples, per_band * kGridThreads);
-        std::vector<int> cand = {rule, rule - 1, rule + 1, rule / 2, rule * 2, 1, 2, 4, 8, 16};
-        std::sort(cand.begin(), cand.end());
-        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-        best_ms = -1.0f;
-        for (int K : cand) {
-            if (K < 1 || K > std::max(1, n_samples / 4) || n_rays * K >= (1LL << 31)) continue;
-            set_tiling(N, ring, n_samples, sosg, RayTiling{best.fwd, K});
-            int status = PACT_OK;
-            const float ms = time_ms([&] { return pact_sos_to_delays_adjoint(sos, &sosg, v0, centres, N, &ring,
-                                                                             n_samples, dL_dw, nullptr, dL_dsos, 0,
-                                                                             ws, ws_bytes, stream); }, st, reps,
-                                     status);
-            if (ms < 0.0f) {
-                set_tiling(N, ring, n_samples, sosg, RayTiling());
-                if (status == PACT_EHIP) set_error("pact_rays_autotune: timing events failed");
-                return status;
-            }
-            if (best_ms < 0.0f || ms < best_ms) {
-                best_ms = ms;
-                best.adj = K;
-            }
-        }
-    }
-    set_tiling(N, ring, n_samples, sosg, best);
+    set_tiling(N, ring, n_samples, sosg, support_radius, best);
     if (tiling) {
         tiling[0] = best.fwd;
-        tiling[1] = best.adj;
+        tiling[1] = 0;
     }
     return PACT_OK;
 }

@@ -52,9 +52,9 @@ _SIGS = {
     "pact_das_stack": (_I, [_P, _I, _F, _F, _PRING, _F, _P, _I, _PGRID, _P, _P]),
     "pact_patch_fft": (_I, [_P, _I, _PGRID, _PPATCH, _I, _P, _P]),
     "pact_ifft2_real": (_I, [_P, _I, _I, _P, _P]),
-    "pact_sos_to_delays": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _P, _P]),
+    "pact_sos_to_delays": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _P]),
     "pact_sos_to_delays_adjoint_workspace_size": (_Z, [_PGRID, _I, _PRING]),
-    "pact_sos_to_delays_adjoint": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _P, _P, _P, _I, _P, _Z, _P]),
+    "pact_sos_to_delays_adjoint": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _P, _P, _I, _P, _Z, _P]),
     "pact_delays_to_psf": (_I, [_P, _P, _I, _PRING, _P, _I, _I, _F, _P, _P, _P]),
     "pact_delays_to_psf_adjoint": (_I, [_P, _P, _I, _PRING, _P, _I, _I, _F, _P, _P, _P]),
     "pact_multichannel_deconv": (_I, [_P, _P, _I, _I, _I, _F, _P, _P]),
@@ -63,6 +63,9 @@ _SIGS = {
     "pact_residual_loss": (_I, [_P, _P, _P, _I, _I, _I, _F, _P, _P, _P, _P, _Z, _P]),
     "pact_loss_and_grad_workspace_size": (_Z, [_I, _I, _I, _I]),
     "pact_loss_and_grad": (_I, [_P, _P, _P, _I, _PRING, _P, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
+    "pact_projected_spectra_floats": (_Z, [_I, _I]),
+    "pact_project_spectra": (_I, [_P, _I, _I, _I, _F, _P, _P, _P]),
+    "pact_loss_and_grad_projected": (_I, [_P, _P, _P, _I, _PRING, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
     "pact_tv_grad": (_I, [_P, _P, _PGRID, _F, _P, _P, _P]),
     "pact_adam_step": (_I, [_P, _P, _P, _P, _P, _I, _P, _F, _F, _F, _F, _P]),
     "pact_stitch": (_I, [_P, _I, _PGRID, _PPATCH, _P, _P]),
@@ -70,6 +73,8 @@ _SIGS = {
     "pact_siren_sos_adjoint_workspace_size": (_Z, [_PGRID, _I]),
     "pact_siren_sos_adjoint": (_I, [_P, _I, _F, _P, _PGRID, _F, _P, _P, _P, _Z, _P]),
     "pact_tv_adam_step": (_I, [_P, _P, _P, _P, _P, _P, _PGRID, _P, _F, _P, _F, _F, _F, _F, _P]),
+    "pact_sos_adjoint_tv_adam_step": (_I, [_P, _P, _P, _P, _P, _P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _F, _P,
+                                           _F, _F, _F, _F, _P, _P, _Z, _P]),
     "pact_nf_param_count": (_Z, [_I, _I]),
     "pact_nf_packed_count": (_Z, [_I, _I]),
     "pact_nf_pack": (_I, [_P, _I, _I, _P, _P]),
@@ -78,7 +83,7 @@ _SIGS = {
     "pact_nf_sos_to_delays_adjoint_workspace_size": (_Z, [_I, _I]),
     "pact_nf_sos_to_delays_adjoint": (_I, [_P, _P, _P, _I, _I, _F, _F, _F, _P, _I, _PRING, _I, _P, _P, _P, _P,
                                            _Z, _P, _Z, _P]),
-    "pact_rays_autotune": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _P, _P, _P, _P, _Z, _P, _P]),
+    "pact_rays_autotune": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _P, _P, _P, _Z, _P, _P]),
     "pact_conv3x3_packed_count": (_Z, [_I, _I]),
     "pact_conv3x3_pack": (_I, [_P, _I, _I, _P, _P, _P]),
     "pact_conv3x3_bf16": (_I, [_P, _I, _I, _I, _I, _P, _P, _I, _I, _P, _P, _P]),
@@ -228,11 +233,12 @@ def ifft2_real(X, out=None):
     return out
 
 
-def sos_to_delays(sos, g: Geometry, v0, centres, n_samples, out=None):
+def sos_to_delays(sos, g: Geometry, v0, centres, n_samples, out=None, support=0.0):
+    """support: radius (mm) of the circular mask outside which the SOS is v0 (0: none); see include/pact.h."""
     N = centres.shape[0]
     out = torch.empty(N, g.n_elem, dtype=F32, device=sos.device) if out is None else out
     _check(load().pact_sos_to_delays(_ptr(sos, F32, "sos", g.sos_ny * g.sos_nx), g.sosg, v0,
-                                     _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples,
+                                     _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples, float(support),
                                      _ptr(out, F32, "w", N * g.n_elem), _stream()), "pact_sos_to_delays")
     return out
 
@@ -242,27 +248,27 @@ def sos_to_delays_adjoint_workspace_size(g: Geometry, N: int) -> int:
 
 
 def sos_to_delays_adjoint(sos, g: Geometry, v0, centres, n_samples, dL_dw, out=None, scale=None, accumulate=False,
-                          ws=None):
+                          ws=None, support=0.0):
     N = centres.shape[0]
     out = torch.empty(g.sos_ny, g.sos_nx, dtype=F32, device=sos.device) if out is None else out
     need = sos_to_delays_adjoint_workspace_size(g, N)
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=sos.device) if ws is None else ws
     _check(load().pact_sos_to_delays_adjoint(
         _ptr(sos, F32, "sos", g.sos_ny * g.sos_nx), g.sosg, v0, _ptr(centres, F32, "centres", 2 * N), N, g.ring,
-        n_samples, _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), _ptr(scale, F32, "scale", 1),
+        n_samples, float(support), _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), _ptr(scale, F32, "scale", 1),
         _ptr(out, F32, "dL_dsos", g.sos_ny * g.sos_nx), int(accumulate), _ptr(ws, name="ws"), ws.numel(),
         _stream()), "pact_sos_to_delays_adjoint")
     return out
 
 
-def rays_autotune(sos, g: Geometry, v0, centres, n_samples, dL_dw, w, dL_dsos, ws):
+def rays_autotune(sos, g: Geometry, v0, centres, n_samples, dL_dw, w, dL_dsos, ws, support=0.0):
     """Time the ray tilings on this geometry and keep the fastest (see include/pact.h); returns
     (forward lanes per ray, adjoint segments per ray).  w, dL_dsos and ws are overwritten."""
     N = centres.shape[0]
     n = g.sos_ny * g.sos_nx
     out = (ctypes.c_int * 2)()
     _check(load().pact_rays_autotune(_ptr(sos, F32, "sos", n), g.sosg, v0, _ptr(centres, F32, "centres", 2 * N), N,
-                                     g.ring, n_samples, _ptr(dL_dw, F32, "dL_dw", N * g.n_elem),
+                                     g.ring, n_samples, float(support), _ptr(dL_dw, F32, "dL_dw", N * g.n_elem),
                                      _ptr(w, F32, "w", N * g.n_elem), _ptr(dL_dsos, F32, "dL_dsos", n),
                                      _ptr(ws, name="ws"), ws.numel(), ctypes.cast(out, ctypes.c_void_p), _stream()),
            "pact_rays_autotune")
@@ -332,11 +338,15 @@ def loss_and_grad_workspace_size(N, M, P, n_elem) -> int:
 
 
 def loss_and_grad(Y_half, w, centres, g: Geometry, d, eps, loss=None, dL_dw=None, want_grad=True, X=None,
-                  ws=None):
+                  ws=None, want_loss=True):
+    """want_loss False: the scalar loss is not formed (one launch fewer); returns (None, dL_dw)."""
     N, M, P, Wh = Y_half.shape
     assert Wh == P // 2 + 1 and P == g.P
     dev = Y_half.device
-    loss = torch.empty(1, dtype=F32, device=dev) if loss is None else loss
+    if want_loss:
+        loss = torch.empty(1, dtype=F32, device=dev) if loss is None else loss
+    else:
+        loss = None
     if want_grad and dL_dw is None:
         dL_dw = torch.empty(N, g.n_elem, dtype=F32, device=dev)
     need = loss_and_grad_workspace_size(N, M, P, g.n_elem)
@@ -347,6 +357,38 @@ def loss_and_grad(Y_half, w, centres, g: Geometry, d, eps, loss=None, dL_dw=None
                                      _ptr(dL_dw, F32, "dL_dw", N * g.n_elem) if want_grad else None,
                                      _ptr(X, C64, "X", N * P * P), _ptr(ws, name="ws"), ws.numel(), _stream()),
            "pact_loss_and_grad")
+    return loss, dL_dw
+
+
+def project_spectra(Y_half, g: Geometry, d, out=None):
+    """Step-invariant projections of the half spectra (see include/pact.h): float [(5 N + 2) P (P/2 + 1)]."""
+    N, M, P, Wh = Y_half.shape
+    assert Wh == P // 2 + 1 and P == g.P
+    n = int(load().pact_projected_spectra_floats(N, P))
+    out = torch.empty(n, dtype=F32, device=Y_half.device) if out is None else out
+    _check(load().pact_project_spectra(_ptr(Y_half, C64, "Y_half"), N, M, P, g.px, _ptr(d, F32, "d", M),
+                                       _ptr(out, F32, "T", n), _stream()), "pact_project_spectra")
+    return out
+
+
+def loss_and_grad_projected(T, M, w, centres, g: Geometry, eps, loss=None, dL_dw=None, want_grad=True, X=None,
+                            ws=None, want_loss=True):
+    """pact_loss_and_grad from projected spectra T (project_spectra) with M delays."""
+    N = centres.shape[0]
+    P = g.P
+    dev = T.device
+    loss = (torch.empty(1, dtype=F32, device=dev) if loss is None else loss) if want_loss else None
+    if want_grad and dL_dw is None:
+        dL_dw = torch.empty(N, g.n_elem, dtype=F32, device=dev)
+    need = loss_and_grad_workspace_size(N, M, P, g.n_elem)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev) if ws is None else ws
+    n = int(load().pact_projected_spectra_floats(N, P))
+    _check(load().pact_loss_and_grad_projected(_ptr(T, F32, "T", n), _ptr(w, F32, "w", N * g.n_elem),
+                                               _ptr(centres, F32, "centres", 2 * N), N, g.ring, M, P, g.px, eps,
+                                               _ptr(loss, F32, "loss", 1),
+                                               _ptr(dL_dw, F32, "dL_dw", N * g.n_elem) if want_grad else None,
+                                               _ptr(X, C64, "X", N * P * P), _ptr(ws, name="ws"), ws.numel(),
+                                               _stream()), "pact_loss_and_grad_projected")
     return loss, dL_dw
 
 
@@ -396,11 +438,28 @@ def siren_sos_adjoint(params, hidden, omega0, mask, g: Geometry, mask_radius, dL
 
 
 def tv_adam_step(sos_in, sos_out, m, v, t, mask, g: Geometry, grad, lam, loss, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """loss None: the TV value is not added to a loss."""
     n = g.sos_ny * g.sos_nx
     _check(load().pact_tv_adam_step(_ptr(sos_in, F32, "sos_in", n), _ptr(sos_out, F32, "sos_out", n),
                                     _ptr(m, F32, "m", n), _ptr(v, F32, "v", n), _ptr(t, I32, "t", 2),
                                     _ptr(mask, U8, "mask", n), g.sosg, _ptr(grad, F32, "grad", n), lam,
                                     _ptr(loss, F32, "loss", 1), lr, b1, b2, eps, _stream()), "pact_tv_adam_step")
+    return sos_out
+
+
+def sos_adjoint_tv_adam_step(sos_in, sos_out, m, v, t, mask, g: Geometry, v0, centres, n_samples, dL_dw, lam, loss,
+                             lr, b1=0.9, b2=0.999, eps=1e-8, support=0.0, grad=None, ws=None):
+    """Ray adjoint, TV and Adam in two launches (see include/pact.h); loss None: no TV value added."""
+    N = centres.shape[0]
+    n = g.sos_ny * g.sos_nx
+    need = sos_to_delays_adjoint_workspace_size(g, N)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=sos_in.device) if ws is None else ws
+    _check(load().pact_sos_adjoint_tv_adam_step(
+        _ptr(sos_in, F32, "sos_in", n), _ptr(sos_out, F32, "sos_out", n), _ptr(m, F32, "m", n), _ptr(v, F32, "v", n),
+        _ptr(t, I32, "t", 2), _ptr(mask, U8, "mask", n), g.sosg, v0, _ptr(centres, F32, "centres", 2 * N), N, g.ring,
+        n_samples, float(support), _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), lam, _ptr(loss, F32, "loss", 1), lr, b1,
+        b2, eps, _ptr(grad, F32, "grad", n), _ptr(ws, name="ws"), ws.numel(), _stream()),
+        "pact_sos_adjoint_tv_adam_step")
     return sos_out
 
 

@@ -39,12 +39,28 @@ class ScanData:
         self.centres = pact.patch_centres(geom, device=S.device)
         self.stack = None
         self.Y = None
+        self.T = None
+
+    @property
+    def M(self) -> int:
+        return self.d.numel()
 
     def prepare(self):
-        """DAS stack and windowed half spectra (once per scan)."""
+        """DAS stack, windowed half spectra and their step-invariant projections (once per scan)."""
         self.stack = pact.das_stack(self.S, self.fs, self.t0, self.geom, self.v0, self.d, out=self.stack)
         self.Y = pact.patch_fft(self.stack, self.geom, half=True, out=self.Y)
+        self.T = pact.project_spectra(self.Y, self.geom, self.d, out=self.T)
         return self.Y
+
+    def use_spectra(self, Y):
+        """Take given half spectra [N][M][P][P/2+1] (instead of the DAS stack's) and project them."""
+        self.Y = Y
+        self.T = pact.project_spectra(Y, self.geom, self.d)
+        return self
+
+    def loss_and_grad(self, w, eps, **kw):
+        """The fused data term and dL/dw at wavefront table w, from the projected spectra."""
+        return pact.loss_and_grad_projected(self.T, self.M, w, self.centres, self.geom, eps, **kw)
 
 
 def prepare_scan(cfg, S, delays, device="cuda") -> ScanData:
@@ -60,11 +76,14 @@ class PixelGridSolver:
     """Adam on the free nodes of the SOS grid; all state on the device."""
 
     def __init__(self, scan: ScanData, mask, eps: float, lam: float, lr: float, n_samples: int, sos_init=None,
-                 b1=0.9, b2=0.999, adam_eps=1e-8):
+                 b1=0.9, b2=0.999, adam_eps=1e-8, support_radius: float = 0.0):
+        """support_radius: when the mask is the disc of free nodes within this radius (mm) of the origin, the
+        ray kernels skip the samples that touch only fixed nodes (0: no such skipping)."""
         g = scan.geom
         dev = scan.S.device
         self.scan, self.g = scan, g
         self.eps, self.lam, self.lr, self.n_samples = float(eps), float(lam), float(lr), int(n_samples)
+        self.support = float(support_radius)
         self.b1, self.b2, self.adam_eps = b1, b2, adam_eps
         self.mask = torch.as_tensor(mask, dtype=torch.uint8).to(dev).contiguous()
         v0 = scan.v0
@@ -86,10 +105,10 @@ class PixelGridSolver:
         self.gw = torch.empty(N, g.n_elem, dtype=F32, device=dev)
         self.grad = torch.empty_like(self.sos)
         self.loss = torch.zeros(1, dtype=F32, device=dev)
-        self.ws_loss = torch.empty(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
+        self.ws_loss = torch.zeros(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
                                    dtype=torch.uint8, device=dev)
-        self.ws_adj = torch.empty(max(1, pact.sos_to_delays_adjoint_workspace_size(g, N)), dtype=torch.uint8,
-                                  device=dev)
+        self.ws_adj_bytes = pact.sos_to_delays_adjoint_workspace_size(g, N)
+        self.ws_adj = torch.empty(max(1, self.ws_adj_bytes), dtype=torch.uint8, device=dev)
         self.graph = None
         self.graph_steps = 0
 
@@ -100,15 +119,16 @@ class PixelGridSolver:
 
     # one optimisation step (a2 -> a8), enqueued on the current stream
     def delays(self):
-        pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w)
+        pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w,
+                           support=self.support)
 
-    def loss_grad(self):
-        pact.loss_and_grad(self.scan.Y, self.w, self.scan.centres, self.g, self.scan.d, self.eps, loss=self.loss,
-                           dL_dw=self.gw, ws=self.ws_loss)
+    def loss_grad(self, with_loss=True):
+        """with_loss False: only dL/dw (the scalar loss is formed on the steps whose loss is read)."""
+        self.scan.loss_and_grad(self.w, self.eps, loss=self.loss, dL_dw=self.gw, ws=self.ws_loss, want_loss=with_loss)
 
     def adjoint(self):
         pact.sos_to_delays_adjoint(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
-                                   out=self.grad, ws=self.ws_adj)
+                                   out=self.grad, ws=self.ws_adj, support=self.support)
 
     def regularise(self):
         """TV value and subgradient added to loss and grad (the separate form of the fused update)."""
@@ -120,17 +140,31 @@ class PixelGridSolver:
         pact.adam_step(self.sos, self.m, self.v, self.t, self.mask, self.grad, self.lr, self.b1, self.b2,
                        self.adam_eps)
 
-    def tv_update(self):
+    def tv_update(self, with_loss=True):
         """TV and Adam in one kernel, from the current buffer into the other one."""
         pact.tv_adam_step(self._bufs[self._cur], self._bufs[1 - self._cur], self.m, self.v, self.t, self.mask,
-                          self.g, self.grad, self.lam, self.loss, self.lr, self.b1, self.b2, self.adam_eps)
+                          self.g, self.grad, self.lam, self.loss if with_loss else None, self.lr, self.b1, self.b2,
+                          self.adam_eps)
         self._cur = 1 - self._cur
 
-    def step(self):
+    def adjoint_update(self, with_loss=True):
+        """Ray adjoint, TV and Adam: two launches where the grid takes the whole-grid or banded adjoint (the
+        partial grids' sum fused with TV and Adam), else the adjoint and the fused TV + Adam."""
+        if self.ws_adj_bytes > 0:
+            pact.sos_adjoint_tv_adam_step(self._bufs[self._cur], self._bufs[1 - self._cur], self.m, self.v, self.t,
+                                          self.mask, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
+                                          self.lam, self.loss if with_loss else None, self.lr, self.b1, self.b2,
+                                          self.adam_eps, support=self.support, grad=self.grad, ws=self.ws_adj)
+            self._cur = 1 - self._cur
+        else:
+            self.adjoint()
+            self.tv_update(with_loss)
+
+    def step(self, with_loss=True):
+        """One step; with_loss False leaves `loss` as it was (the gradient and the update are the same)."""
         self.delays()
-        self.loss_grad()
-        self.adjoint()
-        self.tv_update()
+        self.loss_grad(with_loss)
+        self.adjoint_update(with_loss)
 
     def autotune(self):
         """Time the ray tilings on this scan's geometry (at the current SOS and its loss gradient) and keep
@@ -138,7 +172,7 @@ class PixelGridSolver:
         self.delays()
         self.loss_grad()
         return pact.rays_autotune(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
-                                  self.w, self.grad, self.ws_adj)
+                                  self.w, self.grad, self.ws_adj, support=self.support)
 
     def capture(self, steps: int):
         """Capture `steps` (even) consecutive steps into one HIP graph (run one eager step first).  The
@@ -151,8 +185,10 @@ class PixelGridSolver:
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             with torch.cuda.graph(g, stream=s):
-                for _ in range(steps):
-                    self.step()
+                for k in range(steps):
+                    # the loss is formed on the last step of the graph only: a replay leaves the loss of its last
+                    # step, the value a caller reads
+                    self.step(with_loss=k == steps - 1)
         torch.cuda.current_stream().wait_stream(s)
         self.graph, self.graph_steps = g, steps
         return g
@@ -178,7 +214,7 @@ class SosLoss(torch.autograd.Function):
         g = scan.geom
         sos = sos.contiguous()
         w = pact.sos_to_delays(sos, g, scan.v0, scan.centres, n_samples)
-        loss, gw = pact.loss_and_grad(scan.Y, w, scan.centres, g, scan.d, eps)
+        loss, gw = scan.loss_and_grad(w, eps)
         ctx.save_for_backward(sos, gw)
         ctx.scan, ctx.n_samples = scan, n_samples
         return loss.view(())
@@ -216,7 +252,7 @@ class NeuralFieldSolver:
         self.gw = torch.empty(N, g.n_elem, dtype=F32, device=dev)
         self.grad = torch.empty_like(self.params)
         self.loss = torch.zeros(1, dtype=F32, device=dev)
-        self.ws_loss = torch.empty(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
+        self.ws_loss = torch.zeros(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
                                    dtype=torch.uint8, device=dev)
         self.ws_nf = torch.empty(max(1, pact.nf_sos_to_delays_adjoint_workspace_size(net)), dtype=torch.uint8,
                                  device=dev)
@@ -232,8 +268,7 @@ class NeuralFieldSolver:
                               self.n_samples, out=self.w, act=self.act)
 
     def loss_grad(self):
-        pact.loss_and_grad(self.scan.Y, self.w, self.scan.centres, self.g, self.scan.d, self.eps, loss=self.loss,
-                           dL_dw=self.gw, ws=self.ws_loss)
+        self.scan.loss_and_grad(self.w, self.eps, loss=self.loss, dL_dw=self.gw, ws=self.ws_loss)
 
     def adjoint(self):
         pact.nf_sos_to_delays_adjoint(self.B, self.params, self.packed, self.net, self.scan.v0, self.scan.centres,
@@ -257,11 +292,12 @@ class SirenSolver:
     loss, ray adjoint) and the network's adjoint.  No TV (the paper sets lambda = 0 for the neural field)."""
 
     def __init__(self, scan: ScanData, mask, params, hidden: int, omega0: float, mask_radius: float, lr: float,
-                 eps: float, n_samples: int, b1=0.9, b2=0.999, adam_eps=1e-8):
+                 eps: float, n_samples: int, b1=0.9, b2=0.999, adam_eps=1e-8, support_radius: float = 0.0):
         g = scan.geom
         dev = scan.S.device
         self.scan, self.g = scan, g
         self.hidden, self.omega0, self.rho = int(hidden), float(omega0), float(mask_radius)
+        self.support = float(support_radius)
         self.lr, self.eps, self.n_samples = float(lr), float(eps), int(n_samples)
         self.b1, self.b2, self.adam_eps = b1, b2, adam_eps
         self.mask = torch.as_tensor(mask, dtype=torch.uint8).to(dev).contiguous()
@@ -277,7 +313,7 @@ class SirenSolver:
         self.grad_sos = torch.empty_like(self.sos)
         self.grad = torch.empty_like(self.params)
         self.loss = torch.zeros(1, dtype=F32, device=dev)
-        self.ws_loss = torch.empty(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
+        self.ws_loss = torch.zeros(max(1, pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)),
                                    dtype=torch.uint8, device=dev)
         self.ws_adj = torch.empty(max(1, pact.sos_to_delays_adjoint_workspace_size(g, N)), dtype=torch.uint8,
                                   device=dev)
@@ -292,15 +328,15 @@ class SirenSolver:
                        out=self.sos)
 
     def delays(self):
-        pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w)
+        pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w,
+                           support=self.support)
 
     def loss_grad(self):
-        pact.loss_and_grad(self.scan.Y, self.w, self.scan.centres, self.g, self.scan.d, self.eps, loss=self.loss,
-                           dL_dw=self.gw, ws=self.ws_loss)
+        self.scan.loss_and_grad(self.w, self.eps, loss=self.loss, dL_dw=self.gw, ws=self.ws_loss)
 
     def adjoint(self):
         pact.sos_to_delays_adjoint(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
-                                   out=self.grad_sos, ws=self.ws_adj)
+                                   out=self.grad_sos, ws=self.ws_adj, support=self.support)
         pact.siren_sos_adjoint(self.params, self.hidden, self.omega0, self.mask, self.g, self.rho, self.grad_sos,
                                out=self.grad, ws=self.ws_net)
 

@@ -137,7 +137,8 @@ def evaluate_scan(net, sim, scan, sos_true, blobs, scale, steps=500, chunk=10, d
     v0 = torch.full((G, G), scan.v0, dtype=torch.float32, device=dev)
     solvers = []
     for _ in range(2):
-        s = PixelGridSolver(sd, mask_np, eps=scan.eps, lam=scan.lam_tv, lr=scan.lr, n_samples=scan.n_samples)
+        s = PixelGridSolver(sd, mask_np, eps=scan.eps, lam=scan.lam_tv, lr=scan.lr, n_samples=scan.n_samples,
+                            support_radius=scan.mask_radius)
         s.step()
         s.capture(chunk)
         solvers.append(s)

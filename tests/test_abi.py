@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(P):
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(P.pact.exported_symbols()) == names
-    assert lib.pact_version() == 1
+    assert lib.pact_version() == 2
 
 
 def test_patch_geometry_matches_oracle(P):
@@ -57,12 +57,16 @@ def test_argument_errors(P):
     ring = pt.Ring(256, 50.0, 0.0)
     img = pt.Grid(128, 128, 0.2)
     sosg = pt.Grid(32, 32, 0.8)
-    s, msg = _status(P, "pact_sos_to_delays", None, sosg, 1.5, FAKE, 49, ring, 256, FAKE, None)
+    s, msg = _status(P, "pact_sos_to_delays", None, sosg, 1.5, FAKE, 49, ring, 256, 0.0, FAKE, None)
     assert s == -1 and "null" in msg
-    s, msg = _status(P, "pact_sos_to_delays", FAKE, sosg, 1.5, FAKE, 49, pt.Ring(0, 50.0, 0.0), 256, FAKE, None)
+    s, msg = _status(P, "pact_sos_to_delays", FAKE, sosg, 1.5, FAKE, 49, pt.Ring(0, 50.0, 0.0), 256, 0.0, FAKE,
+                     None)
     assert s == -1 and "n_elem" in msg
-    s, msg = _status(P, "pact_sos_to_delays", FAKE, pt.Grid(300, 300, 0.1), 1.5, FAKE, 49, ring, 256, FAKE, None)
+    s, msg = _status(P, "pact_sos_to_delays", FAKE, pt.Grid(300, 300, 0.1), 1.5, FAKE, 49, ring, 256, 0.0, FAKE,
+                     None)
     assert s == -4 and "LDS" in msg
+    s, msg = _status(P, "pact_sos_to_delays", FAKE, sosg, 1.5, FAKE, 49, ring, 256, -1.0, FAKE, None)
+    assert s == -1 and "support_radius" in msg
     s, msg = _status(P, "pact_patch_fft", FAKE, 5, img, pt.Patches(120, 8, 1.0), 1, FAKE, None)
     assert s == -4
     s, msg = _status(P, "pact_patch_fft", FAKE, 5, img, pt.Patches(200, 8, 1.0), 1, FAKE, None)
@@ -73,11 +77,11 @@ def test_argument_errors(P):
     s, msg = _status(P, "pact_loss_and_grad", FAKE, FAKE, FAKE, 49, ring, FAKE, 5, 32, 0.2, 1e-6, FAKE, FAKE, None,
                      FAKE, 16, None)
     assert s == -3 and "workspace" in msg
-    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, sosg, 1.5, FAKE, 49, ring, 0, FAKE, None, FAKE, 0,
+    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, sosg, 1.5, FAKE, 49, ring, 0, 0.0, FAKE, None, FAKE, 0,
                      None, 0, None)
     assert s == -1 and "n_samples" in msg
-    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, None, 1.5, FAKE, 49, ring, 256, FAKE, None, FAKE, 0,
-                     None, 0, None)
+    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, None, 1.5, FAKE, 49, ring, 256, 0.0, FAKE, None, FAKE,
+                     0, None, 0, None)
     assert s == -1 and "geometry" in msg
     s, msg = _status(P, "pact_residual_loss", FAKE, FAKE, FAKE, 4, 3, 8, 0.1, FAKE, None, None, FAKE, 0, None)
     assert s == -3
@@ -91,7 +95,8 @@ def test_argument_errors(P):
 
 def test_workspace_sizes(P):
     pt = P.pact
-    assert pt.loss_and_grad_workspace_size(169, 11, 80, 512) == 169 * 13 * (1 + 512) * 4
+    # one workgroup per patch: the patch losses, added in order by a second kernel
+    assert pt.loss_and_grad_workspace_size(169, 11, 80, 512) == 169 * 4
     assert P.pact.load().pact_residual_loss_workspace_size(0, 8) == 0
 
 

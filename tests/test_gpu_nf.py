@@ -228,7 +228,7 @@ def test_nf_step_gradient_matches_oracle_chain(lib):
     want = c.oracle_vjp(c.ov.centres, c.ring, gw_o, bf16=True)
 
     sd = lib.ScanData(c.g, torch.zeros(1, device="cuda"), dev32(c.ov.delays), 1.0, 0.0, c.v0)
-    sd.Y = devc64(Opatch.half_spectrum(Y))
+    sd.use_spectra(devc64(Opatch.half_spectrum(Y)))
     solver = lib.NeuralFieldSolver(sd, c.B32, c.params32, c.net, lr=1e-3, eps=eps, n_samples=40)
     solver.pack()
     solver.delays()

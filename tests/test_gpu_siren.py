@@ -76,7 +76,7 @@ def test_siren_step_gradient_matches_oracle_chain(lib):
 
     from oracle import patches as Opatch
     sd = lib.ScanData(g, torch.zeros(1, device="cuda"), dev32(ov.delays), 1.0, 0.0, ov.v0)
-    sd.Y = devc64(Opatch.half_spectrum(Y))
+    sd.use_spectra(devc64(Opatch.half_spectrum(Y)))
     solver = lib.SirenSolver(sd, mask, p, 256, OMEGA0, rho, lr=5e-3, eps=eps, n_samples=scan.n_samples)
     solver.sos_grid()
     solver.delays()
