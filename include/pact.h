@@ -256,6 +256,18 @@ PACT_API int pact_loss_and_grad_projected(const float* T, const float* w, const 
                                           const pact_ring* ring, int M, int P, float px, float eps, float* loss,
                                           float* dL_dw, float* X_opt, void* ws, size_t ws_bytes, void* stream);
 
+/* pact_loss_and_grad without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, results and limits as pact_loss_and_grad,
+ * bit for bit; the per-patch losses go to a scratch array of 16384 floats that
+ * the library keeps in each GPU's memory until the process ends (so N <= 16384,
+ * else PACT_EUNSUPPORTED).  The array holds the last call's values, and calls
+ * that overlap on one GPU race on it (use one stream, or pact_loss_and_grad with
+ * a workspace each).  Allocates nothing. */
+PACT_API int pact_loss_and_grad_noalloc(const float* Y_half, const float* w, const float* centres, int N,
+                                        const pact_ring* ring, const float* d, int M, int P, float px, float eps,
+                                        float* loss, float* dL_dw, float* X_opt, void* stream);
+
 /* Total-variation term of Eq. jr (reading: anisotropic, over node pairs with at
  * least one free node, subgradient sign(0) = 0):
  *   loss += lambda * TV(sos),  grad += lambda * dTV/dsos  (grad over all nodes).

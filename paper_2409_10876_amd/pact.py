@@ -66,6 +66,7 @@ _SIGS = {
     "pact_projected_spectra_floats": (_Z, [_I, _I]),
     "pact_project_spectra": (_I, [_P, _I, _I, _I, _F, _P, _P, _P]),
     "pact_loss_and_grad_projected": (_I, [_P, _P, _P, _I, _PRING, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
+    "pact_loss_and_grad_noalloc": (_I, [_P, _P, _P, _I, _PRING, _P, _I, _I, _F, _F, _P, _P, _P, _P]),
     "pact_tv_grad": (_I, [_P, _P, _PGRID, _F, _P, _P, _P]),
     "pact_adam_step": (_I, [_P, _P, _P, _P, _P, _I, _P, _F, _F, _F, _F, _P]),
     "pact_stitch": (_I, [_P, _I, _PGRID, _PPATCH, _P, _P]),
@@ -389,6 +390,19 @@ def loss_and_grad_projected(T, M, w, centres, g: Geometry, eps, loss=None, dL_dw
                                                _ptr(dL_dw, F32, "dL_dw", N * g.n_elem) if want_grad else None,
                                                _ptr(X, C64, "X", N * P * P), _ptr(ws, name="ws"), ws.numel(),
                                                _stream()), "pact_loss_and_grad_projected")
+    return loss, dL_dw
+
+
+def loss_and_grad_noalloc(Y_half, w, centres, g: Geometry, d, eps, loss, dL_dw=None, X=None):
+    """pact_loss_and_grad without a workspace (the library's own scratch; allocates nothing, so loss and dL_dw
+    must be given)."""
+    N, M, P, Wh = Y_half.shape
+    assert Wh == P // 2 + 1 and P == g.P
+    _check(load().pact_loss_and_grad_noalloc(_ptr(Y_half, C64, "Y_half"), _ptr(w, F32, "w", N * g.n_elem),
+                                             _ptr(centres, F32, "centres", 2 * N), N, g.ring, _ptr(d, F32, "d", M), M,
+                                             P, g.px, eps, _ptr(loss, F32, "loss", 1),
+                                             _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), _ptr(X, C64, "X", N * P * P),
+                                             _stream()), "pact_loss_and_grad_noalloc")
     return loss, dL_dw
 
 
