@@ -211,7 +211,7 @@ def main():
 
     def job():
         sd.prepare()
-        solver.sos.copy_(sos0)
+        solver.set_sos(sos0)
         solver.m.zero_()
         solver.v.zero_()
         solver.t.zero_()
@@ -256,7 +256,7 @@ def main():
     das_ev[1].record()
     sd.Y = P.pact.patch_fft(sd.stack, sd.geom, half=True, out=sd.Y)
     das_ev[2].record()
-    sd.T = P.pact.project_spectra(sd.Y, sd.geom, sd.d, out=sd.T)
+    sd.T = P.pact.project_spectra(sd.Y, sd.geom, sd.d, sd.centres, out=sd.T)
     das_ev[3].record()
     for r in range(reps):
         for k, fn in stages.items():
@@ -446,12 +446,12 @@ def delay_sweep(P, sd, scan, solver, counts=(4, 8, 11, 16), reps=20):
         ws = torch.empty(max(1, P.pact.loss_and_grad_workspace_size(N, M, g.P, g.n_elem)), dtype=torch.uint8,
                          device=sd.S.device)
         gw = torch.empty_like(solver.w)
-        T = P.pact.project_spectra(Y, g, d)
+        T = P.pact.project_spectra(Y, g, d, sd.centres)
         us_direct = timed(lambda: P.pact.loss_and_grad(Y, solver.w, sd.centres, g, d, solver.eps, dL_dw=gw, ws=ws,
                                                        want_loss=False))
         us_proj = timed(lambda: P.pact.loss_and_grad_projected(T, M, solver.w, sd.centres, g, solver.eps, dL_dw=gw,
                                                                ws=ws, want_loss=False))
-        us_once = timed(lambda: P.pact.project_spectra(Y, g, d, out=T))
+        us_once = timed(lambda: P.pact.project_spectra(Y, g, d, sd.centres, out=T))
         out[str(M)] = {"direct_us": us_direct, "direct_GB_per_s": N * M * g.P * (g.P // 2 + 1) * 8 / (us_direct * 1e-6) / 1e9,
                        "projected_us": us_proj, "project_once_us": us_once}
         del Y, ws, T

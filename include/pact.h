@@ -160,9 +160,26 @@ PACT_API int pact_ifft2_real(const float* X, int B, int P, float* x, void* strea
  * farther than support_radius (1 + 1e-6) from the origin are taken as v0
  * whatever sos holds there, and only the samples that can touch a node inside
  * are evaluated (those within the radius grown by a cell diagonal; the others
- * add exactly zero). */
+ * add exactly zero).
+ * staged (optional, DEVICE, may be NULL): the contrast grid of sos that
+ * pact_stage_contrast makes with the same v0 and support_radius.  Every
+ * workgroup of the ray kernels holds that grid in LDS; given it, they copy it
+ * instead of forming it from sos (same results, bit for bit). */
 PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
-                       const pact_ring* ring, int n_samples, float support_radius, float* w, void* stream);
+                       const pact_ring* ring, int n_samples, float support_radius, const float* staged, float* w,
+                       void* stream);
+
+/* The contrast grid the ray kernels work on: (sosg.ny + 2) x (sosg.nx + 2)
+ * floats, row-major, padded node (r, c) = grid node (r - 1, c - 1) holding
+ * sos - v0 where that node lies in the grid and inside the support disc
+ * (support_radius as for pact_sos_to_delays; 0 = every node), and 0 on every
+ * other node and on the one-node ring around the grid.  staged: DEVICE,
+ * pact_staged_contrast_floats() floats (overwritten).  An optimisation step
+ * forms it once (pact_sos_adjoint_tv_adam_step writes it for the updated SOS)
+ * instead of once per workgroup of each ray kernel. */
+PACT_API size_t pact_staged_contrast_floats(const pact_grid* sosg);
+PACT_API int pact_stage_contrast(const float* sos, const pact_grid* sosg, float v0, float support_radius,
+                                 float* staged, void* stream);
 
 /* Adjoint of pact_sos_to_delays: dL_dsos[a][b] = scale * sum_{i,n} dL_dw[i][n] dw[i][n]/dsos[a][b],
  * with dw/dv = dl v0 / v^2 at every sample spread by the bilinear weights.
@@ -177,12 +194,13 @@ PACT_API int pact_sos_to_delays(const float* sos, const pact_grid* sosg, float v
  * two calls in flight.  The per-workgroup sums are exact integer sums at a
  * fixed-point scale and are combined in a fixed order, so the result is
  * deterministic; a non-finite SOS node, or one at or below zero, makes the
- * result NaN. */
+ * result NaN.  staged (may be NULL) as for pact_sos_to_delays (the tiled form,
+ * used where the adjoint workspace size is 0, reads sos only). */
 PACT_API size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sosg, int N, const pact_ring* ring);
 PACT_API int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg, float v0, const float* centres, int N,
-                               const pact_ring* ring, int n_samples, float support_radius, const float* dL_dw,
-                               const float* scale, float* dL_dsos, int accumulate, void* ws, size_t ws_bytes,
-                               void* stream);
+                               const pact_ring* ring, int n_samples, float support_radius, const float* staged,
+                               const float* dL_dw, const float* scale, float* dL_dsos, int accumulate, void* ws,
+                               size_t ws_bytes, void* stream);
 
 /* Transfer functions, Eq. TF (Sec. 3.1), under the e^{-j k.r} forward transform:
  *   H[i][j](k) = 1/2 (e^{+j|k|(d_j - W_i(th))} + e^{-j|k|(d_j - W_i(th + pi))}),  th = atan2(k_y, k_x),
@@ -241,17 +259,28 @@ PACT_API int pact_loss_and_grad(const float* Y_half, const float* w, const float
  * with phi = -|k| wbar and delta_j = |k| d_j, so the delay sums of the closed
  * form need only five step-invariant values per patch and bin,
  *   Pc = sum_j cos(delta_j) Y_j,  Ps = sum_j sin(delta_j) Y_j  (complex),  S = sum_j |Y_j|^2,
- * and two per bin, C2 = sum_j cos(2 delta_j), S2 = sum_j sin(2 delta_j).
- * pact_project_spectra computes them once per scan (in FP64, stored in FP32)
- * into T, pact_projected_spectra_floats(N, P) floats:
- *   T[(i*5 + c) * nb + bin], c = Pc.re, Pc.im, Ps.re, Ps.im, S;  T[(N*5 + c) * nb + bin], c = C2, S2,
- * nb = P (P/2 + 1), bins in the order of Y_half.  pact_loss_and_grad_projected
- * then reads 20 bytes per patch and bin instead of 8 M, and gives what
- * pact_loss_and_grad gives on Y_half (same arguments, workspace and limits; M is
- * the number of delays the spectra were projected with). */
+ * and two per bin, C2 = sum_j cos(2 delta_j), S2 = sum_j sin(2 delta_j).  The
+ * two points where the line through the patch centre along k meets the ring
+ * (where Eq. TF reads the wavefront table) do not change between steps either.
+ * pact_project_spectra computes all of it once per scan (in FP64, stored in
+ * FP32) into T, pact_projected_spectra_floats(N, P) floats; with nb = P (P/2+1)
+ * half-spectrum bins (in the order of Y_half) and nv = nb + (P even ? P/2 - 1 : 0)
+ * virtual bins (the bins, then the Nyquist-row bins at (-k_x, k_y)):
+ *   T[(i*5 + c) * nb + bin],  c = Pc.re, Pc.im, Ps.re, Ps.im, S;
+ *   T[(N*5 + c) * nb + bin],  c = C2, S2;
+ *   T[(N*5 + 2) * nb + (i*2 + h) * nv + v],  h = 0, 1: the two ring hits of
+ *     patch i as fractional element indices in [0, n_elem];
+ *   T[(N*5 + 2) * nb + (N*2 + c) * nv + v],  c = |k| / (2 pi) in cycles per
+ *     unit length, and |k| times the bin's weight in the half-spectrum sum.
+ * centres [N][2] are the patch centres and ring the array, as for
+ * pact_loss_and_grad.  pact_loss_and_grad_projected then reads 36 bytes per
+ * patch and bin instead of 8 M and needs no ring geometry, and gives what
+ * pact_loss_and_grad gives on Y_half (same arguments, workspace and limits; M
+ * is the number of delays the spectra were projected with, and centres and
+ * ring must be those T was made with). */
 PACT_API size_t pact_projected_spectra_floats(int N, int P);
-PACT_API int pact_project_spectra(const float* Y_half, int N, int M, int P, float px, const float* d, float* T,
-                                  void* stream);
+PACT_API int pact_project_spectra(const float* Y_half, int N, int M, int P, float px, const float* d,
+                                  const float* centres, const pact_ring* ring, float* T, void* stream);
 PACT_API int pact_loss_and_grad_projected(const float* T, const float* w, const float* centres, int N,
                                           const pact_ring* ring, int M, int P, float px, float eps, float* loss,
                                           float* dL_dw, float* X_opt, void* ws, size_t ws_bytes, void* stream);
@@ -304,13 +333,16 @@ PACT_API int pact_tv_adam_step(const float* sos_in, float* sos_out, float* m, fl
  * NULL).  grad (may be NULL) receives the data term's dL/dsos on the free nodes inside the support
  * (0 on the others, whose partials are not read).  Only for grids that take the whole-grid or banded
  * adjoint (pact_sos_to_delays_adjoint_workspace_size() > 0); else PACT_EUNSUPPORTED.  The same
- * results as the three calls, bit for bit, on the free nodes. */
+ * results as the three calls, bit for bit, on the free nodes.  staged_in (may be NULL): the
+ * staged contrast grid of sos_in (pact_stage_contrast); staged_out (may be NULL; not staged_in):
+ * receives that of sos_out, whole, so that the next step's ray calls need not form it. */
 PACT_API int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out, float* m, float* v, int* t,
                                            const unsigned char* mask, const pact_grid* sosg, float v0,
                                            const float* centres, int N, const pact_ring* ring, int n_samples,
-                                           float support_radius, const float* dL_dw, float lambda, float* loss,
-                                           float lr, float b1, float b2, float eps, float* grad, void* ws,
-                                           size_t ws_bytes, void* stream);
+                                           float support_radius, const float* staged_in, float* staged_out,
+                                           const float* dL_dw, float lambda, float* loss, float lr, float b1,
+                                           float b2, float eps, float* grad, void* ws, size_t ws_bytes,
+                                           void* stream);
 
 /* ---- The paper's neural-field SOS: a sinusoidal network on the SOS-grid nodes (Sec. 3.3) ----
  *

@@ -205,6 +205,70 @@ __device__ __forceinline__ void ray_setup(float cx, float cy, float ex, float ey
     }
 }
 
+// The same rows from a staged contrast grid (what stage_kernel writes, [Gy + 2][W]): a plain copy of padded rows
+// R0 .. R0 + H - 1 into vs, four floats a load where the rows start on a 16-byte boundary, each lane's loads all
+// issued before it stores any; acc (if given) cleared; vmin and nan_check as in stage_contrast.
+constexpr int kCopyBatch = 8;     // float4 loads in flight per lane (one pass covers 32768 floats at 1024 lanes)
+
+__device__ __forceinline__ void copy_staged(const float* __restrict__ staged, float v0, const RayGeo& g, float* vs,
+                                            int* acc, int R0, int H, float& vmin, float& nan_check) {
+    const int n = H * g.W;
+    const float* src = staged + static_cast<size_t>(R0) * g.W;
+    const int nt = static_cast<int>(blockDim.x);
+    float dmin = 0.0f;
+    int head = 0;                 // floats copied by the vector loop
+    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        const int n4 = n >> 2;
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+        float4* d4 = reinterpret_cast<float4*>(vs);
+        for (int j0 = threadIdx.x; j0 < n4; j0 += kCopyBatch * nt) {
+            float4 x[kCopyBatch];
+#pragma unroll
+            for (int k = 0; k < kCopyBatch; ++k) {
+                const int j = j0 + k * nt;
+                x[k] = j < n4 ? s4[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int k = 0; k < kCopyBatch; ++k) {
+                const int j = j0 + k * nt;
+                if (j < n4) d4[j] = x[k];
+                dmin = fminf(dmin, fminf(fminf(x[k].x, x[k].y), fminf(x[k].z, x[k].w)));
+                nan_check += 0.0f * ((x[k].x + x[k].y) + (x[k].z + x[k].w));
+            }
+        }
+        head = n4 << 2;
+    }
+    for (int j = head + static_cast<int>(threadIdx.x); j < n; j += nt) {
+        const float d = src[j];
+        vs[j] = d;
+        dmin = fminf(dmin, d);
+        nan_check += 0.0f * d;
+    }
+    vmin = fminf(vmin, v0 + dmin);
+    if (acc) {
+        if ((reinterpret_cast<uintptr_t>(acc) & 15) == 0) {
+            int4* a4 = reinterpret_cast<int4*>(acc);
+            for (int j = threadIdx.x; j < (n >> 2); j += nt) a4[j] = make_int4(0, 0, 0, 0);
+            for (int j = ((n >> 2) << 2) + static_cast<int>(threadIdx.x); j < n; j += nt) acc[j] = 0;
+        } else {
+            for (int j = threadIdx.x; j < n; j += nt) acc[j] = 0;
+        }
+    }
+}
+
+// The staged contrast grid of sos: padded node (r, c) (grid node (r - 1, c - 1)) holds sos - v0 where that node
+// lies in the grid and in the support disc, 0 elsewhere, exactly as stage_contrast forms it.
+__global__ __launch_bounds__(256) void stage_kernel(const float* __restrict__ sos, float v0, RayGeo g,
+                                                    float* __restrict__ staged) {
+    const int H = g.Gy + 2;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= H * g.W) return;
+    const int r = j / g.W, c = j - r * g.W;
+    const int a = r - 1, b = c - 1;
+    const bool in = a >= 0 && a < g.Gy && b >= 0 && b < g.Gx && node_in_support(c, row_y2(r, g), g);
+    staged[j] = in ? sos[a * g.Gx + b] - v0 : 0.0f;
+}
+
 // Cell of sample sf of a ray: flat padded index c of its lower-left node and the fractions (fx, fy) inside
 // it.  With kClamp the cell is clamped into the padded grid whatever the input; without, the caller has
 // checked that it lies there (segment_inside).  The flat index is formed in float (exact: the padded grid
@@ -285,7 +349,8 @@ constexpr int kLenBuckets = 33;
 // their sample counts inside the support (longest first, when the order fits in LDS) and each goes to K adjacent
 // lanes (K a power of two) that take its samples in turn: the lanes of a wave then walk rays of similar length,
 // and the lanes of a ray read neighbouring cells.
-__global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restrict__ sos, float v0,
+__global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restrict__ sos,
+                                                            const float* __restrict__ staged, float v0,
                                                             const float* __restrict__ centres, int N, int n_elem,
                                                             float R, float phi0, int Ns, RayGeo g, int log2K,
                                                             int n_rays, int per_block, int sorted,
@@ -299,7 +364,10 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
     for (int k = tid; k < kLenBuckets; k += blockDim.x) hist[k] = 0;
     {
         float vmin = v0, nan_check = 0.0f;   // not used by the forward
-        stage_contrast<kStageRows>(sos, v0, g, vs, nullptr, 0, g.Gy + 2, vmin, nan_check);
+        if (staged)
+            copy_staged(staged, v0, g, vs, nullptr, 0, g.Gy + 2, vmin, nan_check);
+        else
+            stage_contrast<kStageRows>(sos, v0, g, vs, nullptr, 0, g.Gy + 2, vmin, nan_check);
     }
     const int r0 = blockIdx.x * per_block;
     const int n_loc = max(min(per_block, n_rays - r0), 0);
@@ -596,6 +664,10 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
 // a reduce kernel adds the partial grids in a fixed order.
 constexpr int kGridThreads = 1024;
 
+// Floats per partial grid: the node count rounded up to 64, so that every partial, and every run of 64 nodes in
+// it, starts on a 256-byte boundary (a wave's row of loads is then two whole cache lines).
+__host__ __device__ inline int partial_pitch(int ny, int nx) { return (ny * nx + 63) & ~63; }
+
 // Adjoint shares of samples s0 .. s1 - 1 (s1 > s0) of one ray, added into the fixed-point accumulator acc
 // (same layout as vs).  Consecutive samples in the same cell add into registers; a cell's four shares go to
 // LDS once, when the walk leaves it (truncation toward zero: at most one unit of 2^-30 of the bound per
@@ -680,9 +752,10 @@ __device__ __forceinline__ void band_samples(int s0, int s1, float gy0, float dg
 // outside a workgroup's rows) are summed as before.
 template <bool kBanded>
 __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
-    const float* __restrict__ sos, float v0, const float* __restrict__ centres, int N, int n_elem, float R, float phi0,
-    int Ns, RayGeo g, int n_rays, int per_block, int K, int sorted, int n_bands, int band_rows,
-    const float* __restrict__ dL_dw, const float* __restrict__ scale, float* __restrict__ partial) {
+    const float* __restrict__ sos, const float* __restrict__ staged, float v0, const float* __restrict__ centres,
+    int N, int n_elem, float R, float phi0, int Ns, RayGeo g, int n_rays, int per_block, int K, int sorted,
+    int n_bands, int band_rows, const float* __restrict__ dL_dw, const float* __restrict__ scale,
+    float* __restrict__ partial) {
     extern __shared__ float lds[];
     const int W = g.W;
     const int band = kBanded ? static_cast<int>(blockIdx.x) % n_bands : 0;
@@ -695,7 +768,10 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     float* red = reinterpret_cast<float*>(acc + total);     // kGridThreads / 64 floats
     const int tid = threadIdx.x;
     float vmin = v0, nan_check = 0.0f;                     // nan_check turns NaN if any node is not finite
-    stage_contrast<kStageRows>(sos, v0, g, vs, acc, R0, R1 - R0 + 1, vmin, nan_check);
+    if (staged)
+        copy_staged(staged, v0, g, vs, acc, R0, R1 - R0 + 1, vmin, nan_check);
+    else
+        stage_contrast<kStageRows>(sos, v0, g, vs, acc, R0, R1 - R0 + 1, vmin, nan_check);
     vmin = -block_max(-vmin, red);
     const int r0 = bblock * per_block;                      // this workgroup's rays r0 .. r1 - 1 (element-major)
     const int r1 = min(r0 + per_block, n_rays);
@@ -780,7 +856,7 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     __syncthreads();
     const float invF = 1.0f / F;
     const float bad = __builtin_nanf("");
-    float* part = partial + static_cast<size_t>(blockIdx.x) * g.Gy * g.Gx;
+    float* part = partial + static_cast<size_t>(blockIdx.x) * partial_pitch(g.Gy, g.Gx);
     // rows per wave and columns per lane, as in the staging; grid row a is padded row a + 1, held in this
     // workgroup's rows when R0 <= a + 1 <= R1 (zero otherwise)
     {
@@ -806,12 +882,11 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
 constexpr int kAdjSlices = 16;
 
 // Run `slice` of the kAdjSlices contiguous runs of the n_part partials at one node, added in order.
-__device__ __forceinline__ float adj_run_sum(const float* __restrict__ partial, int n_part, int n_nodes, int node,
+__device__ __forceinline__ float adj_run_sum(const float* __restrict__ partial, int n_part, int pitch, int node,
                                              int slice) {
     const int per = (n_part + kAdjSlices - 1) / kAdjSlices;
     const int p0 = slice * per, p1 = min(p0 + per, n_part);
-    return p1 > p0 ? ordered_strided_sum<16>(partial + static_cast<size_t>(p0) * n_nodes + node, p1 - p0,
-                                                   n_nodes)
+    return p1 > p0 ? ordered_strided_sum<16>(partial + static_cast<size_t>(p0) * pitch + node, p1 - p0, pitch)
                    : 0.0f;
 }
 
@@ -830,7 +905,7 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_ker
     const int j = threadIdx.x % kReduceNodes, slice = threadIdx.x / kReduceNodes;
     const int node = blockIdx.x * kReduceNodes + j;
     run[slice][j] = node < n_nodes && grid_node_in_support(node, g)
-                        ? adj_run_sum(partial, n_part, n_nodes, node, slice) : 0.0f;
+                        ? adj_run_sum(partial, n_part, partial_pitch(g.Gy, g.Gx), node, slice) : 0.0f;
     __syncthreads();
     if (slice == 0 && node < n_nodes) {
         float t = 0.0f;
@@ -849,7 +924,7 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void adj_reduce_tv_adam_
     const float* __restrict__ partial, int n_part, RayGeo g, const float* __restrict__ sos_in,
     float* __restrict__ sos_out, float* __restrict__ m, float* __restrict__ v, int* __restrict__ t,
     const unsigned char* __restrict__ mask, float lambda, float* __restrict__ loss, float lr, float b1, float b2,
-    float eps, float* __restrict__ grad_out) {
+    float eps, float* __restrict__ grad_out, float v0, float* __restrict__ staged_out) {
     __shared__ float run[kAdjSlices][kReduceNodes];
     __shared__ float red[kAdjSlices * kReduceNodes / 64];
     const int step = t[0] + 1;
@@ -869,8 +944,8 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void adj_reduce_tv_adam_
         if (lambda != 0.0f) tv_node(sos_in, mask, nd, a, b, g.Gy, g.Gx, tv, g_tv);
         if (!valid) tv = 0.0f;
     }
-    run[slice][j] = is_free && grid_node_in_support(node, g) ? adj_run_sum(partial, n_part, n_nodes, node, slice)
-                                                             : 0.0f;
+    run[slice][j] = is_free && grid_node_in_support(node, g)
+                        ? adj_run_sum(partial, n_part, partial_pitch(g.Gy, g.Gx), node, slice) : 0.0f;
     __syncthreads();
     if (slice == 0 && valid) {
         float gd = 0.0f;
@@ -883,6 +958,26 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void adj_reduce_tv_adam_
             v[node] = vv;
         }
         sos_out[node] = p;
+        if (staged_out) {
+            // the staged contrast of sos_out (as stage_kernel forms it), with the ring of zeros next to the
+            // grid's edge nodes
+            const int W = g.W;
+            float* row = staged_out + static_cast<size_t>(a + 1) * W;
+            row[b + 1] = node_in_support(b + 1, row_y2(a + 1, g), g) ? p - v0 : 0.0f;
+            if (b == 0) row[0] = 0.0f;
+            if (b == g.Gx - 1) row[W - 1] = 0.0f;
+            if (a == 0) {
+                staged_out[b + 1] = 0.0f;
+                if (b == 0) staged_out[0] = 0.0f;
+                if (b == g.Gx - 1) staged_out[W - 1] = 0.0f;
+            }
+            if (a == g.Gy - 1) {
+                float* last = staged_out + static_cast<size_t>(g.Gy + 1) * W;
+                last[b + 1] = 0.0f;
+                if (b == 0) last[0] = 0.0f;
+                if (b == g.Gx - 1) last[W - 1] = 0.0f;
+            }
+        }
     }
     if (loss) {
         tv = block_sum(tv, red);
@@ -961,8 +1056,8 @@ int fwd_lanes_rule(int per_block, int n_samples) {
 }  // namespace pact
 
 extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, float v0, const float* centres, int N,
-                                  const pact_ring* ring_, int n_samples, float support_radius, float* w,
-                                  void* stream) {
+                                  const pact_ring* ring_, int n_samples, float support_radius, const float* staged,
+                                  float* w, void* stream) {
     if (!sosg_ || !ring_) {
         pact::set_error("pact_sos_to_delays: null geometry pointer");
         return PACT_EINVAL;
@@ -1000,7 +1095,7 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
     const size_t with_order = base + static_cast<size_t>(per_block) * sizeof(int);
     const int sorted = with_order <= kLdsBytes ? 1 : 0;
     rays_fwd_kernel<<<blocks, kThreads, sorted ? with_order : base, as_stream(stream)>>>(
-        sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support_radius),
+        sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support_radius),
         log2K, static_cast<int>(n_rays), per_block, sorted, w);
     return launch_status("pact_sos_to_delays");
 }
@@ -1031,14 +1126,14 @@ AdjPlan adj_plan(const pact_grid& sosg) {
 size_t adj_grid_lds(const pact_grid& sosg) { return adj_plan(sosg).bands ? adj_plan(sosg).lds : 0; }
 
 // The grid adjoint into one partial node grid per workgroup (the caller sums them); *n_part = their count.
-int launch_adj_grid(const float* sos, const pact_grid& sosg, float v0, const float* centres, int N,
+int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg, float v0, const float* centres, int N,
                     const pact_ring& ring, int n_samples, float support, const float* dL_dw, const float* scale,
                     float* partial, size_t ws_bytes, hipStream_t st, int* n_part, const char* what) {
     const AdjPlan plan = adj_plan(sosg);
     const int cus = device_cu_count();
     const int per_band = std::max(1, cus / plan.bands);           // workgroups per band
     const int blocks = plan.bands * per_band;
-    const size_t need = static_cast<size_t>(blocks) * sosg.ny * sosg.nx * sizeof(float);
+    const size_t need = static_cast<size_t>(blocks) * partial_pitch(sosg.ny, sosg.nx) * sizeof(float);
     if (!partial || ws_bytes < need) {
         set_error("%s: workspace of %zu bytes needed, %zu given", what, need, partial ? ws_bytes : 0);
         return PACT_EWORKSPACE;
@@ -1063,11 +1158,11 @@ int launch_adj_grid(const float* sos, const pact_grid& sosg, float v0, const flo
     const size_t lds = plan.lds + (sorted ? order_bytes : 0);
     if (plan.bands == 1)
         rays_adj_grid_kernel<false><<<blocks, kGridThreads, lds, st>>>(
-            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
+            sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
             static_cast<int>(n_rays), per_block, K, sorted, 1, sosg.ny + 1, dL_dw, scale, partial);
     else
         rays_adj_grid_kernel<true><<<blocks, kGridThreads, lds, st>>>(
-            sos, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
+            sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
             static_cast<int>(n_rays), per_block, K, sorted, plan.bands, plan.band_rows, dL_dw, scale, partial);
     *n_part = blocks;
     return launch_status(what);
@@ -1083,12 +1178,12 @@ extern "C" size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sos
     const pact::AdjPlan plan = pact::adj_plan(*sosg_);
     if (!plan.bands) return 0;
     const int blocks = plan.bands * std::max(1, pact::device_cu_count() / plan.bands);
-    return static_cast<size_t>(blocks) * sosg_->ny * sosg_->nx * sizeof(float);
+    return static_cast<size_t>(blocks) * pact::partial_pitch(sosg_->ny, sosg_->nx) * sizeof(float);
 }
 
 extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sosg_, float v0, const float* centres,
                                           int N, const pact_ring* ring_, int n_samples, float support_radius,
-                                          const float* dL_dw, const float* scale, float* dL_dsos, int accumulate,
+                                          const float* staged, const float* dL_dw, const float* scale, float* dL_dsos, int accumulate,
                                           void* ws, size_t ws_bytes, void* stream) {
     if (!sosg_ || !ring_) {
         pact::set_error("pact_sos_to_delays_adjoint: null geometry pointer");
@@ -1104,7 +1199,7 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     if (adj_grid_lds(sosg)) {
         float* partial = static_cast<float*>(ws);
         int n_part = 0;
-        if (int st = launch_adj_grid(sos, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, scale, partial,
+        if (int st = launch_adj_grid(sos, staged, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, scale, partial,
                                      ws_bytes, as_stream(stream), &n_part, "pact_sos_to_delays_adjoint"))
             return st;
         const int n_nodes = sosg.ny * sosg.nx;
@@ -1135,9 +1230,10 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
 extern "C" int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out, float* m, float* v, int* t,
                                              const unsigned char* mask, const pact_grid* sosg_, float v0,
                                              const float* centres, int N, const pact_ring* ring_, int n_samples,
-                                             float support_radius, const float* dL_dw, float lambda, float* loss,
-                                             float lr, float b1, float b2, float eps, float* grad, void* ws,
-                                             size_t ws_bytes, void* stream) {
+                                             float support_radius, const float* staged_in, float* staged_out,
+                                             const float* dL_dw, float lambda, float* loss, float lr, float b1,
+                                             float b2, float eps, float* grad, void* ws, size_t ws_bytes,
+                                             void* stream) {
     if (!sosg_ || !ring_) {
         pact::set_error("pact_sos_adjoint_tv_adam_step: null geometry pointer");
         return PACT_EINVAL;
@@ -1157,13 +1253,15 @@ extern "C" int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out
                          "pact_sos_to_delays_adjoint and pact_tv_adam_step", what, sosg.ny, sosg.nx);
     float* partial = static_cast<float*>(ws);
     int n_part = 0;
-    if (int st = launch_adj_grid(sos_in, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, nullptr,
+    PACT_CHECK_ARG(!staged_out || (staged_out != staged_in && static_cast<const float*>(staged_out) != sos_in),
+                   "%s: staged_out must not alias staged_in or sos_in", what);
+    if (int st = launch_adj_grid(sos_in, staged_in, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, nullptr,
                                  partial, ws_bytes, as_stream(stream), &n_part, what))
         return st;
     const int n_nodes = sosg.ny * sosg.nx;
     adj_reduce_tv_adam_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(
         partial, n_part, make_geo(sosg, n_samples, support_radius), sos_in, sos_out, m, v, t, mask, lambda, loss, lr,
-        b1, b2, eps, grad);
+        b1, b2, eps, grad, v0, staged_out);
     return launch_status(what);
 }
 
@@ -1240,7 +1338,7 @@ extern "C" int pact_rays_autotune(const float* sos, const pact_grid* sosg_, floa
         set_tiling(N, ring, n_samples, sosg, support_radius, RayTiling{K});
         int status = PACT_OK;
         const float ms = time_ms([&] { return pact_sos_to_delays(sos, &sosg, v0, centres, N, &ring, n_samples,
-                                                                 support_radius, w, stream); }, st, reps, status);
+                                                                 support_radius, nullptr, w, stream); }, st, reps, status);
         if (ms < 0.0f) {
             set_tiling(N, ring, n_samples, sosg, support_radius, RayTiling());
             if (status == PACT_EHIP) set_error("pact_rays_autotune: timing events failed");
@@ -1257,4 +1355,25 @@ extern "C" int pact_rays_autotune(const float* sos, const pact_grid* sosg_, floa
         tiling[1] = 0;
     }
     return PACT_OK;
+}
+
+extern "C" size_t pact_staged_contrast_floats(const pact_grid* sosg) {
+    if (!sosg || sosg->ny <= 0 || sosg->nx <= 0) return 0;
+    return static_cast<size_t>(sosg->ny + 2) * (sosg->nx + 2);
+}
+
+extern "C" int pact_stage_contrast(const float* sos, const pact_grid* sosg_, float v0, float support_radius,
+                                   float* staged, void* stream) {
+    using namespace pact;
+    clear_error();
+    PACT_CHECK_ARG(sosg_, "pact_stage_contrast: null geometry pointer");
+    const pact_grid sosg = *sosg_;
+    PACT_CHECK_ARG(sos && staged, "pact_stage_contrast: null pointer");
+    if (int s = check_grid(sosg, "pact_stage_contrast")) return s;
+    PACT_CHECK_ARG(v0 > 0.0f && std::isfinite(v0), "pact_stage_contrast: v0 must be positive");
+    PACT_CHECK_ARG(support_radius >= 0.0f && std::isfinite(support_radius),
+                   "pact_stage_contrast: support_radius must be >= 0");
+    const long long n = static_cast<long long>(sosg.ny + 2) * (sosg.nx + 2);
+    stage_kernel<<<ceil_div(n, 256), 256, 0, as_stream(stream)>>>(sos, v0, make_geo(sosg, 1, support_radius), staged);
+    return launch_status("pact_stage_contrast");
 }

@@ -52,9 +52,11 @@ _SIGS = {
     "pact_das_stack": (_I, [_P, _I, _F, _F, _PRING, _F, _P, _I, _PGRID, _P, _P]),
     "pact_patch_fft": (_I, [_P, _I, _PGRID, _PPATCH, _I, _P, _P]),
     "pact_ifft2_real": (_I, [_P, _I, _I, _P, _P]),
-    "pact_sos_to_delays": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _P]),
+    "pact_sos_to_delays": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _P, _P]),
+    "pact_staged_contrast_floats": (_Z, [_PGRID]),
+    "pact_stage_contrast": (_I, [_P, _PGRID, _F, _F, _P, _P]),
     "pact_sos_to_delays_adjoint_workspace_size": (_Z, [_PGRID, _I, _PRING]),
-    "pact_sos_to_delays_adjoint": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _P, _P, _I, _P, _Z, _P]),
+    "pact_sos_to_delays_adjoint": (_I, [_P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _P, _P, _P, _I, _P, _Z, _P]),
     "pact_delays_to_psf": (_I, [_P, _P, _I, _PRING, _P, _I, _I, _F, _P, _P, _P]),
     "pact_delays_to_psf_adjoint": (_I, [_P, _P, _I, _PRING, _P, _I, _I, _F, _P, _P, _P]),
     "pact_multichannel_deconv": (_I, [_P, _P, _I, _I, _I, _F, _P, _P]),
@@ -64,7 +66,7 @@ _SIGS = {
     "pact_loss_and_grad_workspace_size": (_Z, [_I, _I, _I, _I]),
     "pact_loss_and_grad": (_I, [_P, _P, _P, _I, _PRING, _P, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
     "pact_projected_spectra_floats": (_Z, [_I, _I]),
-    "pact_project_spectra": (_I, [_P, _I, _I, _I, _F, _P, _P, _P]),
+    "pact_project_spectra": (_I, [_P, _I, _I, _I, _F, _P, _P, _PRING, _P, _P]),
     "pact_loss_and_grad_projected": (_I, [_P, _P, _P, _I, _PRING, _I, _I, _F, _F, _P, _P, _P, _P, _Z, _P]),
     "pact_loss_and_grad_noalloc": (_I, [_P, _P, _P, _I, _PRING, _P, _I, _I, _F, _F, _P, _P, _P, _P]),
     "pact_tv_grad": (_I, [_P, _P, _PGRID, _F, _P, _P, _P]),
@@ -74,8 +76,8 @@ _SIGS = {
     "pact_siren_sos_adjoint_workspace_size": (_Z, [_PGRID, _I]),
     "pact_siren_sos_adjoint": (_I, [_P, _I, _F, _P, _PGRID, _F, _P, _P, _P, _Z, _P]),
     "pact_tv_adam_step": (_I, [_P, _P, _P, _P, _P, _P, _PGRID, _P, _F, _P, _F, _F, _F, _F, _P]),
-    "pact_sos_adjoint_tv_adam_step": (_I, [_P, _P, _P, _P, _P, _P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _F, _P,
-                                           _F, _F, _F, _F, _P, _P, _Z, _P]),
+    "pact_sos_adjoint_tv_adam_step": (_I, [_P, _P, _P, _P, _P, _P, _PGRID, _F, _P, _I, _PRING, _I, _F, _P, _P, _P,
+                                           _F, _P, _F, _F, _F, _F, _P, _P, _Z, _P]),
     "pact_nf_param_count": (_Z, [_I, _I]),
     "pact_nf_packed_count": (_Z, [_I, _I]),
     "pact_nf_pack": (_I, [_P, _I, _I, _P, _P]),
@@ -234,13 +236,29 @@ def ifft2_real(X, out=None):
     return out
 
 
-def sos_to_delays(sos, g: Geometry, v0, centres, n_samples, out=None, support=0.0):
-    """support: radius (mm) of the circular mask outside which the SOS is v0 (0: none); see include/pact.h."""
+def sos_to_delays(sos, g: Geometry, v0, centres, n_samples, out=None, support=0.0, staged=None):
+    """support: radius (mm) of the circular mask outside which the SOS is v0 (0: none); staged: the staged
+    contrast grid of sos (stage_contrast) or None; see include/pact.h."""
     N = centres.shape[0]
     out = torch.empty(N, g.n_elem, dtype=F32, device=sos.device) if out is None else out
     _check(load().pact_sos_to_delays(_ptr(sos, F32, "sos", g.sos_ny * g.sos_nx), g.sosg, v0,
                                      _ptr(centres, F32, "centres", 2 * N), N, g.ring, n_samples, float(support),
+                                     _ptr(staged, F32, "staged", staged_contrast_floats(g)),
                                      _ptr(out, F32, "w", N * g.n_elem), _stream()), "pact_sos_to_delays")
+    return out
+
+
+def staged_contrast_floats(g: Geometry) -> int:
+    return int(load().pact_staged_contrast_floats(g.sosg))
+
+
+def stage_contrast(sos, g: Geometry, v0, support=0.0, out=None):
+    """The contrast grid the ray kernels hold in LDS, formed once (see include/pact.h): float
+    [(sos_ny + 2) (sos_nx + 2)]."""
+    n = staged_contrast_floats(g)
+    out = torch.empty(n, dtype=F32, device=sos.device) if out is None else out
+    _check(load().pact_stage_contrast(_ptr(sos, F32, "sos", g.sos_ny * g.sos_nx), g.sosg, v0, float(support),
+                                      _ptr(out, F32, "staged", n), _stream()), "pact_stage_contrast")
     return out
 
 
@@ -249,14 +267,15 @@ def sos_to_delays_adjoint_workspace_size(g: Geometry, N: int) -> int:
 
 
 def sos_to_delays_adjoint(sos, g: Geometry, v0, centres, n_samples, dL_dw, out=None, scale=None, accumulate=False,
-                          ws=None, support=0.0):
+                          ws=None, support=0.0, staged=None):
     N = centres.shape[0]
     out = torch.empty(g.sos_ny, g.sos_nx, dtype=F32, device=sos.device) if out is None else out
     need = sos_to_delays_adjoint_workspace_size(g, N)
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=sos.device) if ws is None else ws
     _check(load().pact_sos_to_delays_adjoint(
         _ptr(sos, F32, "sos", g.sos_ny * g.sos_nx), g.sosg, v0, _ptr(centres, F32, "centres", 2 * N), N, g.ring,
-        n_samples, float(support), _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), _ptr(scale, F32, "scale", 1),
+        n_samples, float(support), _ptr(staged, F32, "staged", staged_contrast_floats(g)),
+        _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), _ptr(scale, F32, "scale", 1),
         _ptr(out, F32, "dL_dsos", g.sos_ny * g.sos_nx), int(accumulate), _ptr(ws, name="ws"), ws.numel(),
         _stream()), "pact_sos_to_delays_adjoint")
     return out
@@ -361,14 +380,16 @@ def loss_and_grad(Y_half, w, centres, g: Geometry, d, eps, loss=None, dL_dw=None
     return loss, dL_dw
 
 
-def project_spectra(Y_half, g: Geometry, d, out=None):
-    """Step-invariant projections of the half spectra (see include/pact.h): float [(5 N + 2) P (P/2 + 1)]."""
+def project_spectra(Y_half, g: Geometry, d, centres, out=None):
+    """Step-invariant projections of the half spectra and the ring hits of every patch and bin (see
+    include/pact.h): float [pact_projected_spectra_floats(N, P)]."""
     N, M, P, Wh = Y_half.shape
     assert Wh == P // 2 + 1 and P == g.P
     n = int(load().pact_projected_spectra_floats(N, P))
     out = torch.empty(n, dtype=F32, device=Y_half.device) if out is None else out
     _check(load().pact_project_spectra(_ptr(Y_half, C64, "Y_half"), N, M, P, g.px, _ptr(d, F32, "d", M),
-                                       _ptr(out, F32, "T", n), _stream()), "pact_project_spectra")
+                                       _ptr(centres, F32, "centres", 2 * N), g.ring, _ptr(out, F32, "T", n),
+                                       _stream()), "pact_project_spectra")
     return out
 
 
@@ -462,7 +483,8 @@ def tv_adam_step(sos_in, sos_out, m, v, t, mask, g: Geometry, grad, lam, loss, l
 
 
 def sos_adjoint_tv_adam_step(sos_in, sos_out, m, v, t, mask, g: Geometry, v0, centres, n_samples, dL_dw, lam, loss,
-                             lr, b1=0.9, b2=0.999, eps=1e-8, support=0.0, grad=None, ws=None):
+                             lr, b1=0.9, b2=0.999, eps=1e-8, support=0.0, grad=None, ws=None, staged_in=None,
+                             staged_out=None):
     """Ray adjoint, TV and Adam in two launches (see include/pact.h); loss None: no TV value added."""
     N = centres.shape[0]
     n = g.sos_ny * g.sos_nx
@@ -471,8 +493,10 @@ def sos_adjoint_tv_adam_step(sos_in, sos_out, m, v, t, mask, g: Geometry, v0, ce
     _check(load().pact_sos_adjoint_tv_adam_step(
         _ptr(sos_in, F32, "sos_in", n), _ptr(sos_out, F32, "sos_out", n), _ptr(m, F32, "m", n), _ptr(v, F32, "v", n),
         _ptr(t, I32, "t", 2), _ptr(mask, U8, "mask", n), g.sosg, v0, _ptr(centres, F32, "centres", 2 * N), N, g.ring,
-        n_samples, float(support), _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), lam, _ptr(loss, F32, "loss", 1), lr, b1,
-        b2, eps, _ptr(grad, F32, "grad", n), _ptr(ws, name="ws"), ws.numel(), _stream()),
+        n_samples, float(support), _ptr(staged_in, F32, "staged_in", staged_contrast_floats(g)),
+        _ptr(staged_out, F32, "staged_out", staged_contrast_floats(g)), _ptr(dL_dw, F32, "dL_dw", N * g.n_elem), lam,
+        _ptr(loss, F32, "loss", 1), lr, b1, b2, eps, _ptr(grad, F32, "grad", n), _ptr(ws, name="ws"), ws.numel(),
+        _stream()),
         "pact_sos_adjoint_tv_adam_step")
     return sos_out
 

@@ -49,13 +49,13 @@ class ScanData:
         """DAS stack, windowed half spectra and their step-invariant projections (once per scan)."""
         self.stack = pact.das_stack(self.S, self.fs, self.t0, self.geom, self.v0, self.d, out=self.stack)
         self.Y = pact.patch_fft(self.stack, self.geom, half=True, out=self.Y)
-        self.T = pact.project_spectra(self.Y, self.geom, self.d, out=self.T)
+        self.T = pact.project_spectra(self.Y, self.geom, self.d, self.centres, out=self.T)
         return self.Y
 
     def use_spectra(self, Y):
         """Take given half spectra [N][M][P][P/2+1] (instead of the DAS stack's) and project them."""
         self.Y = Y
-        self.T = pact.project_spectra(Y, self.geom, self.d)
+        self.T = pact.project_spectra(Y, self.geom, self.d, self.centres)
         return self
 
     def loss_and_grad(self, w, eps, **kw):
@@ -92,9 +92,13 @@ class PixelGridSolver:
         else:
             sos = torch.as_tensor(sos_init, dtype=F32).to(dev).clone()
         sos = torch.where(self.mask.bool(), sos, torch.full_like(sos, v0))
-        # two SOS buffers: the fused TV + Adam update reads one and writes the other
+        # two SOS buffers: the fused TV + Adam update reads one and writes the other; beside each, the staged
+        # contrast grid of its SOS that the ray kernels copy (the fused update writes the next one)
         self._bufs = [sos.contiguous(), torch.empty_like(sos)]
+        ns = pact.staged_contrast_floats(g)
+        self._staged = [torch.empty(ns, dtype=F32, device=dev), torch.empty(ns, dtype=F32, device=dev)]
         self._cur = 0
+        self._restage()
         self._graph_cur0 = 0
         self.m = torch.zeros_like(self.sos)
         self.v = torch.zeros_like(self.sos)
@@ -114,13 +118,23 @@ class PixelGridSolver:
 
     @property
     def sos(self) -> torch.Tensor:
-        """The current SOS node grid."""
+        """The current SOS node grid (read only: set it with set_sos)."""
         return self._bufs[self._cur]
+
+    def set_sos(self, sos):
+        """Replace the current SOS node grid (fixed nodes keep v0)."""
+        v0 = self.scan.v0
+        sos = torch.as_tensor(sos, dtype=F32).to(self.sos.device)
+        self.sos.copy_(torch.where(self.mask.bool(), sos, torch.full_like(sos, v0)))
+        self._restage()
+
+    def _restage(self):
+        pact.stage_contrast(self.sos, self.g, self.scan.v0, self.support, out=self._staged[self._cur])
 
     # one optimisation step (a2 -> a8), enqueued on the current stream
     def delays(self):
         pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w,
-                           support=self.support)
+                           support=self.support, staged=self._staged[self._cur])
 
     def loss_grad(self, with_loss=True):
         """with_loss False: only dL/dw (the scalar loss is formed on the steps whose loss is read)."""
@@ -128,7 +142,8 @@ class PixelGridSolver:
 
     def adjoint(self):
         pact.sos_to_delays_adjoint(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
-                                   out=self.grad, ws=self.ws_adj, support=self.support)
+                                   out=self.grad, ws=self.ws_adj, support=self.support,
+                                   staged=self._staged[self._cur])
 
     def regularise(self):
         """TV value and subgradient added to loss and grad (the separate form of the fused update)."""
@@ -139,6 +154,7 @@ class PixelGridSolver:
         """Adam in place with grad as it stands (the separate form of the fused update)."""
         pact.adam_step(self.sos, self.m, self.v, self.t, self.mask, self.grad, self.lr, self.b1, self.b2,
                        self.adam_eps)
+        self._restage()
 
     def tv_update(self, with_loss=True):
         """TV and Adam in one kernel, from the current buffer into the other one."""
@@ -146,6 +162,7 @@ class PixelGridSolver:
                           self.g, self.grad, self.lam, self.loss if with_loss else None, self.lr, self.b1, self.b2,
                           self.adam_eps)
         self._cur = 1 - self._cur
+        self._restage()
 
     def adjoint_update(self, with_loss=True):
         """Ray adjoint, TV and Adam: two launches where the grid takes the whole-grid or banded adjoint (the
@@ -154,7 +171,8 @@ class PixelGridSolver:
             pact.sos_adjoint_tv_adam_step(self._bufs[self._cur], self._bufs[1 - self._cur], self.m, self.v, self.t,
                                           self.mask, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
                                           self.lam, self.loss if with_loss else None, self.lr, self.b1, self.b2,
-                                          self.adam_eps, support=self.support, grad=self.grad, ws=self.ws_adj)
+                                          self.adam_eps, support=self.support, grad=self.grad, ws=self.ws_adj,
+                                          staged_in=self._staged[self._cur], staged_out=self._staged[1 - self._cur])
             self._cur = 1 - self._cur
         else:
             self.adjoint()
@@ -198,6 +216,7 @@ class PixelGridSolver:
         if self.graph is not None and steps % self.graph_steps == 0:
             if self._cur != self._graph_cur0:         # an odd number of eager steps since the capture
                 self._bufs[self._graph_cur0].copy_(self.sos)
+                self._staged[self._graph_cur0].copy_(self._staged[self._cur])
                 self._cur = self._graph_cur0
             for _ in range(steps // self.graph_steps):
                 self.graph.replay()

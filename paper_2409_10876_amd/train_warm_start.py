@@ -108,7 +108,7 @@ def validate(net, X, T, mask, n_free, batch):
 
 
 def _reset(solver, sos_init):
-    solver.sos.copy_(sos_init)
+    solver.set_sos(sos_init)
     solver.m.zero_()
     solver.v.zero_()
     solver.t.zero_()

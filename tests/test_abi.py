@@ -57,15 +57,15 @@ def test_argument_errors(P):
     ring = pt.Ring(256, 50.0, 0.0)
     img = pt.Grid(128, 128, 0.2)
     sosg = pt.Grid(32, 32, 0.8)
-    s, msg = _status(P, "pact_sos_to_delays", None, sosg, 1.5, FAKE, 49, ring, 256, 0.0, FAKE, None)
+    s, msg = _status(P, "pact_sos_to_delays", None, sosg, 1.5, FAKE, 49, ring, 256, 0.0, None, FAKE, None)
     assert s == -1 and "null" in msg
-    s, msg = _status(P, "pact_sos_to_delays", FAKE, sosg, 1.5, FAKE, 49, pt.Ring(0, 50.0, 0.0), 256, 0.0, FAKE,
-                     None)
+    s, msg = _status(P, "pact_sos_to_delays", FAKE, sosg, 1.5, FAKE, 49, pt.Ring(0, 50.0, 0.0), 256, 0.0, None,
+                     FAKE, None)
     assert s == -1 and "n_elem" in msg
-    s, msg = _status(P, "pact_sos_to_delays", FAKE, pt.Grid(300, 300, 0.1), 1.5, FAKE, 49, ring, 256, 0.0, FAKE,
-                     None)
+    s, msg = _status(P, "pact_sos_to_delays", FAKE, pt.Grid(300, 300, 0.1), 1.5, FAKE, 49, ring, 256, 0.0, None,
+                     FAKE, None)
     assert s == -4 and "LDS" in msg
-    s, msg = _status(P, "pact_sos_to_delays", FAKE, sosg, 1.5, FAKE, 49, ring, 256, -1.0, FAKE, None)
+    s, msg = _status(P, "pact_sos_to_delays", FAKE, sosg, 1.5, FAKE, 49, ring, 256, -1.0, None, FAKE, None)
     assert s == -1 and "support_radius" in msg
     s, msg = _status(P, "pact_patch_fft", FAKE, 5, img, pt.Patches(120, 8, 1.0), 1, FAKE, None)
     assert s == -4
@@ -77,11 +77,11 @@ def test_argument_errors(P):
     s, msg = _status(P, "pact_loss_and_grad", FAKE, FAKE, FAKE, 49, ring, FAKE, 5, 32, 0.2, 1e-6, FAKE, FAKE, None,
                      FAKE, 16, None)
     assert s == -3 and "workspace" in msg
-    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, sosg, 1.5, FAKE, 49, ring, 0, 0.0, FAKE, None, FAKE, 0,
-                     None, 0, None)
+    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, sosg, 1.5, FAKE, 49, ring, 0, 0.0, None, FAKE, None,
+                     FAKE, 0, None, 0, None)
     assert s == -1 and "n_samples" in msg
-    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, None, 1.5, FAKE, 49, ring, 256, 0.0, FAKE, None, FAKE,
-                     0, None, 0, None)
+    s, msg = _status(P, "pact_sos_to_delays_adjoint", FAKE, None, 1.5, FAKE, 49, ring, 256, 0.0, None, FAKE, None,
+                     FAKE, 0, None, 0, None)
     assert s == -1 and "geometry" in msg
     s, msg = _status(P, "pact_residual_loss", FAKE, FAKE, FAKE, 4, 3, 8, 0.1, FAKE, None, None, FAKE, 0, None)
     assert s == -3
@@ -91,6 +91,11 @@ def test_argument_errors(P):
     assert s == -1 and "eps" in msg
     s, msg = _status(P, "pact_das_stack", FAKE, 100, 40.0, 0.0, ring, 0.0, FAKE, 5, img, FAKE, None)
     assert s == -1
+    s, msg = _status(P, "pact_stage_contrast", FAKE, sosg, 1.5, -1.0, FAKE, None)
+    assert s == -1 and "support_radius" in msg
+    s, msg = _status(P, "pact_stage_contrast", FAKE, None, 1.5, 0.0, FAKE, None)
+    assert s == -1 and "geometry" in msg
+    assert P.pact.load().pact_staged_contrast_floats(sosg) == 34 * 34
 
 
 def test_workspace_sizes(P):

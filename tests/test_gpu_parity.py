@@ -225,6 +225,99 @@ def test_rays_with_support(lib, case):
     assert torch.equal(got_adj, junk_adj)
 
 
+STAGED_CASES = [
+    # (name, Gy, Gx, spacing, support radius): whole grid with and without a support, a ragged grid, the banded
+    # adjoint (bands start on rows whose offset is not a multiple of four floats) and the tiled one (which does
+    # not take the staged grid)
+    ("whole_23x23_support", 23, 23, 1.0, 9.0),
+    ("whole_23x23_none", 23, 23, 1.0, 0.0),
+    ("ragged_31x17", 31, 17, 0.9, 7.5),
+    ("banded_150x150", 150, 150, 0.16, 9.0),
+    ("tiled_8x2300", 8, 2300, 0.05, 30.0),
+]
+
+
+@pytest.mark.parametrize("case", STAGED_CASES, ids=lambda c: c[0])
+def test_staged_contrast(lib, case):
+    """pact_stage_contrast forms the padded contrast grid exactly (sos - v0 inside the grid and the support,
+    zero elsewhere), and the ray maps given it return what they return when they form it themselves, bit for
+    bit."""
+    name, Gy, Gx, ds, rho = case
+    announce(f"staged contrast {name}")
+    v0, n_elem, R, phi0, Ns = 1.5, 64, 90.0, 0.1, 64
+    g = lib.pact.Geometry(n_elem=n_elem, radius=R, phi0=phi0, ny=64, nx=64, px=0.1, P=16, stride=8, fwhm=1.0,
+                          sos_ny=Gy, sos_nx=Gx, sos_spacing=ds)
+    rng = np.random.default_rng(29)
+    v = np.asarray(synth.random_sos((Gy, Gx), v0, rng, amp=0.06, smooth=8), dtype=np.float32)
+    ax = lambda n: (np.arange(n) - (n - 1) / 2.0) * f32(ds)  # noqa: E731
+    dist = np.sqrt(ax(Gx)[None, :] ** 2 + ax(Gy)[:, None] ** 2)
+    inside = dist <= f32(rho) * (1 + 1e-6) if rho > 0 else np.ones((Gy, Gx), bool)
+    want = np.zeros((Gy + 2, Gx + 2), np.float32)
+    want[1:-1, 1:-1] = np.where(inside, v - np.float32(v0), np.float32(0.0))
+    sos = dev32(v)
+    st = lib.pact.stage_contrast(sos, g, v0, support=rho)
+    hc = min(0.4 * (Gx + 1) * ds, 8.0)
+    hy = min(hc, 0.4 * (Gy + 1) * ds)
+    c = dev32(np.stack([np.linspace(-hc, hc, 7), np.linspace(-hy, hy, 7)], axis=1).astype(np.float32))
+    gw = dev32(rng.standard_normal((7, n_elem)).astype(np.float32))
+    w_a = lib.pact.sos_to_delays(sos, g, v0, c, Ns, support=rho)
+    w_b = lib.pact.sos_to_delays(sos, g, v0, c, Ns, support=rho, staged=st)
+    a_a = lib.pact.sos_to_delays_adjoint(sos, g, v0, c, Ns, gw, support=rho)
+    a_b = lib.pact.sos_to_delays_adjoint(sos, g, v0, c, Ns, gw, support=rho, staged=st)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy().reshape(Gy + 2, Gx + 2)
+    # the kernel tests the support with its FP32 node coordinates: at most nodes on the rim may differ
+    rim = np.zeros((Gy + 2, Gx + 2), bool)
+    rim[1:-1, 1:-1] = np.abs(dist - f32(rho)) < 1e-4 * max(rho, 1.0)
+    assert np.array_equal(got[~rim], want[~rim])
+    assert torch.equal(w_a, w_b) and torch.equal(a_a, a_b)
+
+
+def test_fused_adjoint_tv_adam_step(lib):
+    """The fused end of a step (ray adjoint, partial sums, TV, Adam) against the separate calls on the paper's
+    SOS grid size: the same SOS, moments and gradient on the free nodes, bit for bit; the staged grid it writes
+    for the updated SOS equals pact_stage_contrast's, and a step given the staged grid of its input equals one
+    without."""
+    announce("fused adjoint + TV + Adam")
+    scan = synth.PAPER.with_(ny=240, nx=240, n_elem=128)
+    g = lib.geometry_from(scan)
+    rng = np.random.default_rng(31)
+    G = scan.sos_n
+    free = np.asarray(synth.free_node_mask(scan), bool)
+    v = np.asarray(synth.random_sos((G, G), scan.v0, rng, amp=0.03), dtype=np.float32)
+    v = np.where(free, v, np.float32(scan.v0)).astype(np.float32)
+    from oracle.geometry import patch_centres
+    cent = patch_centres(scan.ny, scan.nx, f32(scan.px), scan.P, scan.stride).numpy().astype(np.float32)
+    N = cent.shape[0]
+    c = dev32(cent)
+    gw = dev32(rng.standard_normal((N, scan.n_elem)).astype(np.float32) * 1e3)
+    mask = torch.tensor(free.astype(np.uint8), device="cuda")
+    rho, lam, lr = scan.mask_radius, f32(3e9), f32(1e-3)
+    m0 = dev32(rng.standard_normal((G, G)).astype(np.float32) * 1e-3)
+    s0 = dev32(np.abs(rng.standard_normal((G, G))).astype(np.float32) * 1e-6)
+    t0 = torch.tensor([7, 0], dtype=torch.int32, device="cuda")
+    sos = dev32(v)
+    # separate calls
+    grad = lib.pact.sos_to_delays_adjoint(sos, g, scan.v0, c, scan.n_samples, gw, support=rho)
+    a_out, a_m, a_v, a_t = torch.empty_like(sos), m0.clone(), s0.clone(), t0.clone()
+    lib.pact.tv_adam_step(sos, a_out, a_m, a_v, a_t, mask, g, grad, lam, None, lr)
+    # fused, without and with the staged grid
+    outs = []
+    for staged in (None, lib.pact.stage_contrast(sos, g, scan.v0, support=rho)):
+        b_out, b_m, b_v, b_t = torch.empty_like(sos), m0.clone(), s0.clone(), t0.clone()
+        b_grad = torch.empty_like(sos)
+        st_out = torch.full((lib.pact.staged_contrast_floats(g),), float("nan"), device="cuda")
+        lib.pact.sos_adjoint_tv_adam_step(sos, b_out, b_m, b_v, b_t, mask, g, scan.v0, c, scan.n_samples, gw, lam,
+                                          None, lr, support=rho, grad=b_grad, staged_in=staged, staged_out=st_out)
+        outs.append((b_out, b_m, b_v, b_t, b_grad, st_out))
+    torch.cuda.synchronize()
+    fr = mask.bool()
+    for b_out, b_m, b_v, b_t, b_grad, st_out in outs:
+        assert torch.equal(b_out, a_out) and torch.equal(b_m[fr], a_m[fr]) and torch.equal(b_v[fr], a_v[fr])
+        assert torch.equal(b_grad[fr], grad[fr]) and b_t.tolist() == a_t.tolist()
+        assert torch.equal(st_out, lib.pact.stage_contrast(b_out, g, scan.v0, support=rho))
+
+
 def _wavefronts(scan, seed):
     """A plausible float32 wavefront table (oracle rays through a random SOS)."""
     ov = OracleView(scan)
@@ -361,7 +454,7 @@ def test_loss_and_grad_projected(lib, scan, P_, M_):
     g = lib.geometry_from(scan)
     Yh = devc64(Opatch.half_spectrum(Y))
     d = dev32(ov.delays)
-    T = lib.pact.project_spectra(Yh, g, d)
+    T = lib.pact.project_spectra(Yh, g, d, dev32(ov.centres))
     X = torch.empty(N, scan.P, scan.P, dtype=torch.complex64, device="cuda")
     loss, gw = lib.pact.loss_and_grad_projected(T, scan.M, dev32(w), dev32(ov.centres), g, eps, X=X)
     loss_d, gw_d = lib.pact.loss_and_grad(Yh, dev32(w), dev32(ov.centres), g, d, eps)
