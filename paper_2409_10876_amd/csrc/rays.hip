@@ -755,7 +755,7 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     const float* __restrict__ sos, const float* __restrict__ staged, float v0, const float* __restrict__ centres,
     int N, int n_elem, float R, float phi0, int Ns, RayGeo g, int n_rays, int per_block, int K, int sorted,
     int n_bands, int band_rows, const float* __restrict__ dL_dw, const float* __restrict__ scale,
-    float* __restrict__ partial) {
+    float* __restrict__ partial, int* __restrict__ step_counter) {
     extern __shared__ float lds[];
     const int W = g.W;
     const int band = kBanded ? static_cast<int>(blockIdx.x) % n_bands : 0;
@@ -854,6 +854,9 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
         }
     }
     __syncthreads();
+    // the optimisation step's counter (no other workgroup of this launch touches it; the update kernel that
+    // follows reads the new value)
+    if (step_counter && blockIdx.x == 0 && tid == 0) step_counter[0] += 1;
     const float invF = 1.0f / F;
     const float bad = __builtin_nanf("");
     float* part = partial + static_cast<size_t>(blockIdx.x) * partial_pitch(g.Gy, g.Gx);
@@ -881,13 +884,30 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
 // LDS and are added in order (= or += into out).
 constexpr int kAdjSlices = 16;
 
-// Run `slice` of the kAdjSlices contiguous runs of the n_part partials at one node, added in order.
+// Run `slice` of the kAdjSlices contiguous runs of the n_part partials at one node, added in order, 16 loads in
+// flight.  The loads address the partials by 32-bit byte offsets from their base (the host keeps the buffer below
+// 4 GiB), one register per address.
 __device__ __forceinline__ float adj_run_sum(const float* __restrict__ partial, int n_part, int pitch, int node,
                                              int slice) {
+    constexpr int B = 16;
     const int per = (n_part + kAdjSlices - 1) / kAdjSlices;
     const int p0 = slice * per, p1 = min(p0 + per, n_part);
-    return p1 > p0 ? ordered_strided_sum<16>(partial + static_cast<size_t>(p0) * pitch + node, p1 - p0, pitch)
-                   : 0.0f;
+    const char* base = reinterpret_cast<const char*>(partial);
+    const unsigned step = static_cast<unsigned>(pitch) * 4u;
+    unsigned off = static_cast<unsigned>(p0) * step + static_cast<unsigned>(node) * 4u;
+    float s = 0.0f;
+    for (int k = p0; k < p1; k += B) {
+        float v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const unsigned o = k + u < p1 ? off + u * step : off;    // past the run: a load that is not used
+            v[u] = *reinterpret_cast<const float*>(base + o);
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) s = k + u < p1 ? s + v[u] : s;
+        off += B * step;
+    }
+    return s;
 }
 
 constexpr int kReduceNodes = 64;
@@ -919,15 +939,18 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_ker
 // of rays_adj_reduce_kernel (the data gradient), plus the TV subgradient at sos_in, then Adam from sos_in into
 // sos_out, as tv_adam_kernel does.  Only the free nodes inside the support read their partials (fixed nodes keep
 // their value, and the partials of nodes outside the support are not written).  The TV value is added to the
-// loss with one float atomic per workgroup (loss may be null); the last workgroup to arrive advances the step.
-__global__ __launch_bounds__(kAdjSlices * kReduceNodes) void adj_reduce_tv_adam_kernel(
+// loss with one float atomic per workgroup (loss may be null).  The step counter t[0] was advanced by the grid
+// adjoint launched just before (so no workgroup here writes it, and none needs an arrival counter).  Two
+// workgroups fit on a CU (eight waves per SIMD: at most 64 VGPRs), so that every workgroup of the 140^2 grid
+// is resident at once.
+__global__ __launch_bounds__(kAdjSlices * kReduceNodes, 8) void adj_reduce_tv_adam_kernel(
     const float* __restrict__ partial, int n_part, RayGeo g, const float* __restrict__ sos_in,
     float* __restrict__ sos_out, float* __restrict__ m, float* __restrict__ v, int* __restrict__ t,
     const unsigned char* __restrict__ mask, float lambda, float* __restrict__ loss, float lr, float b1, float b2,
     float eps, float* __restrict__ grad_out, float v0, float* __restrict__ staged_out) {
     __shared__ float run[kAdjSlices][kReduceNodes];
     __shared__ float red[kAdjSlices * kReduceNodes / 64];
-    const int step = t[0] + 1;
+    const int step = t[0];          // already advanced by the adjoint launch before this one
     const int n_nodes = g.Gy * g.Gx;
     const int j = threadIdx.x % kReduceNodes, slice = threadIdx.x / kReduceNodes;
     const int node = blockIdx.x * kReduceNodes + j;
@@ -983,7 +1006,6 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void adj_reduce_tv_adam_
         tv = block_sum(tv, red);
         if (threadIdx.x == 0 && tv != 0.0f) atomicAdd(loss, lambda * tv);
     }
-    advance_step(t, step);
 }
 
 RayGeo make_geo(const pact_grid& sosg, int n_samples, float support) {
@@ -1128,12 +1150,14 @@ size_t adj_grid_lds(const pact_grid& sosg) { return adj_plan(sosg).bands ? adj_p
 // The grid adjoint into one partial node grid per workgroup (the caller sums them); *n_part = their count.
 int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg, float v0, const float* centres, int N,
                     const pact_ring& ring, int n_samples, float support, const float* dL_dw, const float* scale,
-                    float* partial, size_t ws_bytes, hipStream_t st, int* n_part, const char* what) {
+                    float* partial, size_t ws_bytes, hipStream_t st, int* n_part, const char* what,
+                    int* step_counter = nullptr) {
     const AdjPlan plan = adj_plan(sosg);
     const int cus = device_cu_count();
     const int per_band = std::max(1, cus / plan.bands);           // workgroups per band
     const int blocks = plan.bands * per_band;
     const size_t need = static_cast<size_t>(blocks) * partial_pitch(sosg.ny, sosg.nx) * sizeof(float);
+    PACT_CHECK_SUPPORTED(need < (size_t{1} << 32), "%s: the adjoint's partial grids exceed 4 GiB", what);
     if (!partial || ws_bytes < need) {
         set_error("%s: workspace of %zu bytes needed, %zu given", what, need, partial ? ws_bytes : 0);
         return PACT_EWORKSPACE;
@@ -1159,11 +1183,12 @@ int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg
     if (plan.bands == 1)
         rays_adj_grid_kernel<false><<<blocks, kGridThreads, lds, st>>>(
             sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
-            static_cast<int>(n_rays), per_block, K, sorted, 1, sosg.ny + 1, dL_dw, scale, partial);
+            static_cast<int>(n_rays), per_block, K, sorted, 1, sosg.ny + 1, dL_dw, scale, partial, step_counter);
     else
         rays_adj_grid_kernel<true><<<blocks, kGridThreads, lds, st>>>(
             sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
-            static_cast<int>(n_rays), per_block, K, sorted, plan.bands, plan.band_rows, dL_dw, scale, partial);
+            static_cast<int>(n_rays), per_block, K, sorted, plan.bands, plan.band_rows, dL_dw, scale, partial,
+            step_counter);
     *n_part = blocks;
     return launch_status(what);
 }
@@ -1256,7 +1281,7 @@ extern "C" int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out
     PACT_CHECK_ARG(!staged_out || (staged_out != staged_in && static_cast<const float*>(staged_out) != sos_in),
                    "%s: staged_out must not alias staged_in or sos_in", what);
     if (int st = launch_adj_grid(sos_in, staged_in, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, nullptr,
-                                 partial, ws_bytes, as_stream(stream), &n_part, what))
+                                 partial, ws_bytes, as_stream(stream), &n_part, what, t))
         return st;
     const int n_nodes = sosg.ny * sosg.nx;
     adj_reduce_tv_adam_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(
