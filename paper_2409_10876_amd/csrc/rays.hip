@@ -341,8 +341,37 @@ __device__ __forceinline__ float fwd_samples(const float* vs, int first, int str
     return acc0 + acc1;
 }
 
+// Workgroups are dealt to the 8 XCDs of the GPU in turn (workgroup b to XCD b mod 8), each with its own L2.  The
+// ray kernels take their share of rays by this index instead of blockIdx.x, so that the workgroups of one XCD hold
+// consecutive elements: their reads of dL/dw and writes of w (one float per ray, n_elem apart) then share cache
+// lines within one L2 instead of writing parts of a line back from eight.  A bijection of 0 .. gridDim.x - 1;
+// correct for any XCD count.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block() {
+    const int G = static_cast<int>(gridDim.x), b = static_cast<int>(blockIdx.x);
+    const int q = G / kXcds, r = G - q * kXcds;
+    const int x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;
+}
+
 // Ray-length classes used to order a workgroup's rays (counting sort by the number of samples inside the support).
 constexpr int kLenBuckets = 33;
+
+// Bucket counts hist[0 .. kLenBuckets) -> the first slot of each bucket in the longest-first order (bucket b starts
+// after every longer bucket: an exclusive suffix sum), by the first wave with shuffles; ends with a barrier.
+__device__ __forceinline__ void bucket_starts(int* hist) {
+    const int lane = threadIdx.x;
+    if (lane < 64) {
+        const int c = lane < kLenBuckets ? hist[lane] : 0;
+        int s = c;                                    // inclusive suffix sum over the lanes
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_down(s, off, 64);
+            if (lane + off < 64) s += t;
+        }
+        if (lane < kLenBuckets) hist[lane] = s - c;
+    }
+    __syncthreads();
+}
 
 // Workgroup b takes rays b * per_block .. (element-major: ray = n * N + i, so every workgroup holds the rays of
 // about one element from every patch, and all workgroups carry about the same work).  Its rays are ordered by
@@ -369,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
         else
             stage_contrast<kStageRows>(sos, v0, g, vs, nullptr, 0, g.Gy + 2, vmin, nan_check);
     }
-    const int r0 = blockIdx.x * per_block;
+    const int r0 = xcd_block() * per_block;
     const int n_loc = max(min(per_block, n_rays - r0), 0);
     const float inv_N = 1.0f / static_cast<float>(N);
     auto setup = [&](int ray, int& i, int& n, float& gx0, float& gy0, float& dgx, float& dgy, float& dl, int& sa,
@@ -383,28 +412,23 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
     auto bucket_of = [&](int cnt) { return min(cnt * kLenBuckets / (Ns + 1), kLenBuckets - 1); };
     if (sorted) {
         __syncthreads();
-        for (int lr = tid; lr < n_loc; lr += blockDim.x) {
+        // a ray's bucket stays in its thread's register between the two passes when every ray has a thread
+        const bool one_each = n_loc <= static_cast<int>(blockDim.x);
+        auto bucket_of_ray = [&](int lr) {
             int i, n, sa, sb;
             float gx0, gy0, dgx, dgy, dl;
             setup(r0 + lr, i, n, gx0, gy0, dgx, dgy, dl, sa, sb);
-            atomicAdd(&hist[bucket_of(max(sb - sa, 0))], 1);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int run = 0;
-            for (int k = kLenBuckets - 1; k >= 0; --k) {
-                const int c = hist[k];
-                hist[k] = run;
-                run += c;
-            }
-        }
-        __syncthreads();
+            return bucket_of(max(sb - sa, 0));
+        };
+        int my_b = 0;
         for (int lr = tid; lr < n_loc; lr += blockDim.x) {
-            int i, n, sa, sb;
-            float gx0, gy0, dgx, dgy, dl;
-            setup(r0 + lr, i, n, gx0, gy0, dgx, dgy, dl, sa, sb);
-            order[atomicAdd(&hist[bucket_of(max(sb - sa, 0))], 1)] = r0 + lr;
+            my_b = bucket_of_ray(lr);
+            atomicAdd(&hist[my_b], 1);
         }
+        __syncthreads();
+        bucket_starts(hist);
+        for (int lr = tid; lr < n_loc; lr += blockDim.x)
+            order[atomicAdd(&hist[one_each ? my_b : bucket_of_ray(lr)], 1)] = r0 + lr;
     }
     __syncthreads();
     // the K lanes of a ray are adjacent and aligned, so they enter and leave the loop together and add their
@@ -758,8 +782,9 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     float* __restrict__ partial, int* __restrict__ step_counter) {
     extern __shared__ float lds[];
     const int W = g.W;
-    const int band = kBanded ? static_cast<int>(blockIdx.x) % n_bands : 0;
-    const int bblock = kBanded ? static_cast<int>(blockIdx.x) / n_bands : static_cast<int>(blockIdx.x);
+    const int vb = xcd_block();
+    const int band = kBanded ? vb % n_bands : 0;
+    const int bblock = kBanded ? vb / n_bands : vb;
     const int R0 = kBanded ? band * band_rows : 0;                        // cell rows R0 .. R1 - 1
     const int R1 = kBanded ? min(R0 + band_rows, g.Gy + 1) : g.Gy + 1;
     const int total = (R1 - R0 + 1) * W;                                  // staged padded rows R0 .. R1
@@ -799,30 +824,27 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     };
     auto bucket_of = [&](int cnt) { return min(cnt * kLenBuckets / (Ns + 1), kLenBuckets - 1); };
     float bnd = 0.0f;
+    const bool one_each = n_loc <= static_cast<int>(blockDim.x);   // then a ray's bucket stays in a register
+    int my_b = 0;
     for (int lr = tid; lr < n_loc; lr += blockDim.x) {
         float c;
         const int cnt = ray_count(r0 + lr, c);
         bnd += c;
-        if (sorted) atomicAdd(&hist[bucket_of(cnt)], 1);
+        my_b = bucket_of(cnt);
+        if (sorted) atomicAdd(&hist[my_b], 1);
     }
     bnd = block_sum(bnd + nan_check, red) / (vmin * vmin);
     const bool ok = vmin > 0.0f && bnd <= 3.0e38f;        // false for NaN or infinite bounds too
     const float F = (ok && bnd > 0.0f) ? ldexpf(1.0f, min(30 - (ilogbf(bnd) + 1), 126)) : 1.0f;
     if (sorted) {
-        // longest first: bucket b starts after every longer bucket (exclusive prefix from the top)
-        if (tid == 0) {
-            int run = 0;
-            for (int k = kLenBuckets - 1; k >= 0; --k) {
-                const int c = hist[k];
-                hist[k] = run;
-                run += c;
-            }
-        }
-        __syncthreads();
+        bucket_starts(hist);     // the barriers of block_sum above ordered the counts
         for (int lr = tid; lr < n_loc; lr += blockDim.x) {
-            float c;
-            const int cnt = ray_count(r0 + lr, c);
-            order[atomicAdd(&hist[bucket_of(cnt)], 1)] = r0 + lr;
+            int b = my_b;
+            if (!one_each) {
+                float c;
+                b = bucket_of(ray_count(r0 + lr, c));
+            }
+            order[atomicAdd(&hist[b], 1)] = r0 + lr;
         }
     }
     __syncthreads();
