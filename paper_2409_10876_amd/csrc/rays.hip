@@ -688,6 +688,8 @@ __global__ __launch_bounds__(kAdjThreads) void rays_adj_tile_kernel(
 // a reduce kernel adds the partial grids in a fixed order.
 constexpr int kGridThreads = 1024;
 
+constexpr bool kPartialNt = true;
+
 // Floats per partial grid: the node count rounded up to 64, so that every partial, and every run of 64 nodes in
 // it, starts on a 256-byte boundary (a wave's row of loads is then two whole cache lines).
 __host__ __device__ inline int partial_pitch(int ny, int nx) { return (ny * nx + 63) & ~63; }
@@ -769,11 +771,11 @@ __device__ __forceinline__ void band_samples(int s0, int s1, float gy0, float dg
 }
 
 
-// Banded form (kBanded), for grids whose contrast fits in LDS but not twice: workgroup b takes band
-// b % n_bands, cell rows R0 .. R1 - 1 (padded coordinates, R0 = band band_rows), stages padded rows
-// R0 .. R1 and accumulates the samples whose cells lie in its band; the workgroups of a band share out
-// every ray segment.  Bands overlap in one row of nodes, which both accumulate; the partial grids (zero
-// outside a workgroup's rows) are summed as before.
+// Banded form (kBanded): workgroup vb (the XCD-aware index) takes band vb % n_bands, cell rows R0 .. R1 - 1
+// (padded coordinates, R0 = band band_rows), stages padded rows R0 .. R1 and accumulates the samples whose cells
+// lie in its band; the workgroups of a band share out every ray segment.  Bands overlap in one row of nodes,
+// which both accumulate.  Partial grid vb holds the workgroup's own rows only (the reduction reads, for each
+// node, the partials of the one or two bands that hold it).
 template <bool kBanded>
 __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     const float* __restrict__ sos, const float* __restrict__ staged, float v0, const float* __restrict__ centres,
@@ -881,20 +883,23 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     if (step_counter && blockIdx.x == 0 && tid == 0) step_counter[0] += 1;
     const float invF = 1.0f / F;
     const float bad = __builtin_nanf("");
-    float* part = partial + static_cast<size_t>(blockIdx.x) * partial_pitch(g.Gy, g.Gx);
+    float* part = partial + static_cast<size_t>(vb) * partial_pitch(g.Gy, g.Gx);
     // rows per wave and columns per lane, as in the staging; grid row a is padded row a + 1, held in this
-    // workgroup's rows when R0 <= a + 1 <= R1 (zero otherwise)
+    // workgroup's rows when R0 <= a + 1 <= R1 (the only rows it writes)
     {
         const int lane = tid & 63;
         const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-        for (int a = wave; a < g.Gy; a += kGridThreads / 64) {
-            const bool mine = !kBanded || (a + 1 >= R0 && a + 1 <= R1);
+        const int a0 = kBanded ? max(R0 - 1, 0) : 0, a1 = kBanded ? min(R1 - 1, g.Gy - 1) : g.Gy - 1;
+        for (int a = a0 + wave; a <= a1; a += kGridThreads / 64) {
             const float y2 = row_y2(a + 1, g);
             for (int b = lane; b < g.Gx; b += 64) {
                 // nodes outside the support are not written: the readers of the partials take them as zero
                 if (!node_in_support(b + 1, y2, g)) continue;
-                part[a * g.Gx + b] =
-                    !ok ? bad : (mine ? static_cast<float>(acc[(a + 1 - R0) * W + b + 1]) * invF : 0.0f);
+                const float val = !ok ? bad : static_cast<float>(acc[(a + 1 - R0) * W + b + 1]) * invF;
+                if (kPartialNt)
+                    __builtin_nontemporal_store(val, part + a * g.Gx + b);
+                else
+                    part[a * g.Gx + b] = val;
             }
         }
     }
@@ -906,28 +911,54 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
 // LDS and are added in order (= or += into out).
 constexpr int kAdjSlices = 16;
 
-// Run `slice` of the kAdjSlices contiguous runs of the n_part partials at one node, added in order, 16 loads in
-// flight.  The loads address the partials by 32-bit byte offsets from their base (the host keeps the buffer below
-// 4 GiB), one register per address.
-__device__ __forceinline__ float adj_run_sum(const float* __restrict__ partial, int n_part, int pitch, int node,
-                                             int slice) {
+// Partials of the grid adjoint as the reduction sees them: n_bands bands of band_rows padded cell rows, per_band
+// partials each; partial vb belongs to band vb % n_bands (one band: every partial).
+struct PartialSet {
+    const float* base;
+    int pitch, n_bands, band_rows, per_band;
+};
+
+// The sum, in order, of `count` partials at one node, from partial index first in steps of `stride`, 16 loads
+// in flight.  The loads address the partials by 32-bit byte offsets from their base (the host keeps the buffer
+// below 4 GiB), one register per address.
+__device__ __forceinline__ float strided_partial_sum(const PartialSet& ps, int first, int count, int stride,
+                                                     int node, float s) {
     constexpr int B = 16;
-    const int per = (n_part + kAdjSlices - 1) / kAdjSlices;
-    const int p0 = slice * per, p1 = min(p0 + per, n_part);
-    const char* base = reinterpret_cast<const char*>(partial);
-    const unsigned step = static_cast<unsigned>(pitch) * 4u;
-    unsigned off = static_cast<unsigned>(p0) * step + static_cast<unsigned>(node) * 4u;
-    float s = 0.0f;
-    for (int k = p0; k < p1; k += B) {
+    const char* base = reinterpret_cast<const char*>(ps.base);
+    const unsigned step = static_cast<unsigned>(stride) * static_cast<unsigned>(ps.pitch) * 4u;
+    unsigned off = static_cast<unsigned>(first) * static_cast<unsigned>(ps.pitch) * 4u + static_cast<unsigned>(node) * 4u;
+    for (int k = 0; k < count; k += B) {
         float v[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            const unsigned o = k + u < p1 ? off + u * step : off;    // past the run: a load that is not used
+            const unsigned o = k + u < count ? off + u * step : off;    // past the run: a load that is not used
             v[u] = *reinterpret_cast<const float*>(base + o);
         }
 #pragma unroll
-        for (int u = 0; u < B; ++u) s = k + u < p1 ? s + v[u] : s;
+        for (int u = 0; u < B; ++u) s = k + u < count ? s + v[u] : s;
         off += B * step;
+    }
+    return s;
+}
+
+// Run `slice` of the kAdjSlices contiguous runs of the list of partials that hold grid node `node` (row a), added
+// in order: the partials of the band above (when the node's padded row a + 1 is the first row of a band, the
+// previous band's last row), then those of the node's band.
+__device__ __forceinline__ float adj_run_sum(const PartialSet& ps, int node, int a, int slice) {
+    const int r = a + 1;
+    const int k1 = min(r / ps.band_rows, ps.n_bands - 1);
+    const int k0 = (k1 > 0 && r == k1 * ps.band_rows) ? k1 - 1 : -1;
+    const int m = ps.per_band * (k0 >= 0 ? 2 : 1);
+    const int per = (m + kAdjSlices - 1) / kAdjSlices;
+    const int q0 = min(slice * per, m), q1 = min(q0 + per, m);
+    float s = 0.0f;
+    if (k0 >= 0) {
+        const int e = min(q1, ps.per_band);               // list entries q0 .. e - 1 are band k0's
+        if (e > q0) s = strided_partial_sum(ps, k0 + ps.n_bands * q0, e - q0, ps.n_bands, node, s);
+        const int b0 = max(q0, ps.per_band) - ps.per_band, b1 = q1 - ps.per_band;
+        if (b1 > b0) s = strided_partial_sum(ps, k1 + ps.n_bands * b0, b1 - b0, ps.n_bands, node, s);
+    } else if (q1 > q0) {
+        s = strided_partial_sum(ps, k1 + ps.n_bands * q0, q1 - q0, ps.n_bands, node, s);
     }
     return s;
 }
@@ -940,14 +971,15 @@ __device__ __forceinline__ bool grid_node_in_support(int node, const RayGeo& g) 
     return node_in_support(node - a * g.Gx + 1, row_y2(a + 1, g), g);
 }
 
-__global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_kernel(
-    const float* __restrict__ partial, int n_part, RayGeo g, int accumulate, float* __restrict__ out) {
+__global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_kernel(PartialSet ps, RayGeo g,
+                                                                                   int accumulate,
+                                                                                   float* __restrict__ out) {
     __shared__ float run[kAdjSlices][kReduceNodes];
     const int n_nodes = g.Gy * g.Gx;
     const int j = threadIdx.x % kReduceNodes, slice = threadIdx.x / kReduceNodes;
     const int node = blockIdx.x * kReduceNodes + j;
-    run[slice][j] = node < n_nodes && grid_node_in_support(node, g)
-                        ? adj_run_sum(partial, n_part, partial_pitch(g.Gy, g.Gx), node, slice) : 0.0f;
+    run[slice][j] = node < n_nodes && grid_node_in_support(node, g) ? adj_run_sum(ps, node, node / g.Gx, slice)
+                                                                    : 0.0f;
     __syncthreads();
     if (slice == 0 && node < n_nodes) {
         float t = 0.0f;
@@ -966,7 +998,7 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_ker
 // workgroups fit on a CU (eight waves per SIMD: at most 64 VGPRs), so that every workgroup of the 140^2 grid
 // is resident at once.
 __global__ __launch_bounds__(kAdjSlices * kReduceNodes, 8) void adj_reduce_tv_adam_kernel(
-    const float* __restrict__ partial, int n_part, RayGeo g, const float* __restrict__ sos_in,
+    PartialSet ps, RayGeo g, const float* __restrict__ sos_in,
     float* __restrict__ sos_out, float* __restrict__ m, float* __restrict__ v, int* __restrict__ t,
     const unsigned char* __restrict__ mask, float lambda, float* __restrict__ loss, float lr, float b1, float b2,
     float eps, float* __restrict__ grad_out, float v0, float* __restrict__ staged_out) {
@@ -989,8 +1021,7 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes, 8) void adj_reduce_tv_ad
         if (lambda != 0.0f) tv_node(sos_in, mask, nd, a, b, g.Gy, g.Gx, tv, g_tv);
         if (!valid) tv = 0.0f;
     }
-    run[slice][j] = is_free && grid_node_in_support(node, g)
-                        ? adj_run_sum(partial, n_part, partial_pitch(g.Gy, g.Gx), node, slice) : 0.0f;
+    run[slice][j] = is_free && grid_node_in_support(node, g) ? adj_run_sum(ps, node, a, slice) : 0.0f;
     __syncthreads();
     if (slice == 0 && valid) {
         float gd = 0.0f;
@@ -1149,34 +1180,51 @@ namespace {
 
 // Layout of rays_adj_grid_kernel for a grid: bands of band_rows cell rows (1 band: the whole grid) and the
 // LDS bytes of one band; bands == 0 if even bands of 8 rows do not fit (the tile kernel is used instead).
+// Bands of the grid adjoint.  A workgroup holds its band's contrast and accumulator in LDS (padded rows R0 .. R1,
+// one row shared with the next band) and writes a partial grid of those rows only, so with more bands fewer
+// partial bytes are written and read back (each band's workgroups walk only the samples inside the band, and set
+// up every ray).  Grids are cut into kAdjBands bands of at least kAdjMinBandRows rows where they have the rows
+// (one band below 2 kAdjMinBandRows), more where a band would not fit in LDS; kAdjWgsPerCu workgroups share a
+// CU where their LDS allows.
+constexpr int kAdjBands = 1;
+constexpr int kAdjMinBandRows = 16;
+constexpr int kAdjWgsPerCu = 1;
+
 struct AdjPlan {
     int bands, band_rows;
-    size_t lds;
+    size_t lds;        // without the ray order list
 };
 
 AdjPlan adj_plan(const pact_grid& sosg) {
-    const size_t W = static_cast<size_t>(sosg.nx) + 2, H = static_cast<size_t>(sosg.ny) + 2;
+    const size_t W = static_cast<size_t>(sosg.nx) + 2;
     // after the grid arrays: the block reduction's slots and the ray-length buckets
     const size_t red = (kGridThreads / 64) * sizeof(float) + kLenBuckets * sizeof(int);
-    if (2 * H * W * sizeof(float) + red <= kLdsBytes) return {1, sosg.ny + 1, 2 * H * W * sizeof(float) + red};
     const long long max_rows = static_cast<long long>((kLdsBytes - red) / (2 * W * sizeof(float))) - 1;
     if (max_rows < 8) return {0, 0, 0};
-    const int bands = ceil_div(sosg.ny + 1, max_rows);
+    const int cell_rows = sosg.ny + 1;
+    const int fit = ceil_div(cell_rows, static_cast<int>(std::min<long long>(max_rows, cell_rows)));
+    const int bands = std::max(fit, std::min(kAdjBands, std::max(1, cell_rows / kAdjMinBandRows)));
     if (bands > 64) return {0, 0, 0};
-    const int rows = ceil_div(sosg.ny + 1, bands);             // balanced bands
+    const int rows = ceil_div(cell_rows, bands);                 // balanced bands
     return {bands, rows, 2 * (static_cast<size_t>(rows) + 1) * W * sizeof(float) + red};
+}
+
+// Workgroups of the grid adjoint: per band, and in all.
+int adj_per_band(const AdjPlan& plan, int cus) {
+    const int per_cu = std::max<int>(1, std::min<size_t>(kAdjWgsPerCu, kLdsBytes / (plan.lds + 4096)));
+    return std::max(1, ceil_div(cus * per_cu, plan.bands));
 }
 
 size_t adj_grid_lds(const pact_grid& sosg) { return adj_plan(sosg).bands ? adj_plan(sosg).lds : 0; }
 
-// The grid adjoint into one partial node grid per workgroup (the caller sums them); *n_part = their count.
+// The grid adjoint into one partial node grid per workgroup (rows of its band only); *ps describes them for the
+// reduction.
 int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg, float v0, const float* centres, int N,
                     const pact_ring& ring, int n_samples, float support, const float* dL_dw, const float* scale,
-                    float* partial, size_t ws_bytes, hipStream_t st, int* n_part, const char* what,
+                    float* partial, size_t ws_bytes, hipStream_t st, PartialSet* ps, const char* what,
                     int* step_counter = nullptr) {
     const AdjPlan plan = adj_plan(sosg);
-    const int cus = device_cu_count();
-    const int per_band = std::max(1, cus / plan.bands);           // workgroups per band
+    const int per_band = adj_per_band(plan, device_cu_count());
     const int blocks = plan.bands * per_band;
     const size_t need = static_cast<size_t>(blocks) * partial_pitch(sosg.ny, sosg.nx) * sizeof(float);
     PACT_CHECK_SUPPORTED(need < (size_t{1} << 32), "%s: the adjoint's partial grids exceed 4 GiB", what);
@@ -1196,8 +1244,10 @@ int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg
     // ray and item indices are split by float quotients, exact below 2^24
     PACT_CHECK_SUPPORTED(n_rays < (1LL << 24), "%s: too many rays", what);
     const int per_block = ceil_div(n_rays, per_band);
-    // segments per ray: as many as fill the workgroup's lanes in one round (at least 8 samples a segment)
-    const int K = std::max(1, std::min(kGridThreads / std::max(per_block, 1), std::max(1, n_samples / 8)));
+    // segments per ray: as many as fill the workgroup's lanes in one round with one band's rays (at least 8
+    // samples a segment); a band's segments are about 1 / bands of a ray, but its longest are whole rays, so
+    // with several bands each lane takes several short segments instead of one long one
+    const int K = std::max(1, std::min(kGridThreads * plan.bands / std::max(per_block, 1), std::max(1, n_samples / 8)));
     // the rays in order of length, if the workgroup's list fits beside the grid arrays
     const size_t order_bytes = static_cast<size_t>(per_block) * sizeof(int);
     const int sorted = plan.lds + order_bytes <= kLdsBytes ? 1 : 0;
@@ -1211,7 +1261,7 @@ int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg
             sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
             static_cast<int>(n_rays), per_block, K, sorted, plan.bands, plan.band_rows, dL_dw, scale, partial,
             step_counter);
-    *n_part = blocks;
+    *ps = PartialSet{partial, partial_pitch(sosg.ny, sosg.nx), plan.bands, plan.band_rows, per_band};
     return launch_status(what);
 }
 
@@ -1224,7 +1274,7 @@ extern "C" size_t pact_sos_to_delays_adjoint_workspace_size(const pact_grid* sos
     if (!sosg_ || sosg_->ny <= 0 || sosg_->nx <= 0) return 0;
     const pact::AdjPlan plan = pact::adj_plan(*sosg_);
     if (!plan.bands) return 0;
-    const int blocks = plan.bands * std::max(1, pact::device_cu_count() / plan.bands);
+    const int blocks = plan.bands * pact::adj_per_band(plan, pact::device_cu_count());
     return static_cast<size_t>(blocks) * pact::partial_pitch(sosg_->ny, sosg_->nx) * sizeof(float);
 }
 
@@ -1245,13 +1295,13 @@ extern "C" int pact_sos_to_delays_adjoint(const float* sos, const pact_grid* sos
     PACT_CHECK_ARG(dL_dw && dL_dsos, "pact_sos_to_delays_adjoint: null pointer");
     if (adj_grid_lds(sosg)) {
         float* partial = static_cast<float*>(ws);
-        int n_part = 0;
-        if (int st = launch_adj_grid(sos, staged, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, scale, partial,
-                                     ws_bytes, as_stream(stream), &n_part, "pact_sos_to_delays_adjoint"))
+        PartialSet ps;
+        if (int st = launch_adj_grid(sos, staged, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, scale,
+                                     partial, ws_bytes, as_stream(stream), &ps, "pact_sos_to_delays_adjoint"))
             return st;
         const int n_nodes = sosg.ny * sosg.nx;
         rays_adj_reduce_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(
-            partial, n_part, make_geo(sosg, n_samples, support_radius), accumulate, dL_dsos);
+            ps, make_geo(sosg, n_samples, support_radius), accumulate, dL_dsos);
         return launch_status("pact_sos_to_delays_adjoint");
     }
     const size_t lds = static_cast<size_t>(kTile + 2) * (kTile + 2) * kAdjThreads * sizeof(float) +
@@ -1299,15 +1349,15 @@ extern "C" int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out
     PACT_CHECK_SUPPORTED(adj_grid_lds(sosg) > 0, "%s: the %d x %d grid takes the tiled adjoint; use "
                          "pact_sos_to_delays_adjoint and pact_tv_adam_step", what, sosg.ny, sosg.nx);
     float* partial = static_cast<float*>(ws);
-    int n_part = 0;
+    PartialSet ps;
     PACT_CHECK_ARG(!staged_out || (staged_out != staged_in && static_cast<const float*>(staged_out) != sos_in),
                    "%s: staged_out must not alias staged_in or sos_in", what);
     if (int st = launch_adj_grid(sos_in, staged_in, sosg, v0, centres, N, ring, n_samples, support_radius, dL_dw, nullptr,
-                                 partial, ws_bytes, as_stream(stream), &n_part, what, t))
+                                 partial, ws_bytes, as_stream(stream), &ps, what, t))
         return st;
     const int n_nodes = sosg.ny * sosg.nx;
     adj_reduce_tv_adam_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(
-        partial, n_part, make_geo(sosg, n_samples, support_radius), sos_in, sos_out, m, v, t, mask, lambda, loss, lr,
+        ps, make_geo(sosg, n_samples, support_radius), sos_in, sos_out, m, v, t, mask, lambda, loss, lr,
         b1, b2, eps, grad, v0, staged_out);
     return launch_status(what);
 }
