@@ -82,10 +82,10 @@ def traffic_bytes(stage):
 # copy kernel read as 256 MiB; rocprofv3 counter runs recorded under profiles/), keyed to the kernel source
 # it was taken on.
 TRAFFIC = {
-    "sos_to_delays": {"source": "rays.hip", "sha256_16": "54c341ee909d8aad", "bytes": 1067917},
-    "loss_and_grad": {"source": "loss.hip", "sha256_16": "387f46a72608b6aa", "bytes": 61953624},
-    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "54c341ee909d8aad", "bytes": 48840806},
-    "tv_adam_step": {"source": "optim.hip", "sha256_16": "d8c556e2161b22f0", "bytes": 749997},
+    "sos_to_delays": {"source": "rays.hip", "sha256_16": "ddee195ffe097f8e", "bytes": 1133448},
+    "loss_and_grad": {"source": "loss.hip", "sha256_16": "ea8f8d36bc036bb4", "bytes": 16832988},
+    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "ddee195ffe097f8e", "bytes": 33797880},
+    "adjoint_tv_adam": {"source": "rays.hip", "sha256_16": "ddee195ffe097f8e", "bytes": 34853730},
 }
 
 
@@ -273,11 +273,14 @@ def main():
     # the ray samples the method needs: those that can touch a free node (the others add exactly zero)
     samples = active_samples(scan, solver.support)
     rays_io = N * scan.n_elem * 4
+    n_virtual = Pp * (Pp // 2 + 1) + (Pp // 2 - 1 if Pp % 2 == 0 else 0)
     # per stage: (kernels, bound, algorithmic work per launch, unit of the work)
     work = {
         "sos_to_delays": ("rays_fwd_kernel", "alu", samples * FLOPS_PER_SAMPLE_FWD, "flop"),
         # the projected spectra (five floats per patch and bin) once, w in, dL/dw out
-        "loss_and_grad": ("loss_proj_kernel", "hbm", N * Pp * (Pp // 2 + 1) * 20 + 2 * rays_io, "byte"),
+        # per patch and bin the five projections, per patch and virtual bin the two ring hits, w in, dL/dw out
+        "loss_and_grad": ("loss_proj_kernel", "hbm", N * Pp * (Pp // 2 + 1) * 20 + N * n_virtual * 8 + 2 * rays_io,
+                          "byte"),
         "sos_to_delays_adjoint": ("rays_adj_grid_kernel + rays_adj_reduce_kernel", "alu",
                                   samples * FLOPS_PER_SAMPLE_ADJ, "flop"),
         # the step's last two launches: the grid adjoint, then its partials' sum fused with TV and Adam
@@ -297,9 +300,10 @@ def main():
             rooflines[k]["issue_peak"] = ALU_ISSUE_PEAK_TFLOPS
             rooflines[k]["frac_of_issue_peak"] = ach / ALU_ISSUE_PEAK_TFLOPS
     dominant = max(work, key=lambda k: breakdown[k])
-    # the step as a whole against the HBM roofline: the bytes one optimisation step must move (Y once, w and
-    # dL/dw written and read, the SOS read by both ray kernels and TV + Adam and written, the gradient written
-    # and read, Adam's m and v read and written, the mask) over the graph-replayed time per step
+    # the step as a whole against the HBM roofline: the bytes one optimisation step must move (the projected
+    # spectra and ring hits once, w and dL/dw written and read, the SOS read by both ray kernels and TV + Adam
+    # and written, the gradient written and read, Adam's m and v read and written, the mask) over the
+    # graph-replayed time per step
     step_bytes = work["loss_and_grad"][2] + 2 * rays_io + G2 * 4 * (3 + 1 + 1 + 4) + G2
     us_step = 1e6 * elapsed / opt_steps
     print("[bench] stage times (us): " + ", ".join(f"{k} {v:.1f}" for k, v in breakdown.items()), flush=True)
@@ -324,6 +328,11 @@ def main():
         "stage_us": breakdown,
     }
     out["reconstruction"] = reconstruction_quality(P, sd, solver, inp, scan, elapsed / args.steps)
+    rq = out["reconstruction"]
+    af = rq["ip_image"]["aberration_free"]
+    print(f"[bench] SOS RMSE {rq['sos_rmse_initial_m_per_s']:.2f} -> {rq['sos_rmse_m_per_s']:.2f} m/s; image PSNR / SSIM "
+          "against the aberration-free image: " + ", ".join(f"{k} {v['psnr_db']:.2f} dB / {v['ssim']:.3f}"
+                                                            for k, v in af.items()), flush=True)
     out["precision"] = precision_leg(P, sd, solver, scan, inp.mask)
     out["delay_sweep"] = delay_sweep(P, sd, scan, solver)
     out["paper_neural_field"] = siren_leg(P, sd, scan, inp, reps=args.timing_steps)
@@ -342,7 +351,8 @@ def main():
                 "speedup": sm["t_plain_to_rmse_s"] / sm["t_warm_to_rmse_s"],
                 "rmse_plain_m_per_s": sm["rmse_plain"], "rmse_warm_start_m_per_s": sm["rmse_net"],
                 "scans": sm["n_scans"], "reached_fraction": sm["rmse_target_reached_fraction"],
-                "equal_loss_reached_fraction": sm.get("equal_loss_reached_fraction")}
+                "equal_loss_reached_fraction": sm.get("equal_loss_reached_fraction"),
+                "loss_split_where_equal_loss_not_reached": sm.get("loss_split_not_reached")}
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, inp, args.cpu_steps)
@@ -391,33 +401,57 @@ def precision_leg(P, sd, solver, scan, mask):
 
 
 def reconstruction_quality(P, sd, solver, inp, scan, job_s):
-    """The state after the last timed job: SOS error on the free nodes and the stitched deconvolved image
-    (Supp. S1.4) against the synthetic truth (PSNR / SSIM after normalisation to the truth's range)."""
+    """The state after the last timed job: SOS error on the free nodes, and the stitched deconvolved image
+    (Supp. S1.4) against three references (PSNR / SSIM after scaling to the reference's range):
+    - the aberration-free image: the same blobs in a uniform medium (SOS v0 everywhere), the same processing
+      (DAS, patch spectra, deconvolution with w = 0, stitching).  It is what a perfect SOS correction gives, and
+      it is band-limited like every reconstruction;
+    - the deconvolution of the same data with the true SOS (Table 1's oracle row);
+    - the synthetic initial pressure itself (unfiltered blobs, which no band-limited image matches)."""
+    import numpy as np
     import torch
+    import synth
+    from synth.phantoms import SosPhantom
     from paper_2409_10876_amd import metrics
     g = sd.geom
     N = sd.centres.shape[0]
     X = torch.empty(N, g.P, g.P, dtype=torch.complex64, device=sd.S.device)
+
+    def image(scan_data, w):
+        scan_data.loss_and_grad(w, solver.eps, X=X)
+        return P.pact.stitch(P.pact.ifft2_real(X), g)
+
     solver.delays()
-    sd.loss_and_grad(solver.w, solver.eps, X=X)
-    img = P.pact.stitch(P.pact.ifft2_real(X), g)
-    # the same with no SOS correction (uniform v0): what the deconvolution alone gives
+    img = image(sd, solver.w)
     w0 = torch.zeros_like(solver.w)
-    sd.loss_and_grad(w0, solver.eps, X=X)
-    img0 = P.pact.stitch(P.pact.ifft2_real(X), g)
-    das = sd.stack[len(scan.delays) // 2]                  # the d = 0 DAS image
-    torch.cuda.synchronize()
-    ref = torch.tensor(inp.ip_true)
+    img0 = image(sd, w0)                                    # no SOS correction (uniform v0)
     mask = torch.tensor(inp.mask).bool()
     vt = torch.tensor(inp.sos_true)
-    rmse = lambda v: 1e3 * torch.sqrt(((v.cpu().double() - vt)[mask] ** 2).mean()).item()
+    v_true = torch.where(mask, vt, torch.full_like(vt, scan.v0)).to(torch.float32).to(sd.S.device).contiguous()
+    w_true = P.pact.sos_to_delays(v_true, g, scan.v0, sd.centres, scan.n_samples)
+    img_true = image(sd, w_true)                            # deconvolution with the true SOS
+    # the same blobs in a uniform medium, through the same processing
+    S_free = synth.channel_data(scan, SosPhantom("uniform", scan.v0, {}), inp.blobs, rng=np.random.default_rng(0))
+    sd_free = P.prepare_scan(scan, S_free, np.asarray(scan.delays, dtype=np.float32), device=sd.S.device)
+    img_free = image(sd_free, w0)
+    das = sd.stack[len(scan.delays) // 2]                   # the d = 0 DAS image
+    torch.cuda.synchronize()
+    rmse = lambda v: 1e3 * torch.sqrt(((v.cpu().double() - vt)[mask] ** 2).mean()).item()  # noqa: E731
+    refs = {"aberration_free": img_free.cpu(), "true_sos_deconv": img_true.cpu(),
+            "synthetic_truth": torch.tensor(inp.ip_true)}
+    images = {"reconstructed": img, "true_sos_deconv": img_true, "uniform_sos": img0, "das_d0": das}
     q = {}
-    for name, im in (("reconstructed", img), ("uniform_sos", img0), ("das_d0", das)):
-        a, b = metrics.normalise(im.cpu(), ref)
-        q[name] = {"psnr_db": metrics.psnr(a, b), "ssim": metrics.ssim(a, b)}
+    for rname, ref in refs.items():
+        q[rname] = {}
+        for name, im in images.items():
+            if name == rname:
+                continue
+            a, b = metrics.normalise(im.cpu().double(), ref.double())
+            q[rname][name] = {"psnr_db": metrics.psnr(a, b), "ssim": metrics.ssim(a, b)}
+    del sd_free
     return {"sos_rmse_m_per_s": rmse(solver.sos), "sos_rmse_initial_m_per_s": rmse(torch.full_like(vt, scan.v0)),
             "time_to_rmse_s": job_s, "ip_image": q,
-            "note": "plain method after one timed job; IP figures after scaling to the synthetic truth's range"}
+            "note": "plain method after one timed job; IP figures after scaling to each reference's range"}
 
 
 def delay_sweep(P, sd, scan, solver, counts=(4, 8, 11, 16), reps=20):
@@ -680,30 +714,39 @@ def nf_oracle_rate(scan, cfg, n_centres=4, n_elem=32):
 
 
 def nf_bf16_error(solver, scan, cfg, n_centres=4, n_elem=32):
-    """The BF16 error of the neural-field delays at the initial parameters, on a sample of rays: relative L2
-    of the GPU's w against the plain FP64 network (the workload's own precision error) and against the
-    oracle with the same BF16 rounding points (the logic)."""
+    """The BF16 error of the neural-field delays at the initial parameters, on a sample of rays, as relative L2
+    of the GPU's w against the FP64 oracle network: with the FP32 master weights (the whole precision error of
+    the workload: BF16 weights and activations), with the weights rounded to BF16 as the kernels use them (the
+    activations' rounding alone), and with the kernels' BF16 rounding points too (what is left is FP32 against
+    FP64 arithmetic: the logic)."""
     import numpy as np
     import torch
     import synth
     from oracle import nf as Onf
     F64 = torch.float64
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
     solver.pack()
     solver.delays()
     stride = scan.n_elem // n_elem
     w = solver.w[:n_centres, ::stride][:, :n_elem].cpu().double()
-    B = torch.tensor(synth.nf.frequencies(cfg), dtype=F64)
-    params = torch.tensor(synth.nf.init_params(cfg), dtype=F64)
+    B = torch.tensor(np.asarray(synth.nf.frequencies(cfg), dtype=np.float32), dtype=F64)
+    params = torch.tensor(np.asarray(synth.nf.init_params(cfg), dtype=np.float32), dtype=F64)
+    blocks = Onf.unpack(params, cfg.n_freq, cfg.width)
+    for name in ("W1", "W2", "W3", "W4", "w5"):
+        blocks[name] = Onf.round_bf16(blocks[name])
+    params_bf16 = Onf.pack(blocks, cfg.n_freq, cfg.width)
     c = solver.scan.centres[:n_centres].cpu().double()
-    phi = scan.phi0 + 2 * np.pi * np.arange(0, scan.n_elem, stride)[:n_elem] / scan.n_elem
-    ring = torch.tensor(np.stack([scan.radius * np.cos(phi), scan.radius * np.sin(phi)], -1), dtype=F64)
+    phi = f32(scan.phi0) + 2 * np.pi * np.arange(0, scan.n_elem, stride)[:n_elem] / scan.n_elem
+    ring = torch.tensor(np.stack([f32(scan.radius) * np.cos(phi), f32(scan.radius) * np.sin(phi)], -1), dtype=F64)
     rel = lambda a, b: (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()  # noqa: E731
     out = {}
-    for name, bf in (("w_vs_fp64_network", False), ("w_vs_bf16_rounding_oracle", True)):
-        out[name] = rel(w, Onf.sos_to_delays(params, B, c, ring, scan.mask_radius, scan.v0, cfg.amp,
+    for name, p, bf in (("w_vs_fp64_network", params, False), ("w_vs_fp64_network_bf16_weights", params_bf16, False),
+                        ("w_vs_bf16_rounding_oracle", params_bf16, True)):
+        out[name] = rel(w, Onf.sos_to_delays(p, B, c, ring, f32(scan.mask_radius), f32(scan.v0), f32(cfg.amp),
                                              scan.n_samples, bf16=bf))
     out["sample"] = f"{n_centres} patch centres x {n_elem} elements (every {stride}th), initial parameters"
-    print(f"[bench] neural field BF16 error: w rel L2 {out['w_vs_fp64_network']:.2e} vs FP64, "
+    print(f"[bench] neural field BF16 error: w rel L2 {out['w_vs_fp64_network']:.2e} vs the FP64 network, "
+          f"{out['w_vs_fp64_network_bf16_weights']:.2e} with its weights in BF16, "
           f"{out['w_vs_bf16_rounding_oracle']:.2e} vs the BF16-rounding oracle", flush=True)
     return out
 

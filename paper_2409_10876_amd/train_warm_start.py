@@ -173,6 +173,9 @@ def evaluate_scan(net, sim, scan, sos_true, blobs, scale, steps=500, chunk=10, d
     torch.cuda.synchronize()
     rm_p = [rmse(snaps[0, k]) for k in range(n_chunks + 1)]
     rm_w = [rmse(snaps[1, k]) for k in range(n_chunks + 1)]
+    # the loss split into its data term and lambda * TV at the network's SOS and at both final SOS grids
+    terms = {name: loss_terms(plain, snaps[i, k].contiguous())
+             for name, i, k in (("net", 1, 0), ("plain_final", 0, n_chunks), ("warm_final", 1, n_chunks))}
     L_plain = loss_p[-1]
     eq = next((k for k, L in enumerate(loss_w) if L <= L_plain), None)
     target = rm_p[-1]
@@ -187,7 +190,19 @@ def evaluate_scan(net, sim, scan, sos_true, blobs, scale, steps=500, chunk=10, d
             "t_warm_to_equal_loss_s": None if eq is None else time_w[eq],
             "t_plain_to_rmse_s": t_at(time_p, first_p, 0.0),
             "t_warm_to_rmse_s": None if first_w is None else t_at(time_w, first_w, t_inf),
-            "rmse_curve_plain": rm_p, "rmse_curve_warm": rm_w, "loss_curve_plain": loss_p, "loss_curve_warm": loss_w}
+            "rmse_curve_plain": rm_p, "rmse_curve_warm": rm_w, "loss_curve_plain": loss_p, "loss_curve_warm": loss_w,
+            **{f"data_{n}": t[0] for n, t in terms.items()}, **{f"lam_tv_{n}": t[1] for n, t in terms.items()}}
+
+
+def loss_terms(solver, sos):
+    """The two parts of the step's loss (Eq. jr) at an SOS grid: the data term of the fused deconvolution loss
+    and lambda * TV."""
+    w = pact.sos_to_delays(sos, solver.g, solver.scan.v0, solver.scan.centres, solver.n_samples,
+                           support=solver.support)
+    data, _ = solver.scan.loss_and_grad(w, solver.eps, want_grad=False)
+    tvl = torch.zeros(1, dtype=torch.float32, device=sos.device)
+    pact.tv_grad(sos.contiguous(), solver.mask, solver.g, solver.lam, torch.zeros_like(sos), tvl)
+    return float(data), float(tvl)
 
 
 def summarise(rows):
@@ -203,6 +218,14 @@ def summarise(rows):
         out["t_warm_to_equal_loss_s_mean_where_reached"] = float(np.mean([r["t_warm_to_equal_loss_s"] for r in reached]))
         out["rmse_warm_at_equal_loss_mean_where_reached"] = float(np.mean([r["rmse_warm_at_equal_loss"] for r in reached]))
         out["rmse_plain_mean_where_reached"] = float(np.mean([r["rmse_plain"] for r in reached]))
+    # where the warm run stays above the plain run's final loss: which part of the loss keeps it there
+    missed = [r for r in rows if r["steps_warm_to_equal_loss"] is None]
+    for grp, rs in (("not_reached", missed), ("reached", reached)):
+        if rs:
+            out[f"loss_split_{grp}"] = {
+                k: float(np.mean([r[k] for r in rs]))
+                for k in ("data_net", "lam_tv_net", "data_plain_final", "lam_tv_plain_final", "data_warm_final",
+                          "lam_tv_warm_final")}
     rr = [r for r in rows if r["t_warm_to_rmse_s"] is not None]
     out["rmse_target_reached_fraction"] = len(rr) / len(rows)
     if rr:
