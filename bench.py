@@ -536,8 +536,9 @@ def siren_leg(P, sd, scan, inp, reps=100, graph_steps=50):
 
 def batch_leg(P, n_scans, steps=100, graph_steps=10):
     """Independent scans of uneven sizes (256^2 .. 768^2 px, 256 .. 1024 elements, 7 .. 15 delays, 64^2 or
-    80^2 patches) solved together: per-scan step graphs replayed on one stream each, against the same work
-    one scan after another.  Reports optimisation steps per second summed over the scans."""
+    80^2 patches) solved together, three ways: per-scan step graphs replayed one scan after another, the same
+    graphs on one stream each, and one launch per stage over all scans (five launches per batched step,
+    captured in one graph).  Reports optimisation steps per second summed over the scans."""
     import numpy as np
     import torch
     import synth
@@ -553,11 +554,13 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
     t0 = time.perf_counter()
     batch = P.BatchedSolver(solvers, graph_steps=graph_steps, autotune=True)
     print(f"[bench] batch: ray tilings autotuned per scan shape in {time.perf_counter() - t0:.1f} s", flush=True)
+    grouped = P.GroupedBatchSolver(solvers, graph_steps=graph_steps)     # the same scans' buffers
     batch.run(graph_steps)
     batch.run_sequential(graph_steps)
+    grouped.run(graph_steps)
     torch.cuda.synchronize()
     out = {}
-    for name, fn in (("sequential", batch.run_sequential), ("concurrent", batch.run)):
+    for name, fn in (("sequential", batch.run_sequential), ("concurrent", batch.run), ("grouped", grouped.run)):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         fn(steps)
@@ -566,11 +569,15 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
         ms = a.elapsed_time(b)
         out[name] = {"ms": ms, "scan_steps_per_s": n_scans * steps / (ms * 1e-3)}
     out["speedup"] = out["sequential"]["ms"] / out["concurrent"]["ms"]
+    out["speedup_grouped"] = out["sequential"]["ms"] / out["grouped"]["ms"]
     out["scans"] = [{"px": s.ny, "n_elem": s.n_elem, "M": s.M, "P": s.P, "patches": s.n_patches, "sos_n": s.sos_n,
                      "ray_tiling": list(t)} for s, t in zip(scans, batch.tilings)]
-    out["patches_x_delays_per_s"] = sum(s.n_patches * s.M for s in scans) * steps / (out["concurrent"]["ms"] * 1e-3)
+    best = min(("concurrent", "grouped"), key=lambda k: out[k]["ms"])
+    out["fastest"] = best
+    out["patches_x_delays_per_s"] = sum(s.n_patches * s.M for s in scans) * steps / (out[best]["ms"] * 1e-3)
     print(f"[bench] batch: {n_scans} scans x {steps} steps: sequential {out['sequential']['ms']:.1f} ms, "
-          f"concurrent {out['concurrent']['ms']:.1f} ms", flush=True)
+          f"concurrent streams {out['concurrent']['ms']:.1f} ms, grouped launches {out['grouped']['ms']:.1f} ms",
+          flush=True)
     return out
 
 

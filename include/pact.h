@@ -344,6 +344,58 @@ PACT_API int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out, 
                                            float b2, float eps, float* grad, void* ws, size_t ws_bytes,
                                            void* stream);
 
+/* ---- Batched solves: one launch per stage over many scans ----
+ *
+ * Independent scans (each its own geometry, spectra and SOS grid) advance together: every stage of a
+ * pixel-grid step (wavefronts, fused loss, ray adjoint, partial sums + TV + Adam) runs as one launch over
+ * all scans, each workgroup taking one scan's block from a table.  Every scan keeps the partition of work it
+ * has alone (the same workgroups' rays, lanes per ray, length order, fixed-point scales and partial grids),
+ * so its results equal those of pact_sos_to_delays, pact_loss_and_grad_projected and
+ * pact_sos_adjoint_tv_adam_step on that scan, bit for bit.
+ *
+ * pact_batch_scan describes one scan: its geometry and optimiser settings, and the DEVICE buffers of its step
+ * as those calls take them.  sos[k] and staged[k] (k = 0, 1) are the two SOS buffers and their staged
+ * contrast grids (pact_stage_contrast) that the steps alternate: a step of parity k reads sos[k] and
+ * staged[k] and writes sos[1 - k] and staged[1 - k].  grad may be NULL.  partial: the adjoint workspace
+ * (pact_sos_to_delays_adjoint_workspace_size() bytes); patch_loss: N floats.  Only grids that take the
+ * whole-grid or banded adjoint are accepted (as for pact_sos_adjoint_tv_adam_step). */
+typedef struct {
+    pact_grid sosg;
+    pact_ring ring;
+    int N, M, P, n_samples;
+    float px, v0, support_radius, eps;
+    float lambda, lr, b1, b2, adam_eps;
+    const float* centres;
+    const float* T;
+    float* w;
+    float* dL_dw;
+    float* patch_loss;
+    float* loss;
+    float* sos[2];
+    float* staged[2];
+    float* m;
+    float* v;
+    int* t;
+    const unsigned char* mask;
+    float* grad;
+    float* partial;
+    size_t partial_bytes;
+} pact_batch_scan;
+
+/* pact_batch_plan checks the scans, plans every stage of both parities and writes the plan: a HOST buffer of
+ * pact_batch_plan_bytes(n_scans) bytes (kernel grids, LDS sizes, where the table is) and a DEVICE table of
+ * pact_batch_table_bytes(n_scans) bytes (per-scan launch arguments and block ranges), copied synchronously;
+ * both are the caller's and must outlive every step that uses them.  The plan captures the ray tilings
+ * pact_rays_autotune chose at that time.  n_scans <= 256.
+ * pact_batch_step enqueues one step of every scan (5 launches; with with_loss != 0 also each scan's scalar
+ * loss, data term plus lambda TV, as pact_sos_adjoint_tv_adam_step adds it).  It reads only the host plan, so
+ * it can be captured in a graph. */
+PACT_API size_t pact_batch_plan_bytes(int n_scans);
+PACT_API size_t pact_batch_table_bytes(int n_scans);
+PACT_API int pact_batch_plan(const pact_batch_scan* scans, int n_scans, void* plan, size_t plan_bytes, void* table,
+                             size_t table_bytes, void* stream);
+PACT_API int pact_batch_step(const void* plan, int parity, int with_loss, void* stream);
+
 /* ---- The paper's neural-field SOS: a sinusoidal network on the SOS-grid nodes (Sec. 3.3) ----
  *
  * v[a][b] = v0 + s (w2 . sin(omega0 (W1 (x_b, y_a) + b1)) + b2) + o on the free nodes (mask != 0),

@@ -9,9 +9,9 @@ there is no fallback implementation.
 from . import pact  # noqa: F401
 from .pact import PactError, Geometry, load  # noqa: F401
 
-from .solver import (ScanData, PixelGridSolver, NeuralFieldSolver, SirenSolver, BatchedSolver,  # noqa: E402,F401
+from .solver import (ScanData, PixelGridSolver, NeuralFieldSolver, SirenSolver, BatchedSolver, GroupedBatchSolver,  # noqa: E402,F401,E501
                      SosLoss, geometry_from, prepare_scan)
 from . import warmstart  # noqa: E402,F401
 
-__all__ = ["pact", "PactError", "Geometry", "load", "ScanData", "PixelGridSolver", "NeuralFieldSolver", "SirenSolver", "BatchedSolver", "SosLoss",
+__all__ = ["pact", "PactError", "Geometry", "load", "ScanData", "PixelGridSolver", "NeuralFieldSolver", "SirenSolver", "BatchedSolver", "GroupedBatchSolver", "SosLoss",
            "geometry_from", "prepare_scan", "warmstart"]

@@ -344,11 +344,11 @@ __device__ __forceinline__ float fwd_samples(const float* vs, int first, int str
 // Workgroups are dealt to the 8 XCDs of the GPU in turn (workgroup b to XCD b mod 8), each with its own L2.  The
 // ray kernels take their share of rays by this index instead of blockIdx.x, so that the workgroups of one XCD hold
 // consecutive elements: their reads of dL/dw and writes of w (one float per ray, n_elem apart) then share cache
-// lines within one L2 instead of writing parts of a line back from eight.  A bijection of 0 .. gridDim.x - 1;
-// correct for any XCD count.
+// lines within one L2 instead of writing parts of a line back from eight.  A bijection of 0 .. G - 1 for block b
+// of G (a batched launch passes the scan's own block and count; its scans start on multiples of 8); correct for
+// any XCD count.
 constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_block() {
-    const int G = static_cast<int>(gridDim.x), b = static_cast<int>(blockIdx.x);
+__device__ __forceinline__ int xcd_block(int b, int G) {
     const int q = G / kXcds, r = G - q * kXcds;
     const int x = b % kXcds;
     return x * q + min(x, r) + b / kXcds;
@@ -378,13 +378,30 @@ __device__ __forceinline__ void bucket_starts(int* hist) {
 // their sample counts inside the support (longest first, when the order fits in LDS) and each goes to K adjacent
 // lanes (K a power of two) that take its samples in turn: the lanes of a wave then walk rays of similar length,
 // and the lanes of a ray read neighbouring cells.
-__global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restrict__ sos,
-                                                            const float* __restrict__ staged, float v0,
-                                                            const float* __restrict__ centres, int N, int n_elem,
-                                                            float R, float phi0, int Ns, RayGeo g, int log2K,
-                                                            int n_rays, int per_block, int sorted,
-                                                            float* __restrict__ w) {
-    extern __shared__ float vs[];
+struct FwdArgs {
+    const float* sos;
+    const float* staged;
+    float v0;
+    const float* centres;
+    int N, n_elem;
+    float R, phi0;
+    int Ns;
+    RayGeo g;
+    int log2K, n_rays, per_block, sorted;
+    float* w;
+};
+
+// The forward pass of block blk of nblk (the scan's own numbering) with its LDS at vs.
+__device__ __forceinline__ void rays_fwd_body(const FwdArgs& A, int blk, int nblk, float* vs) {
+    const float* __restrict__ sos = A.sos;
+    const float* __restrict__ staged = A.staged;
+    const float v0 = A.v0;
+    const float* __restrict__ centres = A.centres;
+    const int N = A.N, n_elem = A.n_elem, Ns = A.Ns, log2K = A.log2K, n_rays = A.n_rays, per_block = A.per_block,
+              sorted = A.sorted;
+    const float R = A.R, phi0 = A.phi0;
+    const RayGeo& g = A.g;
+    float* __restrict__ w = A.w;
     const int K = 1 << log2K;
     const int total = (g.Gy + 2) * g.W;
     int* hist = reinterpret_cast<int*>(vs + total);        // [kLenBuckets]
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
         else
             stage_contrast<kStageRows>(sos, v0, g, vs, nullptr, 0, g.Gy + 2, vmin, nan_check);
     }
-    const int r0 = xcd_block() * per_block;
+    const int r0 = xcd_block(blk, nblk) * per_block;
     const int n_loc = max(min(per_block, n_rays - r0), 0);
     const float inv_N = 1.0f / static_cast<float>(N);
     auto setup = [&](int ray, int& i, int& n, float& gx0, float& gy0, float& dgx, float& dgy, float& dl, int& sa,
@@ -456,6 +473,11 @@ __global__ __launch_bounds__(kThreads) void rays_fwd_kernel(const float* __restr
         for (int off = K >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, K);
         if (it < n_items && k == 0) w[static_cast<size_t>(i) * n_elem + n] = acc * dl;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void rays_fwd_kernel(FwdArgs A) {
+    extern __shared__ float vs[];
+    rays_fwd_body(A, blockIdx.x, gridDim.x, vs);
 }
 
 // Sector of the elements whose rays from (cx, cy) can cross the rectangle [x0, x1] x [y0, y1]:
@@ -776,15 +798,39 @@ __device__ __forceinline__ void band_samples(int s0, int s1, float gy0, float dg
 // lie in its band; the workgroups of a band share out every ray segment.  Bands overlap in one row of nodes,
 // which both accumulate.  Partial grid vb holds the workgroup's own rows only (the reduction reads, for each
 // node, the partials of the one or two bands that hold it).
+struct AdjArgs {
+    const float* sos;
+    const float* staged;
+    float v0;
+    const float* centres;
+    int N, n_elem;
+    float R, phi0;
+    int Ns;
+    RayGeo g;
+    int n_rays, per_block, K, sorted, n_bands, band_rows;
+    const float* dL_dw;
+    const float* scale;
+    float* partial;
+    int* step_counter;
+};
+
+// The grid adjoint of block blk of nblk (the scan's own numbering) with its LDS at lds.
 template <bool kBanded>
-__global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
-    const float* __restrict__ sos, const float* __restrict__ staged, float v0, const float* __restrict__ centres,
-    int N, int n_elem, float R, float phi0, int Ns, RayGeo g, int n_rays, int per_block, int K, int sorted,
-    int n_bands, int band_rows, const float* __restrict__ dL_dw, const float* __restrict__ scale,
-    float* __restrict__ partial, int* __restrict__ step_counter) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void rays_adj_grid_body(const AdjArgs& A, int blk, int nblk, float* lds) {
+    const float* __restrict__ sos = A.sos;
+    const float* __restrict__ staged = A.staged;
+    const float v0 = A.v0;
+    const float* __restrict__ centres = A.centres;
+    const int N = A.N, n_elem = A.n_elem, Ns = A.Ns, n_rays = A.n_rays, per_block = A.per_block, K = A.K,
+              sorted = A.sorted, n_bands = A.n_bands, band_rows = A.band_rows;
+    const float R = A.R, phi0 = A.phi0;
+    const RayGeo& g = A.g;
+    const float* __restrict__ dL_dw = A.dL_dw;
+    const float* __restrict__ scale = A.scale;
+    float* __restrict__ partial = A.partial;
+    int* __restrict__ step_counter = A.step_counter;
     const int W = g.W;
-    const int vb = xcd_block();
+    const int vb = xcd_block(blk, nblk);
     const int band = kBanded ? vb % n_bands : 0;
     const int bblock = kBanded ? vb / n_bands : vb;
     const int R0 = kBanded ? band * band_rows : 0;                        // cell rows R0 .. R1 - 1
@@ -880,7 +926,7 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
     __syncthreads();
     // the optimisation step's counter (no other workgroup of this launch touches it; the update kernel that
     // follows reads the new value)
-    if (step_counter && blockIdx.x == 0 && tid == 0) step_counter[0] += 1;
+    if (step_counter && blk == 0 && tid == 0) step_counter[0] += 1;
     const float invF = 1.0f / F;
     const float bad = __builtin_nanf("");
     float* part = partial + static_cast<size_t>(vb) * partial_pitch(g.Gy, g.Gx);
@@ -903,6 +949,12 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(
             }
         }
     }
+}
+
+template <bool kBanded>
+__global__ __launch_bounds__(kGridThreads) void rays_adj_grid_kernel(AdjArgs A) {
+    extern __shared__ float lds[];
+    rays_adj_grid_body<kBanded>(A, blockIdx.x, gridDim.x, lds);
 }
 
 // Sum of the per-workgroup partial grids in a fixed order.  A workgroup owns 64 consecutive nodes; its
@@ -997,17 +1049,41 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes) void rays_adj_reduce_ker
 // adjoint launched just before (so no workgroup here writes it, and none needs an arrival counter).  Two
 // workgroups fit on a CU (eight waves per SIMD: at most 64 VGPRs), so that every workgroup of the 140^2 grid
 // is resident at once.
-__global__ __launch_bounds__(kAdjSlices * kReduceNodes, 8) void adj_reduce_tv_adam_kernel(
-    PartialSet ps, RayGeo g, const float* __restrict__ sos_in,
-    float* __restrict__ sos_out, float* __restrict__ m, float* __restrict__ v, int* __restrict__ t,
-    const unsigned char* __restrict__ mask, float lambda, float* __restrict__ loss, float lr, float b1, float b2,
-    float eps, float* __restrict__ grad_out, float v0, float* __restrict__ staged_out) {
-    __shared__ float run[kAdjSlices][kReduceNodes];
-    __shared__ float red[kAdjSlices * kReduceNodes / 64];
+struct UpdArgs {
+    PartialSet ps;
+    RayGeo g;
+    const float* sos_in;
+    float* sos_out;
+    float *m, *v;
+    int* t;
+    const unsigned char* mask;
+    float lambda;
+    float* loss;
+    float lr, b1, b2, eps;
+    float* grad_out;
+    float v0;
+    float* staged_out;
+};
+
+// The update of nodes blk * 64 .. with the LDS arrays run and red.
+__device__ __forceinline__ void adj_reduce_tv_adam_body(const UpdArgs& A, int blk, float (&run)[kAdjSlices][kReduceNodes],
+                                                        float* red) {
+    const PartialSet& ps = A.ps;
+    const RayGeo& g = A.g;
+    const float* __restrict__ sos_in = A.sos_in;
+    float* __restrict__ sos_out = A.sos_out;
+    float* __restrict__ m = A.m;
+    float* __restrict__ v = A.v;
+    const int* __restrict__ t = A.t;
+    const unsigned char* __restrict__ mask = A.mask;
+    const float lambda = A.lambda, lr = A.lr, b1 = A.b1, b2 = A.b2, eps = A.eps, v0 = A.v0;
+    float* __restrict__ loss = A.loss;
+    float* __restrict__ grad_out = A.grad_out;
+    float* __restrict__ staged_out = A.staged_out;
     const int step = t[0];          // already advanced by the adjoint launch before this one
     const int n_nodes = g.Gy * g.Gx;
     const int j = threadIdx.x % kReduceNodes, slice = threadIdx.x / kReduceNodes;
-    const int node = blockIdx.x * kReduceNodes + j;
+    const int node = blk * kReduceNodes + j;
     const bool valid = node < n_nodes;
     const bool is_free = valid && mask[node] != 0;
     // the update's own loads go out before the partial sums, so that their latency is hidden behind them
@@ -1059,6 +1135,12 @@ __global__ __launch_bounds__(kAdjSlices * kReduceNodes, 8) void adj_reduce_tv_ad
         tv = block_sum(tv, red);
         if (threadIdx.x == 0 && tv != 0.0f) atomicAdd(loss, lambda * tv);
     }
+}
+
+__global__ __launch_bounds__(kAdjSlices * kReduceNodes, 8) void adj_reduce_tv_adam_kernel(UpdArgs A) {
+    __shared__ float run[kAdjSlices][kReduceNodes];
+    __shared__ float red[kAdjSlices * kReduceNodes / 64];
+    adj_reduce_tv_adam_body(A, blockIdx.x, run, red);
 }
 
 RayGeo make_geo(const pact_grid& sosg, int n_samples, float support) {
@@ -1130,6 +1212,50 @@ int fwd_lanes_rule(int per_block, int n_samples) {
 }  // namespace
 }  // namespace pact
 
+namespace pact {
+namespace {
+
+// The forward launch of one scan (arguments already checked): its kernel arguments, workgroups and LDS bytes.
+// Two workgroups per CU, each with about the same number of rays (element-major, so about one element's rays
+// from every patch); lanes per ray: the autotuned value for this geometry, else the built-in rule; the rays'
+// order by length when it fits beside the staged grid.
+int plan_fwd(const float* sos, const float* staged, const pact_grid& sosg, float v0, const float* centres, int N,
+             const pact_ring& ring, int n_samples, float support_radius, float* w, FwdArgs* A, int* blocks,
+             size_t* lds, const char* what) {
+    const size_t grid_lds = static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2) * sizeof(float);
+    PACT_CHECK_SUPPORTED(grid_lds + kLenBuckets * sizeof(int) <= kLdsBytes, "%s: SOS grid %d x %d does not fit in LDS",
+                         what, sosg.ny, sosg.nx);
+    const long long n_rays = static_cast<long long>(N) * ring.n_elem;
+    // ray indices are split by float quotients, exact below 2^24
+    PACT_CHECK_SUPPORTED(n_rays < (1LL << 24), "%s: too many rays", what);
+    *blocks = static_cast<int>(std::min<long long>(2LL * device_cu_count(), n_rays));
+    const int per_block = ceil_div(n_rays, *blocks);
+    const int tuned = tuned_tiling(N, ring, n_samples, sosg, support_radius).fwd;
+    const int K = tuned > 0 ? tuned : fwd_lanes_rule(per_block, n_samples);
+    int log2K = 0;
+    while ((1 << log2K) < K) ++log2K;
+    PACT_CHECK_ARG((1 << log2K) == K, "%s: lanes per ray must be a power of two", what);
+    const size_t base = grid_lds + kLenBuckets * sizeof(int);
+    const size_t with_order = base + static_cast<size_t>(per_block) * sizeof(int);
+    const int sorted = with_order <= kLdsBytes ? 1 : 0;
+    *lds = sorted ? with_order : base;
+    *A = FwdArgs{sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples,
+                 make_geo(sosg, n_samples, support_radius), log2K, static_cast<int>(n_rays), per_block, sorted, w};
+    return PACT_OK;
+}
+
+void fwd_lds_attribute() {
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_fwd_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        attr = true;
+    }
+}
+
+}  // namespace
+}  // namespace pact
+
 extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, float v0, const float* centres, int N,
                                   const pact_ring* ring_, int n_samples, float support_radius, const float* staged,
                                   float* w, void* stream) {
@@ -1144,34 +1270,14 @@ extern "C" int pact_sos_to_delays(const float* sos, const pact_grid* sosg_, floa
     if (int s = check_rays(sos, sosg, v0, centres, N, ring, n_samples, support_radius, "pact_sos_to_delays"))
         return s;
     PACT_CHECK_ARG(w, "pact_sos_to_delays: null output");
-    const size_t lds = static_cast<size_t>(sosg.ny + 2) * (sosg.nx + 2) * sizeof(float);
-    PACT_CHECK_SUPPORTED(lds + kLenBuckets * sizeof(int) <= kLdsBytes,
-                         "pact_sos_to_delays: SOS grid %d x %d does not fit in LDS", sosg.ny, sosg.nx);
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_fwd_kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
-        attr = true;
-    }
-    // two workgroups per CU, each with about the same number of rays (element-major, so about one element's
-    // rays from every patch); lanes per ray: the autotuned value for this geometry, else the built-in rule
-    const long long n_rays = static_cast<long long>(N) * ring.n_elem;
-    // ray indices are split by float quotients, exact below 2^24
-    PACT_CHECK_SUPPORTED(n_rays < (1LL << 24), "pact_sos_to_delays: too many rays");
-    const int blocks = static_cast<int>(std::min<long long>(2LL * device_cu_count(), n_rays));
-    const int per_block = ceil_div(n_rays, blocks);
-    const int tuned = tuned_tiling(N, ring, n_samples, sosg, support_radius).fwd;
-    const int K = tuned > 0 ? tuned : fwd_lanes_rule(per_block, n_samples);
-    int log2K = 0;
-    while ((1 << log2K) < K) ++log2K;
-    PACT_CHECK_ARG((1 << log2K) == K, "pact_sos_to_delays: lanes per ray must be a power of two");
-    // the rays' order by length, if it fits beside the staged grid (with two workgroups per CU when it can)
-    const size_t base = lds + kLenBuckets * sizeof(int);
-    const size_t with_order = base + static_cast<size_t>(per_block) * sizeof(int);
-    const int sorted = with_order <= kLdsBytes ? 1 : 0;
-    rays_fwd_kernel<<<blocks, kThreads, sorted ? with_order : base, as_stream(stream)>>>(
-        sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support_radius),
-        log2K, static_cast<int>(n_rays), per_block, sorted, w);
+    FwdArgs A;
+    int blocks = 0;
+    size_t lds = 0;
+    if (int s = plan_fwd(sos, staged, sosg, v0, centres, N, ring, n_samples, support_radius, w, &A, &blocks, &lds,
+                         "pact_sos_to_delays"))
+        return s;
+    fwd_lds_attribute();
+    rays_fwd_kernel<<<blocks, kThreads, lds, as_stream(stream)>>>(A);
     return launch_status("pact_sos_to_delays");
 }
 
@@ -1217,28 +1323,20 @@ int adj_per_band(const AdjPlan& plan, int cus) {
 
 size_t adj_grid_lds(const pact_grid& sosg) { return adj_plan(sosg).bands ? adj_plan(sosg).lds : 0; }
 
-// The grid adjoint into one partial node grid per workgroup (rows of its band only); *ps describes them for the
-// reduction.
-int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg, float v0, const float* centres, int N,
-                    const pact_ring& ring, int n_samples, float support, const float* dL_dw, const float* scale,
-                    float* partial, size_t ws_bytes, hipStream_t st, PartialSet* ps, const char* what,
-                    int* step_counter = nullptr) {
+// The grid adjoint of one scan (arguments already checked): its kernel arguments, workgroups, LDS bytes and the
+// partial grids it leaves for the reduction (one per workgroup, rows of its band only).
+int plan_adj_grid(const float* sos, const float* staged, const pact_grid& sosg, float v0, const float* centres,
+                  int N, const pact_ring& ring, int n_samples, float support, const float* dL_dw, const float* scale,
+                  float* partial, size_t ws_bytes, int* step_counter, AdjArgs* A, int* blocks, size_t* lds,
+                  PartialSet* ps, const char* what) {
     const AdjPlan plan = adj_plan(sosg);
     const int per_band = adj_per_band(plan, device_cu_count());
-    const int blocks = plan.bands * per_band;
-    const size_t need = static_cast<size_t>(blocks) * partial_pitch(sosg.ny, sosg.nx) * sizeof(float);
+    *blocks = plan.bands * per_band;
+    const size_t need = static_cast<size_t>(*blocks) * partial_pitch(sosg.ny, sosg.nx) * sizeof(float);
     PACT_CHECK_SUPPORTED(need < (size_t{1} << 32), "%s: the adjoint's partial grids exceed 4 GiB", what);
     if (!partial || ws_bytes < need) {
         set_error("%s: workspace of %zu bytes needed, %zu given", what, need, partial ? ws_bytes : 0);
         return PACT_EWORKSPACE;
-    }
-    static bool gattr = false;
-    if (!gattr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel<false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel<true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
-        gattr = true;
     }
     const long long n_rays = static_cast<long long>(N) * ring.n_elem;
     // ray and item indices are split by float quotients, exact below 2^24
@@ -1251,17 +1349,40 @@ int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg
     // the rays in order of length, if the workgroup's list fits beside the grid arrays
     const size_t order_bytes = static_cast<size_t>(per_block) * sizeof(int);
     const int sorted = plan.lds + order_bytes <= kLdsBytes ? 1 : 0;
-    const size_t lds = plan.lds + (sorted ? order_bytes : 0);
-    if (plan.bands == 1)
-        rays_adj_grid_kernel<false><<<blocks, kGridThreads, lds, st>>>(
-            sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
-            static_cast<int>(n_rays), per_block, K, sorted, 1, sosg.ny + 1, dL_dw, scale, partial, step_counter);
-    else
-        rays_adj_grid_kernel<true><<<blocks, kGridThreads, lds, st>>>(
-            sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples, make_geo(sosg, n_samples, support),
-            static_cast<int>(n_rays), per_block, K, sorted, plan.bands, plan.band_rows, dL_dw, scale, partial,
-            step_counter);
+    *lds = plan.lds + (sorted ? order_bytes : 0);
+    *A = AdjArgs{sos, staged, v0, centres, N, ring.n_elem, ring.radius, ring.phi0, n_samples,
+                 make_geo(sosg, n_samples, support), static_cast<int>(n_rays), per_block, K, sorted, plan.bands,
+                 plan.bands == 1 ? sosg.ny + 1 : plan.band_rows, dL_dw, scale, partial, step_counter};
     *ps = PartialSet{partial, partial_pitch(sosg.ny, sosg.nx), plan.bands, plan.band_rows, per_band};
+    return PACT_OK;
+}
+
+void adj_lds_attribute() {
+    static bool gattr = false;
+    if (!gattr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel<false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_grid_kernel<true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        gattr = true;
+    }
+}
+
+int launch_adj_grid(const float* sos, const float* staged, const pact_grid& sosg, float v0, const float* centres, int N,
+                    const pact_ring& ring, int n_samples, float support, const float* dL_dw, const float* scale,
+                    float* partial, size_t ws_bytes, hipStream_t st, PartialSet* ps, const char* what,
+                    int* step_counter = nullptr) {
+    AdjArgs A;
+    int blocks = 0;
+    size_t lds = 0;
+    if (int s = plan_adj_grid(sos, staged, sosg, v0, centres, N, ring, n_samples, support, dL_dw, scale, partial,
+                              ws_bytes, step_counter, &A, &blocks, &lds, ps, what))
+        return s;
+    adj_lds_attribute();
+    if (A.n_bands == 1)
+        rays_adj_grid_kernel<false><<<blocks, kGridThreads, lds, st>>>(A);
+    else
+        rays_adj_grid_kernel<true><<<blocks, kGridThreads, lds, st>>>(A);
     return launch_status(what);
 }
 
@@ -1356,9 +1477,9 @@ extern "C" int pact_sos_adjoint_tv_adam_step(const float* sos_in, float* sos_out
                                  partial, ws_bytes, as_stream(stream), &ps, what, t))
         return st;
     const int n_nodes = sosg.ny * sosg.nx;
-    adj_reduce_tv_adam_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(
-        ps, make_geo(sosg, n_samples, support_radius), sos_in, sos_out, m, v, t, mask, lambda, loss, lr,
-        b1, b2, eps, grad, v0, staged_out);
+    const UpdArgs U{ps, make_geo(sosg, n_samples, support_radius), sos_in, sos_out, m, v, t, mask, lambda, loss, lr,
+                    b1, b2, eps, grad, v0, staged_out};
+    adj_reduce_tv_adam_kernel<<<ceil_div(n_nodes, kReduceNodes), kAdjSlices * kReduceNodes, 0, as_stream(stream)>>>(U);
     return launch_status(what);
 }
 
@@ -1474,3 +1595,131 @@ extern "C" int pact_stage_contrast(const float* sos, const pact_grid* sosg_, flo
     stage_kernel<<<ceil_div(n, 256), 256, 0, as_stream(stream)>>>(sos, v0, make_geo(sosg, 1, support_radius), staged);
     return launch_status("pact_stage_contrast");
 }
+
+// ---- Batched step: the ray stages of many scans, one launch each ----
+//
+// Every workgroup finds its scan in the launch's block ranges and runs that scan's block with the scan's own
+// block number and count, so each scan's work is split exactly as in its own launch (the same rays per
+// workgroup, lanes per ray, length order, fixed-point scales and partial grids) and its results are the same.
+// A launch's dynamic LDS is the largest any of its scans needs.  Forward and adjoint ranges start on multiples
+// of 8 blocks, so that the XCD-aware numbering of each scan sees the hardware's dealing of blocks to XCDs.
+
+namespace pact {
+namespace {
+
+struct RayBatchDesc {
+    FwdArgs fwd;
+    AdjArgs adj;
+    UpdArgs upd;
+    int blocks[3];      // forward, adjoint, update
+};
+
+// Scan of this workgroup: the last s with starts[s] <= blockIdx.x (uniform across the workgroup).
+__device__ __forceinline__ int batch_scan_of(const int* __restrict__ starts, int n) {
+    const int b = static_cast<int>(blockIdx.x);
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void rays_fwd_batch_kernel(const RayBatchDesc* __restrict__ d,
+                                                                  const int* __restrict__ starts, int n) {
+    extern __shared__ float vs[];
+    const int s = batch_scan_of(starts, n);
+    const int b = static_cast<int>(blockIdx.x) - starts[s];
+    if (b >= d[s].blocks[0]) return;            // padding to the next multiple of 8
+    rays_fwd_body(d[s].fwd, b, d[s].blocks[0], vs);
+}
+
+__global__ __launch_bounds__(kGridThreads) void rays_adj_batch_kernel(const RayBatchDesc* __restrict__ d,
+                                                                      const int* __restrict__ starts, int n) {
+    extern __shared__ float lds[];
+    const int s = batch_scan_of(starts, n);
+    const int b = static_cast<int>(blockIdx.x) - starts[s];
+    if (b >= d[s].blocks[1]) return;
+    if (d[s].adj.n_bands == 1)
+        rays_adj_grid_body<false>(d[s].adj, b, d[s].blocks[1], lds);
+    else
+        rays_adj_grid_body<true>(d[s].adj, b, d[s].blocks[1], lds);
+}
+
+__global__ __launch_bounds__(kAdjSlices * kReduceNodes, 8) void adj_update_batch_kernel(
+    const RayBatchDesc* __restrict__ d, const int* __restrict__ starts, int n, int with_loss) {
+    __shared__ float run[kAdjSlices][kReduceNodes];
+    __shared__ float red[kAdjSlices * kReduceNodes / 64];
+    const int s = batch_scan_of(starts, n);
+    const int b = static_cast<int>(blockIdx.x) - starts[s];
+    if (b >= d[s].blocks[2]) return;
+    UpdArgs A = d[s].upd;
+    if (!with_loss) A.loss = nullptr;
+    adj_reduce_tv_adam_body(A, b, run, red);
+}
+
+void batch_lds_attributes() {
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_fwd_batch_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(rays_adj_batch_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        attr = true;
+    }
+}
+
+}  // namespace
+
+size_t batch_ray_desc_bytes() { return sizeof(RayBatchDesc); }
+
+int batch_ray_plan(const pact_batch_scan& s, int parity, void* desc, int blocks[3], size_t lds[3], const char* what) {
+    const float* sos_in = s.sos[parity];
+    float* sos_out = s.sos[1 - parity];
+    const float* st_in = s.staged[parity];
+    float* st_out = s.staged[1 - parity];
+    if (int e = check_rays(sos_in, s.sosg, s.v0, s.centres, s.N, s.ring, s.n_samples, s.support_radius, what))
+        return e;
+    PACT_CHECK_ARG(sos_out && st_in && st_out && s.m && s.v && s.t && s.mask && s.w && s.dL_dw,
+                   "%s: null pointer", what);
+    PACT_CHECK_ARG(sos_in != sos_out && st_in != st_out, "%s: the two SOS (and staged) buffers must differ", what);
+    PACT_CHECK_ARG(std::isfinite(s.lambda), "%s: lambda must be finite", what);
+    PACT_CHECK_ARG(s.b1 >= 0.0f && s.b1 < 1.0f && s.b2 >= 0.0f && s.b2 < 1.0f, "%s: betas must be in [0, 1)", what);
+    PACT_CHECK_ARG(s.adam_eps > 0.0f && std::isfinite(s.lr), "%s: adam_eps must be positive and lr finite", what);
+    PACT_CHECK_SUPPORTED(adj_grid_lds(s.sosg) > 0, "%s: the %d x %d grid takes the tiled adjoint", what, s.sosg.ny,
+                         s.sosg.nx);
+    RayBatchDesc D;
+    if (int e = plan_fwd(sos_in, st_in, s.sosg, s.v0, s.centres, s.N, s.ring, s.n_samples, s.support_radius, s.w,
+                         &D.fwd, &blocks[0], &lds[0], what))
+        return e;
+    PartialSet ps;
+    if (int e = plan_adj_grid(sos_in, st_in, s.sosg, s.v0, s.centres, s.N, s.ring, s.n_samples, s.support_radius,
+                              s.dL_dw, nullptr, s.partial, s.partial_bytes, s.t, &D.adj, &blocks[1], &lds[1], &ps,
+                              what))
+        return e;
+    D.upd = UpdArgs{ps, make_geo(s.sosg, s.n_samples, s.support_radius), sos_in, sos_out, s.m, s.v, s.t, s.mask,
+                    s.lambda, s.loss, s.lr, s.b1, s.b2, s.adam_eps, s.grad, s.v0, st_out};
+    blocks[2] = ceil_div(s.sosg.ny * s.sosg.nx, kReduceNodes);
+    lds[2] = 0;
+    for (int k = 0; k < 3; ++k) D.blocks[k] = blocks[k];
+    std::memcpy(desc, &D, sizeof D);
+    return PACT_OK;
+}
+
+int batch_ray_launch(int stage, const void* descs, const int* starts, int n, int total, size_t lds, int with_loss,
+                     hipStream_t st) {
+    const auto* d = static_cast<const RayBatchDesc*>(descs);
+    batch_lds_attributes();
+    if (stage == 0)
+        rays_fwd_batch_kernel<<<total, kThreads, lds, st>>>(d, starts, n);
+    else if (stage == 1)
+        rays_adj_batch_kernel<<<total, kGridThreads, lds, st>>>(d, starts, n);
+    else
+        adj_update_batch_kernel<<<total, kAdjSlices * kReduceNodes, 0, st>>>(d, starts, n, with_loss);
+    return launch_status("pact_batch_step (rays)");
+}
+
+}  // namespace pact

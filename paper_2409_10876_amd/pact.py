@@ -35,6 +35,19 @@ class Patches(ctypes.Structure):
 
 
 _P = ctypes.c_void_p
+
+
+class BatchScan(ctypes.Structure):
+    """pact_batch_scan (include/pact.h): one scan of a batched solve."""
+    _fields_ = [("sosg", Grid), ("ring", Ring), ("N", ctypes.c_int), ("M", ctypes.c_int), ("P", ctypes.c_int),
+                ("n_samples", ctypes.c_int), ("px", ctypes.c_float), ("v0", ctypes.c_float),
+                ("support_radius", ctypes.c_float), ("eps", ctypes.c_float), ("lam", ctypes.c_float),
+                ("lr", ctypes.c_float), ("b1", ctypes.c_float), ("b2", ctypes.c_float), ("adam_eps", ctypes.c_float),
+                ("centres", ctypes.c_void_p), ("T", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("dL_dw", ctypes.c_void_p), ("patch_loss", ctypes.c_void_p), ("loss", ctypes.c_void_p),
+                ("sos", ctypes.c_void_p * 2), ("staged", ctypes.c_void_p * 2), ("m", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("t", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("grad", ctypes.c_void_p),
+                ("partial", ctypes.c_void_p), ("partial_bytes", ctypes.c_size_t)]
 # geometry structs are passed by pointer (passing small float-bearing structs by value through libffi is not
 # reliable); ctypes applies byref() to a struct instance given for a POINTER argument
 _PRING = ctypes.POINTER(Ring)
@@ -45,6 +58,10 @@ _F = ctypes.c_float
 _Z = ctypes.c_size_t
 
 _SIGS = {
+    "pact_batch_plan_bytes": (_Z, [_I]),
+    "pact_batch_table_bytes": (_Z, [_I]),
+    "pact_batch_plan": (_I, [_P, _I, _P, _Z, _P, _Z, _P]),
+    "pact_batch_step": (_I, [_P, _I, _I, _P]),
     "pact_last_error": (ctypes.c_char_p, []),
     "pact_version": (_I, []),
     "pact_patch_count": (_I, [_PGRID, _PPATCH, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -693,3 +710,25 @@ def ricker_channels(w, sources, amp, sigma, g: Geometry, v0, n_t, fs, t0=0.0, ou
                                        v0, n_t, fs, t0, _ptr(out, F32, "S", g.n_elem * n_t), _stream()),
            "pact_ricker_channels")
     return out
+
+
+# ---- batched solves: one launch per stage over many scans ----
+
+def batch_plan(scans):
+    """Plan a batched step over `scans` (a ctypes array of BatchScan): returns (host plan buffer, device table)."""
+    n = len(scans)
+    lib = load()
+    plan = ctypes.create_string_buffer(int(lib.pact_batch_plan_bytes(n)))
+    nb = int(lib.pact_batch_table_bytes(n))
+    if nb == 0:
+        raise PactError(f"pact_batch_table_bytes: {n} scans not supported")
+    table = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    _check(lib.pact_batch_plan(ctypes.cast(scans, ctypes.c_void_p), n, ctypes.cast(plan, ctypes.c_void_p), len(plan),
+                               _ptr(table, name="table"), nb, _stream()), "pact_batch_plan")
+    return plan, table
+
+
+def batch_step(plan, parity, with_loss=True):
+    _check(load().pact_batch_step(ctypes.cast(plan, ctypes.c_void_p), int(parity), int(bool(with_loss)), _stream()),
+           "pact_batch_step")
+

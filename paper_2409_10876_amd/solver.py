@@ -424,3 +424,85 @@ class BatchedSolver:
         """The same work, one scan after another on the current stream (the reference for the overlap)."""
         for s in self.solvers:
             s.run(steps)
+
+
+class GroupedBatchSolver:
+    """Independent scans advanced together with one launch per stage over all scans (pact_batch_step): five
+    launches per step for the whole batch instead of five per scan.  Each scan keeps its own buffers (those of
+    its PixelGridSolver) and the partition of work it has alone, so its states equal, bit for bit, those it
+    reaches alone.  Every scan must take the whole-grid or banded adjoint."""
+
+    def __init__(self, solvers, graph_steps: int = 10, autotune: bool = False):
+        self.solvers = list(solvers)
+        self.graph_steps = graph_steps
+        if any(s.ws_adj_bytes == 0 for s in self.solvers):
+            raise ValueError("a scan takes the tiled adjoint, which the batched step does not run")
+        # ray tilings timed per scan shape before the plan records them
+        self.tilings = [s.autotune() for s in self.solvers] if autotune else None
+        for s in self.solvers:               # every scan starts on its buffer 0 (the plan's parity 0)
+            if s._cur != 0:
+                s._bufs[0].copy_(s._bufs[s._cur])
+                s._staged[0].copy_(s._staged[s._cur])
+                s._cur = 0
+        self.scans = (pact.BatchScan * len(self.solvers))()
+        for k, s in enumerate(self.solvers):
+            self.scans[k] = self._describe(s)
+        self.plan, self.table = pact.batch_plan(self.scans)
+        self.parity = 0
+        self.graph = None
+        self.step()
+        torch.cuda.synchronize()
+        self.capture(graph_steps)
+        torch.cuda.synchronize()
+
+    @staticmethod
+    def _describe(s: "PixelGridSolver") -> "pact.BatchScan":
+        g, sd = s.g, s.scan
+        ptr = lambda t: t.data_ptr()  # noqa: E731
+        d = pact.BatchScan()
+        d.sosg, d.ring = g.sosg, g.ring
+        d.N, d.M, d.P, d.n_samples = sd.centres.shape[0], sd.M, g.P, s.n_samples
+        d.px, d.v0, d.support_radius, d.eps = g.px, sd.v0, s.support, s.eps
+        d.lam, d.lr, d.b1, d.b2, d.adam_eps = s.lam, s.lr, s.b1, s.b2, s.adam_eps
+        d.centres, d.T, d.w, d.dL_dw = ptr(sd.centres), ptr(sd.T), ptr(s.w), ptr(s.gw)
+        d.patch_loss, d.loss = ptr(s.ws_loss), ptr(s.loss)
+        d.sos[0], d.sos[1] = ptr(s._bufs[0]), ptr(s._bufs[1])
+        d.staged[0], d.staged[1] = ptr(s._staged[0]), ptr(s._staged[1])
+        d.m, d.v, d.t, d.mask, d.grad = ptr(s.m), ptr(s.v), ptr(s.t), ptr(s.mask), ptr(s.grad)
+        d.partial, d.partial_bytes = ptr(s.ws_adj), s.ws_adj.numel()
+        return d
+
+    def step(self, with_loss: bool = True):
+        """One step of every scan, enqueued on the current stream."""
+        pact.batch_step(self.plan, self.parity, with_loss)
+        self.parity ^= 1
+        for s in self.solvers:
+            s._cur = self.parity
+
+    def capture(self, steps: int):
+        """Capture `steps` (even) batched steps into one HIP graph; the scalar losses on the last step only."""
+        if steps % 2:
+            raise ValueError("capture an even number of steps (the SOS buffers alternate)")
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        p0 = self.parity
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(g, stream=st):
+                for k in range(steps):
+                    self.step(with_loss=k == steps - 1)
+        torch.cuda.current_stream().wait_stream(st)
+        self.parity = p0                      # capturing does not run the steps
+        for s in self.solvers:
+            s._cur = p0
+        self.graph = g
+        return g
+
+    def run(self, steps: int):
+        """Advance every scan by `steps` steps (graph replays where the captured graph divides the count)."""
+        if self.graph is not None and steps % self.graph_steps == 0:
+            for _ in range(steps // self.graph_steps):
+                self.graph.replay()
+        else:
+            for _ in range(steps):
+                self.step()

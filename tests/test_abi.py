@@ -166,3 +166,42 @@ def test_nf_activation_buffer_too_small(P):
     s, msg = _status(P, "pact_nf_sos_to_delays", FAKE, FAKE, FAKE, 128, 128, 0.15, 26.0, 1.5, FAKE, 169, ring, 256,
                      FAKE, FAKE, need - 1, None)
     assert s == -3 and "activation buffer" in msg
+
+
+def test_batch_scan_layout_matches_the_header(P, tmp_path):
+    """The binding's pact_batch_scan has the C layout (offsets from a host program compiled against the
+    header)."""
+    import shutil
+    import subprocess
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    bs = P.pact.BatchScan
+    names = [f[0] for f in bs._fields_]
+    c_names = ["lambda" if n == "lam" else n for n in names]
+    src = tmp_path / "layout.cpp"
+    src.write_text('#include <cstddef>\n#include <cstdio>\n#include "pact.h"\nint main() {\n'
+                   '  printf("%zu\\n", sizeof(pact_batch_scan));\n' +
+                   "".join(f'  printf("%zu\\n", offsetof(pact_batch_scan, {n}));\n' for n in c_names) + "}\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cxx, "-I", include, str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(bs)
+    assert got[1:] == [getattr(bs, n).offset for n in names]
+
+
+def test_batch_argument_errors(P):
+    lib = P.pact.load()
+    plan = ctypes.create_string_buffer(int(lib.pact_batch_plan_bytes(1)))
+    assert lib.pact_batch_table_bytes(0) == 0 and lib.pact_batch_table_bytes(257) == 0
+    assert lib.pact_batch_table_bytes(32) > 0
+    s = lib.pact_batch_plan(None, 1, plan, len(plan), FAKE, 1 << 20, None)
+    assert s == -1 and "null" in lib.pact_last_error().decode()
+    scans = (P.pact.BatchScan * 1)()
+    s = lib.pact_batch_plan(ctypes.cast(scans, ctypes.c_void_p), 300, plan, len(plan), FAKE, 1 << 20, None)
+    assert s == -4 and "256" in lib.pact_last_error().decode()
+    # a buffer that pact_batch_plan did not fill is refused before anything is launched
+    s = lib.pact_batch_step(plan, 0, 1, None)
+    assert s == -1 and "plan" in lib.pact_last_error().decode()
+

@@ -4,8 +4,8 @@
 takes two bands (576^2, 15 delays).  For each, one optimisation step at a random SOS is held to the oracle on
 sampled patches, in the launch configuration of the batched solver (support disc, staged contrast, autotuned ray
 tiling): the patch spectra from the channel data, the wavefront errors, dL/dw of the fused loss, and the ray
-adjoint of those patches' dL/dw.  Then the three scans solved together (graphs on their own streams) reach,
-bit for bit, the states they reach alone."""
+adjoint of those patches' dL/dw.  Then the three scans solved together (graphs on their own streams, or one
+launch per stage over all three) reach, bit for bit, the states they reach alone."""
 import numpy as np
 import pytest
 import torch
@@ -95,10 +95,14 @@ def test_batch_scan_step_matches_oracle(lib, k):
     assert ew < TOL_DELAYS and eg < TOL_GRAD and ea < TOL_GRAD
 
 
-def test_batch_of_real_size_scans_matches_solo(lib):
+@pytest.mark.parametrize("form", ["streams", "grouped"])
+def test_batch_of_real_size_scans_matches_solo(lib, form):
+    """The three scans solved together (their step graphs on their own streams, or one launch per stage over all
+    three) reach the states they reach alone, bit for bit."""
     P = lib
-    announce("batched workload: three real-size scans together vs alone")
-    batch = P.BatchedSolver([_setup(P, k)[3] for k in PICKS], graph_steps=2, autotune=True)
+    announce(f"batched workload: three real-size scans together ({form}) vs alone")
+    cls = P.BatchedSolver if form == "streams" else P.GroupedBatchSolver
+    batch = cls([_setup(P, k)[3] for k in PICKS], graph_steps=2, autotune=True)
     solo = [_setup(P, k)[3] for k in PICKS]
     for s in solo:
         s.step()                                  # the batch ran one eager step before capturing

@@ -53,3 +53,24 @@ def test_batched_matches_solo(lib):
     for a, b in zip(batch.solvers, solo):
         assert a.t.tolist() == b.t.tolist() == [9, 0]
         assert torch.equal(a.sos, b.sos)
+
+
+def test_grouped_launches_match_solo(lib):
+    """One launch per stage over all scans (pact_batch_step) reaches each scan's solo state, bit for bit; the
+    scalar loss of the last step too."""
+    announce("grouped batched step vs solo")
+    scans = _scans()
+    grouped = lib.GroupedBatchSolver(_solvers(lib, scans), graph_steps=4)
+    solo = _solvers(lib, scans)
+    for s in solo:
+        s.step()                                  # the grouped solver ran one eager step before capturing
+    grouped.run(8)
+    torch.cuda.synchronize()
+    for s in solo:
+        s.run(8)
+    torch.cuda.synchronize()
+    for a, b in zip(grouped.solvers, solo):
+        assert a.t.tolist() == b.t.tolist() == [9, 0]
+        assert torch.equal(a.sos, b.sos) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+        assert torch.equal(a.w, b.w) and torch.equal(a.gw, b.gw)
+        assert abs(a.loss.item() - b.loss.item()) <= 1e-6 * abs(b.loss.item())   # TV's float atomics aside
