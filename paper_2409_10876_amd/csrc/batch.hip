@@ -4,6 +4,7 @@
 // ranges, and the largest LDS each launch needs.
 #include "common.h"
 
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -13,24 +14,31 @@ namespace {
 constexpr unsigned kPlanMagic = 0x50424154u;     // "PBAT"
 constexpr int kMaxBatch = 256;
 
-enum Stage { kFwd = 0, kLoss, kSum, kAdj, kUpd, kStages };
+// The launches of one batched step, in order.  The two ray stages are split by the LDS their scans' workgroups
+// need: scans whose workgroups fit twice in a CU's LDS (smaller SOS grids) run in a launch of their own, whose
+// LDS then lets two workgroups share a CU; one launch has one LDS size, so mixed with the large grids they would
+// run one per CU.  The large-grid launch goes first.  Within a launch, scans come in order of decreasing work per
+// workgroup, so the longest workgroups are dispatched first.
+enum Launch { kFwdLarge = 0, kFwdSmall, kLoss, kSum, kAdjLarge, kAdjSmall, kUpd, kLaunches };
 
 // The host part of a plan (the caller's HOST buffer).
 struct BatchPlan {
     unsigned magic;
     int n;
-    const char* table;          // DEVICE
-    size_t off_ray[2];          // ray descriptors of parity 0 and 1
-    size_t off_loss;            // loss descriptors
-    size_t off_starts[kStages]; // block ranges of each stage: n + 1 ints
-    int total[kStages];         // blocks of each launch
-    size_t lds[kStages];        // dynamic LDS of each launch
+    const char* table;              // DEVICE
+    size_t off_ray[2];              // ray descriptors of parity 0 and 1
+    size_t off_loss;                // loss descriptors
+    size_t off_starts[kLaunches];   // each launch's block ranges: count + 1 ints
+    size_t off_ids[kLaunches];      // each launch's scans: count ints
+    int count[kLaunches];           // scans in each launch
+    int total[kLaunches];           // blocks of each launch
+    size_t lds[kLaunches];          // dynamic LDS of each launch
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct TableLayout {
-    size_t off_ray[2], off_loss, off_starts[kStages], bytes;
+    size_t off_ray[2], off_loss, off_starts[kLaunches], off_ids[kLaunches], bytes;
 };
 
 TableLayout layout(int n) {
@@ -42,13 +50,23 @@ TableLayout layout(int n) {
     }
     L.off_loss = o;
     o = align256(o + static_cast<size_t>(n) * batch_loss_desc_bytes());
-    for (int k = 0; k < kStages; ++k) {
+    for (int k = 0; k < kLaunches; ++k) {
         L.off_starts[k] = o;
         o = align256(o + static_cast<size_t>(n + 1) * sizeof(int));
+        L.off_ids[k] = o;
+        o = align256(o + static_cast<size_t>(n) * sizeof(int));
     }
     L.bytes = o;
     return L;
 }
+
+struct ScanStages {
+    int blocks[3];          // forward, adjoint, update
+    size_t lds[3];
+    int loss_blocks;
+    size_t loss_lds;
+    double work[2];         // forward and adjoint work per workgroup (ray samples)
+};
 
 }  // namespace
 }  // namespace pact
@@ -83,37 +101,70 @@ extern "C" int pact_batch_plan(const pact_batch_scan* scans, int n_scans, void* 
     P.magic = kPlanMagic;
     P.n = n_scans;
     P.table = static_cast<const char*>(table);
-    int* starts[kStages];
-    for (int k = 0; k < kStages; ++k) {
-        P.off_starts[k] = L.off_starts[k];
-        starts[k] = reinterpret_cast<int*>(host.data() + L.off_starts[k]);
-        starts[k][0] = 0;
-    }
     for (int p = 0; p < 2; ++p) P.off_ray[p] = L.off_ray[p];
     P.off_loss = L.off_loss;
+    std::vector<ScanStages> st(n_scans);
     for (int s = 0; s < n_scans; ++s) {
-        int rb[3] = {0, 0, 0};
-        size_t rl[3] = {0, 0, 0};
+        ScanStages& S = st[s];
         for (int p = 0; p < 2; ++p) {
             void* d = host.data() + L.off_ray[p] + static_cast<size_t>(s) * batch_ray_desc_bytes();
-            if (int e = batch_ray_plan(scans[s], p, d, rb, rl, what)) return e;
+            if (int e = batch_ray_plan(scans[s], p, d, S.blocks, S.lds, what)) return e;
         }
-        int lb = 0;
-        size_t ll = 0;
         if (int e = batch_loss_plan(scans[s], host.data() + L.off_loss + static_cast<size_t>(s) * batch_loss_desc_bytes(),
-                                    &lb, &ll, what))
+                                    &S.loss_blocks, &S.loss_lds, what))
             return e;
-        // forward and adjoint ranges start on multiples of 8 blocks (the XCD-aware numbering of each scan)
-        starts[kFwd][s + 1] = starts[kFwd][s] + ceil_div(rb[0], 8) * 8;
-        starts[kAdj][s + 1] = starts[kAdj][s] + ceil_div(rb[1], 8) * 8;
-        starts[kUpd][s + 1] = starts[kUpd][s] + rb[2];
-        starts[kLoss][s + 1] = starts[kLoss][s] + lb;
-        starts[kSum][s + 1] = s + 1;
-        P.lds[kFwd] = std::max(P.lds[kFwd], rl[0]);
-        P.lds[kAdj] = std::max(P.lds[kAdj], rl[1]);
-        P.lds[kLoss] = std::max(P.lds[kLoss], ll);
+        const double samples = static_cast<double>(scans[s].N) * scans[s].ring.n_elem * scans[s].n_samples;
+        S.work[0] = samples / S.blocks[0];
+        S.work[1] = samples / S.blocks[1];
     }
-    for (int k = 0; k < kStages; ++k) P.total[k] = starts[k][n_scans];
+    // the scans of each launch, in order of decreasing work per workgroup
+    std::vector<int> members[kLaunches];
+    for (int s = 0; s < n_scans; ++s) {
+        const bool fwd_small = 2 * st[s].lds[0] <= kLdsBytes, adj_small = 2 * st[s].lds[1] <= kLdsBytes;
+        members[fwd_small ? kFwdSmall : kFwdLarge].push_back(s);
+        members[adj_small ? kAdjSmall : kAdjLarge].push_back(s);
+        members[kLoss].push_back(s);
+        members[kSum].push_back(s);
+        members[kUpd].push_back(s);
+    }
+    for (int k : {kFwdLarge, kFwdSmall, kAdjLarge, kAdjSmall}) {
+        const int w = (k == kFwdLarge || k == kFwdSmall) ? 0 : 1;
+        std::stable_sort(members[k].begin(), members[k].end(),
+                         [&](int a, int b) { return st[a].work[w] > st[b].work[w]; });
+    }
+    for (int k = 0; k < kLaunches; ++k) {
+        P.off_starts[k] = L.off_starts[k];
+        P.off_ids[k] = L.off_ids[k];
+        int* starts = reinterpret_cast<int*>(host.data() + L.off_starts[k]);
+        int* ids = reinterpret_cast<int*>(host.data() + L.off_ids[k]);
+        starts[0] = 0;
+        size_t lds = 0;
+        for (size_t q = 0; q < members[k].size(); ++q) {
+            const int s = members[k][q];
+            ids[q] = s;
+            int blocks = 0;
+            switch (k) {
+                case kFwdLarge: case kFwdSmall:   // ray ranges start on multiples of 8 (XCD-aware numbering)
+                    blocks = ceil_div(st[s].blocks[0], 8) * 8;
+                    lds = std::max(lds, st[s].lds[0]);
+                    break;
+                case kAdjLarge: case kAdjSmall:
+                    blocks = ceil_div(st[s].blocks[1], 8) * 8;
+                    lds = std::max(lds, st[s].lds[1]);
+                    break;
+                case kLoss:
+                    blocks = st[s].loss_blocks;
+                    lds = std::max(lds, st[s].loss_lds);
+                    break;
+                case kSum: blocks = 1; break;
+                default: blocks = st[s].blocks[2]; break;
+            }
+            starts[q + 1] = starts[q] + blocks;
+        }
+        P.count[k] = static_cast<int>(members[k].size());
+        P.total[k] = starts[P.count[k]];
+        P.lds[k] = lds;
+    }
     // the table is small (a few hundred bytes per scan): a synchronous copy, after the stream's earlier work
     if (hipStreamSynchronize(as_stream(stream)) != hipSuccess ||
         hipMemcpy(table, host.data(), L.bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -134,13 +185,19 @@ extern "C" int pact_batch_step(const void* plan, int parity, int with_loss, void
     PACT_CHECK_ARG(P.magic == kPlanMagic && P.n > 0, "%s: not a plan made by pact_batch_plan", what);
     PACT_CHECK_ARG(parity == 0 || parity == 1, "%s: parity must be 0 or 1", what);
     const hipStream_t st = as_stream(stream);
-    const auto start = [&](int k) { return reinterpret_cast<const int*>(P.table + P.off_starts[k]); };
+    const auto starts = [&](int k) { return reinterpret_cast<const int*>(P.table + P.off_starts[k]); };
+    const auto ids = [&](int k) { return reinterpret_cast<const int*>(P.table + P.off_ids[k]); };
     const void* rays = P.table + P.off_ray[parity];
     const void* loss = P.table + P.off_loss;
-    if (int e = batch_ray_launch(0, rays, start(kFwd), P.n, P.total[kFwd], P.lds[kFwd], 0, st)) return e;
-    if (int e = batch_loss_launch(0, loss, start(kLoss), P.n, P.total[kLoss], P.lds[kLoss], st)) return e;
+    for (int k : {kFwdLarge, kFwdSmall})
+        if (P.count[k] > 0)
+            if (int e = batch_ray_launch(0, rays, starts(k), ids(k), P.count[k], P.total[k], P.lds[k], 0, st)) return e;
+    if (int e = batch_loss_launch(0, loss, starts(kLoss), ids(kLoss), P.count[kLoss], P.total[kLoss], P.lds[kLoss], st))
+        return e;
     if (with_loss)
-        if (int e = batch_loss_launch(1, loss, start(kSum), P.n, P.n, 0, st)) return e;
-    if (int e = batch_ray_launch(1, rays, start(kAdj), P.n, P.total[kAdj], P.lds[kAdj], 0, st)) return e;
-    return batch_ray_launch(2, rays, start(kUpd), P.n, P.total[kUpd], 0, with_loss, st);
+        if (int e = batch_loss_launch(1, loss, starts(kSum), ids(kSum), P.count[kSum], P.total[kSum], 0, st)) return e;
+    for (int k : {kAdjLarge, kAdjSmall})
+        if (P.count[k] > 0)
+            if (int e = batch_ray_launch(1, rays, starts(k), ids(k), P.count[k], P.total[k], P.lds[k], 0, st)) return e;
+    return batch_ray_launch(2, rays, starts(kUpd), ids(kUpd), P.count[kUpd], P.total[kUpd], 0, with_loss, st);
 }

@@ -52,14 +52,16 @@ int check_grid(const pact_grid& g, const char* what);
 
 // Batched solves (pact_batch_plan / pact_batch_step): each source file plans and launches its own stages of
 // the grouped step.  Descriptors are written to host memory by the plan functions and read on the device from
-// the table; starts[s] is the first block of scan s in a stage's launch (starts[n] = the launch's blocks).
+// the table.  A launch covers n scans: starts[q] is the first block of its q-th scan (starts[n] = the launch's
+// blocks) and ids[q] that scan's descriptor.
 size_t batch_ray_desc_bytes();
 int batch_ray_plan(const pact_batch_scan& s, int parity, void* desc, int blocks[3], size_t lds[3], const char* what);
-int batch_ray_launch(int stage, const void* descs, const int* starts, int n, int total, size_t lds, int with_loss,
-                     hipStream_t st);
+int batch_ray_launch(int stage, const void* descs, const int* starts, const int* ids, int n, int total, size_t lds,
+                     int with_loss, hipStream_t st);
 size_t batch_loss_desc_bytes();
 int batch_loss_plan(const pact_batch_scan& s, void* desc, int* blocks, size_t* lds, const char* what);
-int batch_loss_launch(int stage, const void* descs, const int* starts, int n, int total, size_t lds, hipStream_t st);
+int batch_loss_launch(int stage, const void* descs, const int* starts, const int* ids, int n, int total, size_t lds,
+                      hipStream_t st);
 
 // ------------------------------------------------------------- device ---
 

@@ -1614,7 +1614,8 @@ struct RayBatchDesc {
     int blocks[3];      // forward, adjoint, update
 };
 
-// Scan of this workgroup: the last s with starts[s] <= blockIdx.x (uniform across the workgroup).
+// Position of this workgroup's scan in a launch: the last s with starts[s] <= blockIdx.x (uniform across the
+// workgroup); ids[s] is that scan's descriptor.
 __device__ __forceinline__ int batch_scan_of(const int* __restrict__ starts, int n) {
     const int b = static_cast<int>(blockIdx.x);
     int lo = 0, hi = n - 1;
@@ -1629,19 +1630,21 @@ __device__ __forceinline__ int batch_scan_of(const int* __restrict__ starts, int
 }
 
 __global__ __launch_bounds__(kThreads) void rays_fwd_batch_kernel(const RayBatchDesc* __restrict__ d,
-                                                                  const int* __restrict__ starts, int n) {
+                                                                  const int* __restrict__ starts,
+                                                                  const int* __restrict__ ids, int n) {
     extern __shared__ float vs[];
-    const int s = batch_scan_of(starts, n);
-    const int b = static_cast<int>(blockIdx.x) - starts[s];
+    const int q = batch_scan_of(starts, n), s = ids[q];
+    const int b = static_cast<int>(blockIdx.x) - starts[q];
     if (b >= d[s].blocks[0]) return;            // padding to the next multiple of 8
     rays_fwd_body(d[s].fwd, b, d[s].blocks[0], vs);
 }
 
 __global__ __launch_bounds__(kGridThreads) void rays_adj_batch_kernel(const RayBatchDesc* __restrict__ d,
-                                                                      const int* __restrict__ starts, int n) {
+                                                                      const int* __restrict__ starts,
+                                                                      const int* __restrict__ ids, int n) {
     extern __shared__ float lds[];
-    const int s = batch_scan_of(starts, n);
-    const int b = static_cast<int>(blockIdx.x) - starts[s];
+    const int q = batch_scan_of(starts, n), s = ids[q];
+    const int b = static_cast<int>(blockIdx.x) - starts[q];
     if (b >= d[s].blocks[1]) return;
     if (d[s].adj.n_bands == 1)
         rays_adj_grid_body<false>(d[s].adj, b, d[s].blocks[1], lds);
@@ -1650,11 +1653,12 @@ __global__ __launch_bounds__(kGridThreads) void rays_adj_batch_kernel(const RayB
 }
 
 __global__ __launch_bounds__(kAdjSlices * kReduceNodes, 8) void adj_update_batch_kernel(
-    const RayBatchDesc* __restrict__ d, const int* __restrict__ starts, int n, int with_loss) {
+    const RayBatchDesc* __restrict__ d, const int* __restrict__ starts, const int* __restrict__ ids, int n,
+    int with_loss) {
     __shared__ float run[kAdjSlices][kReduceNodes];
     __shared__ float red[kAdjSlices * kReduceNodes / 64];
-    const int s = batch_scan_of(starts, n);
-    const int b = static_cast<int>(blockIdx.x) - starts[s];
+    const int q = batch_scan_of(starts, n), s = ids[q];
+    const int b = static_cast<int>(blockIdx.x) - starts[q];
     if (b >= d[s].blocks[2]) return;
     UpdArgs A = d[s].upd;
     if (!with_loss) A.loss = nullptr;
@@ -1709,16 +1713,16 @@ int batch_ray_plan(const pact_batch_scan& s, int parity, void* desc, int blocks[
     return PACT_OK;
 }
 
-int batch_ray_launch(int stage, const void* descs, const int* starts, int n, int total, size_t lds, int with_loss,
-                     hipStream_t st) {
+int batch_ray_launch(int stage, const void* descs, const int* starts, const int* ids, int n, int total, size_t lds,
+                     int with_loss, hipStream_t st) {
     const auto* d = static_cast<const RayBatchDesc*>(descs);
     batch_lds_attributes();
     if (stage == 0)
-        rays_fwd_batch_kernel<<<total, kThreads, lds, st>>>(d, starts, n);
+        rays_fwd_batch_kernel<<<total, kThreads, lds, st>>>(d, starts, ids, n);
     else if (stage == 1)
-        rays_adj_batch_kernel<<<total, kGridThreads, lds, st>>>(d, starts, n);
+        rays_adj_batch_kernel<<<total, kGridThreads, lds, st>>>(d, starts, ids, n);
     else
-        adj_update_batch_kernel<<<total, kAdjSlices * kReduceNodes, 0, st>>>(d, starts, n, with_loss);
+        adj_update_batch_kernel<<<total, kAdjSlices * kReduceNodes, 0, st>>>(d, starts, ids, n, with_loss);
     return launch_status("pact_batch_step (rays)");
 }
 
