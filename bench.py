@@ -554,13 +554,17 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
     t0 = time.perf_counter()
     batch = P.BatchedSolver(solvers, graph_steps=graph_steps, autotune=True)
     print(f"[bench] batch: ray tilings autotuned per scan shape in {time.perf_counter() - t0:.1f} s", flush=True)
-    grouped = P.GroupedBatchSolver(solvers, graph_steps=graph_steps)     # the same scans' buffers
+    # one launch per stage over all scans, and over each of 2 and 4 groups of scans on their own streams
+    grouped = {g: P.GroupedBatchSolver(solvers, graph_steps=graph_steps, groups=g) for g in (1, 2, 4)}
     batch.run(graph_steps)
     batch.run_sequential(graph_steps)
-    grouped.run(graph_steps)
+    for gs in grouped.values():
+        gs.run(graph_steps)
     torch.cuda.synchronize()
     out = {}
-    for name, fn in (("sequential", batch.run_sequential), ("concurrent", batch.run), ("grouped", grouped.run)):
+    forms = [("sequential", batch.run_sequential), ("concurrent", batch.run)] + \
+        [("grouped" if g == 1 else f"grouped_{g}_streams", gs.run) for g, gs in grouped.items()]
+    for name, fn in forms:
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         fn(steps)
@@ -572,11 +576,12 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
     out["speedup_grouped"] = out["sequential"]["ms"] / out["grouped"]["ms"]
     out["scans"] = [{"px": s.ny, "n_elem": s.n_elem, "M": s.M, "P": s.P, "patches": s.n_patches, "sos_n": s.sos_n,
                      "ray_tiling": list(t)} for s, t in zip(scans, batch.tilings)]
-    best = min(("concurrent", "grouped"), key=lambda k: out[k]["ms"])
+    best = min((k for k, _ in forms if k != "sequential"), key=lambda k: out[k]["ms"])
     out["fastest"] = best
     out["patches_x_delays_per_s"] = sum(s.n_patches * s.M for s in scans) * steps / (out[best]["ms"] * 1e-3)
     print(f"[bench] batch: {n_scans} scans x {steps} steps: sequential {out['sequential']['ms']:.1f} ms, "
-          f"concurrent streams {out['concurrent']['ms']:.1f} ms, grouped launches {out['grouped']['ms']:.1f} ms",
+          f"concurrent streams {out['concurrent']['ms']:.1f} ms, grouped launches {out['grouped']['ms']:.1f} ms, "
+          f"in 2 groups {out['grouped_2_streams']['ms']:.1f} ms, in 4 groups {out['grouped_4_streams']['ms']:.1f} ms",
           flush=True)
     return out
 

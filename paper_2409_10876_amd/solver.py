@@ -427,12 +427,14 @@ class BatchedSolver:
 
 
 class GroupedBatchSolver:
-    """Independent scans advanced together with one launch per stage over all scans (pact_batch_step): five
-    launches per step for the whole batch instead of five per scan.  Each scan keeps its own buffers (those of
-    its PixelGridSolver) and the partition of work it has alone, so its states equal, bit for bit, those it
-    reaches alone.  Every scan must take the whole-grid or banded adjoint."""
+    """Independent scans advanced together with one launch per stage over all scans of a group
+    (pact_batch_step): five launches per step for the whole group instead of five per scan.  Each scan keeps
+    its own buffers (those of its PixelGridSolver) and the partition of work it has alone, so its states equal,
+    bit for bit, those it reaches alone.  With groups > 1 the scans are dealt to that many groups of about
+    equal work (largest first), each group with its own plan and graph replayed on its own stream, so that one
+    group's stages overlap another's.  Every scan must take the whole-grid or banded adjoint."""
 
-    def __init__(self, solvers, graph_steps: int = 10, autotune: bool = False):
+    def __init__(self, solvers, graph_steps: int = 10, autotune: bool = False, groups: int = 1):
         self.solvers = list(solvers)
         self.graph_steps = graph_steps
         if any(s.ws_adj_bytes == 0 for s in self.solvers):
@@ -444,12 +446,22 @@ class GroupedBatchSolver:
                 s._bufs[0].copy_(s._bufs[s._cur])
                 s._staged[0].copy_(s._staged[s._cur])
                 s._cur = 0
-        self.scans = (pact.BatchScan * len(self.solvers))()
-        for k, s in enumerate(self.solvers):
-            self.scans[k] = self._describe(s)
-        self.plan, self.table = pact.batch_plan(self.scans)
+        work = [s.scan.centres.shape[0] * s.g.n_elem * s.n_samples for s in self.solvers]
+        n_groups = max(1, min(groups, len(self.solvers)))
+        members, load = [[] for _ in range(n_groups)], [0] * n_groups
+        for k in sorted(range(len(self.solvers)), key=lambda k: -work[k]):
+            j = load.index(min(load))
+            members[j].append(k)
+            load[j] += work[k]
+        self.groups = []
+        for ks in members:
+            scans = (pact.BatchScan * len(ks))()
+            for q, k in enumerate(ks):
+                scans[q] = self._describe(self.solvers[k])
+            plan, table = pact.batch_plan(scans)
+            self.groups.append({"members": ks, "scans": scans, "plan": plan, "table": table, "graph": None,
+                                "stream": torch.cuda.Stream()})
         self.parity = 0
-        self.graph = None
         self.step()
         torch.cuda.synchronize()
         self.capture(graph_steps)
@@ -472,37 +484,52 @@ class GroupedBatchSolver:
         d.partial, d.partial_bytes = ptr(s.ws_adj), s.ws_adj.numel()
         return d
 
-    def step(self, with_loss: bool = True):
-        """One step of every scan, enqueued on the current stream."""
-        pact.batch_step(self.plan, self.parity, with_loss)
+    def _flip(self):
         self.parity ^= 1
         for s in self.solvers:
             s._cur = self.parity
 
+    def step(self, with_loss: bool = True):
+        """One step of every scan, every group on the current stream."""
+        for gr in self.groups:
+            pact.batch_step(gr["plan"], self.parity, with_loss)
+        self._flip()
+
     def capture(self, steps: int):
-        """Capture `steps` (even) batched steps into one HIP graph; the scalar losses on the last step only."""
+        """Capture `steps` (even) batched steps of each group into a HIP graph of its own; the scalar losses on
+        the last step only."""
         if steps % 2:
             raise ValueError("capture an even number of steps (the SOS buffers alternate)")
-        g = torch.cuda.CUDAGraph()
-        st = torch.cuda.Stream()
-        st.wait_stream(torch.cuda.current_stream())
         p0 = self.parity
-        with torch.cuda.stream(st):
-            with torch.cuda.graph(g, stream=st):
-                for k in range(steps):
-                    self.step(with_loss=k == steps - 1)
-        torch.cuda.current_stream().wait_stream(st)
+        for gr in self.groups:
+            g = torch.cuda.CUDAGraph()
+            st = torch.cuda.Stream()
+            st.wait_stream(torch.cuda.current_stream())
+            par = p0
+            with torch.cuda.stream(st):
+                with torch.cuda.graph(g, stream=st):
+                    for k in range(steps):
+                        pact.batch_step(gr["plan"], par, k == steps - 1)
+                        par ^= 1
+            torch.cuda.current_stream().wait_stream(st)
+            gr["graph"] = g
         self.parity = p0                      # capturing does not run the steps
         for s in self.solvers:
             s._cur = p0
-        self.graph = g
-        return g
 
     def run(self, steps: int):
-        """Advance every scan by `steps` steps (graph replays where the captured graph divides the count)."""
-        if self.graph is not None and steps % self.graph_steps == 0:
-            for _ in range(steps // self.graph_steps):
-                self.graph.replay()
+        """Advance every scan by `steps` steps: graph replays (each group on its own stream) where the captured
+        graphs divide the count, else eager steps."""
+        if all(gr["graph"] is not None for gr in self.groups) and steps % self.graph_steps == 0:
+            cur = torch.cuda.current_stream()
+            for gr in self.groups:
+                gr["stream"].wait_stream(cur)
+                with torch.cuda.stream(gr["stream"]):
+                    for _ in range(steps // self.graph_steps):
+                        gr["graph"].replay()
+            for gr in self.groups:
+                cur.wait_stream(gr["stream"])
         else:
             for _ in range(steps):
                 self.step()
+

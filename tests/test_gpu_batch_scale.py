@@ -95,14 +95,19 @@ def test_batch_scan_step_matches_oracle(lib, k):
     assert ew < TOL_DELAYS and eg < TOL_GRAD and ea < TOL_GRAD
 
 
-@pytest.mark.parametrize("form", ["streams", "grouped"])
+@pytest.mark.parametrize("form", ["streams", "grouped", "grouped_2"])
 def test_batch_of_real_size_scans_matches_solo(lib, form):
-    """The three scans solved together (their step graphs on their own streams, or one launch per stage over all
-    three) reach the states they reach alone, bit for bit."""
+    """The three scans solved together (their step graphs on their own streams, one launch per stage over all
+    three, or one per stage over each of two groups on their own streams) reach the states they reach alone, bit
+    for bit."""
     P = lib
     announce(f"batched workload: three real-size scans together ({form}) vs alone")
-    cls = P.BatchedSolver if form == "streams" else P.GroupedBatchSolver
-    batch = cls([_setup(P, k)[3] for k in PICKS], graph_steps=2, autotune=True)
+    solvers = [_setup(P, k)[3] for k in PICKS]
+    if form == "streams":
+        batch = P.BatchedSolver(solvers, graph_steps=2, autotune=True)
+    else:
+        batch = P.GroupedBatchSolver(solvers, graph_steps=2, autotune=True, groups=2 if form == "grouped_2" else 1)
+        assert len(batch.groups) == (2 if form == "grouped_2" else 1)
     solo = [_setup(P, k)[3] for k in PICKS]
     for s in solo:
         s.step()                                  # the batch ran one eager step before capturing

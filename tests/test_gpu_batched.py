@@ -55,12 +55,13 @@ def test_batched_matches_solo(lib):
         assert torch.equal(a.sos, b.sos)
 
 
-def test_grouped_launches_match_solo(lib):
-    """One launch per stage over all scans (pact_batch_step) reaches each scan's solo state, bit for bit; the
-    scalar loss of the last step too."""
-    announce("grouped batched step vs solo")
+@pytest.mark.parametrize("groups", [1, 2])
+def test_grouped_launches_match_solo(lib, groups):
+    """One launch per stage over all scans (pact_batch_step), or over each of two groups of scans on their own
+    streams, reaches each scan's solo state, bit for bit; the scalar loss of the last step too."""
+    announce(f"grouped batched step ({groups} groups) vs solo")
     scans = _scans()
-    grouped = lib.GroupedBatchSolver(_solvers(lib, scans), graph_steps=4)
+    grouped = lib.GroupedBatchSolver(_solvers(lib, scans), graph_steps=4, groups=groups)
     solo = _solvers(lib, scans)
     for s in solo:
         s.step()                                  # the grouped solver ran one eager step before capturing
