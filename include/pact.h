@@ -438,8 +438,8 @@ PACT_API int pact_nf_pack(const float* params, int n_freq, int width, unsigned s
  * and w = 0 for rays that miss the disc.  w [N][n_elem].
  * act (optional, DEVICE, pact_nf_activation_bytes() bytes, or NULL): the pass also stores every
  * sample's hidden activations (BF16) and head output, for pact_nf_sos_to_delays_adjoint to use
- * instead of recomputing them (about 1.3 KB per sample, 29 GB for 169 x 512 rays x 256 samples; the
- * last 256 bytes per sample are scratch of the adjoint). */
+ * instead of recomputing them (1.3 KB per sample, 29 GB for 169 x 512 rays x 256 samples; the last
+ * 256 bytes per sample are scratch of the adjoint). */
 PACT_API size_t pact_nf_activation_bytes(int N, const pact_ring* ring, int n_samples);
 PACT_API int pact_nf_sos_to_delays(const float* B, const float* params, const unsigned short* packed, int n_freq,
                           int width, float amp, float mask_radius, float v0, const float* centres, int N,
@@ -453,9 +453,8 @@ PACT_API int pact_nf_sos_to_delays(const float* B, const float* params, const un
  * once; the adjoint writes the layer-1 pre-activation gradients into the buffer's tail and reads them
  * back), or NULL (four passes recompute the forward activations; same result).
  * ws: DEVICE workspace of pact_nf_sos_to_delays_adjoint_workspace_size() bytes (one partial gradient
- * per CU of the current device, plus 16 for the second level of their sum); not shared by two calls in
- * flight.  Partial gradients are combined
- * in a fixed order. */
+ * per CU of the current device, 16 for the second level of their sum, and two partial W1 gradients per
+ * CU); not shared by two calls in flight.  Partial gradients are combined in a fixed order. */
 PACT_API size_t pact_nf_sos_to_delays_adjoint_workspace_size(int n_freq, int width);
 PACT_API int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, const unsigned short* packed,
                                   int n_freq, int width, float amp, float mask_radius, float v0,

@@ -121,10 +121,9 @@ __device__ __forceinline__ NfRay nf_ray(const NfArgs& a, int ray) {
     return r;
 }
 
-// Fourier features of the chunk's points into LDS, point-major (and feature-major if featT).
+// Fourier features of the chunk's points into LDS, point-major.
 // Thread t: point t % 32, frequencies 8 (t / 32) .. + 7.
-__device__ __forceinline__ void nf_features(const NfArgs& a, const NfRay& r, int s0, const float* Bs, __bf16* feat,
-                                            __bf16* featT) {
+__device__ __forceinline__ void nf_features(const NfArgs& a, const NfRay& r, int s0, const float* Bs, __bf16* feat) {
     const int p = threadIdx.x & (kPc - 1);
     const int k0 = (threadIdx.x >> 5) * 8;
     const float t = fmaf(static_cast<float>(s0 + p) + 0.5f, r.dl, r.ta);
@@ -139,12 +138,35 @@ __device__ __forceinline__ void nf_features(const NfArgs& a, const NfRay& r, int
     }
     *reinterpret_cast<bf16x8*>(feat + p * kLd1 + k0) = c8;
     *reinterpret_cast<bf16x8*>(feat + p * kLd1 + kF + k0) = s8;
-    if (featT) {
+}
+
+// Fourier features of a chunk, feature-major only (the layer-1 weight-gradient operand).  Task k of 512:
+// frequency k % 128, points 8 (k / 128) .. + 7.  Along a ray the samples are dl apart, so the phase of
+// a frequency advances by dl (B . u) revolutions per sample: a task takes cos and sin at its first point and
+// the step's cos and sin from the hardware functions, then rotates through the other seven points (four
+// FP32 products per point instead of two hardware calls), and writes each row's eight values at once.
+__device__ __forceinline__ void nf_features_rot(const NfRay& r, int s0, const float* Bs, __bf16* featT) {
+    for (int k = threadIdx.x; k < 4 * kF; k += blockDim.x) {
+        const int f = k & (kF - 1), p0 = 8 * (k >> 7);
+        const float bx = Bs[2 * f], by = Bs[2 * f + 1];
+        float step = r.dl * fmaf(bx, r.ux, by * r.uy);
+        step -= rintf(step);
+        const float cd = __builtin_amdgcn_cosf(step), sd = __builtin_amdgcn_sinf(step);
+        const float t = fmaf(static_cast<float>(s0 + p0) + 0.5f, r.dl, r.ta);
+        float ph = fmaf(bx, fmaf(t, r.ux, r.cx), by * fmaf(t, r.uy, r.cy));
+        ph -= rintf(ph);
+        float c = __builtin_amdgcn_cosf(ph), sn = __builtin_amdgcn_sinf(ph);
+        bf16x8 c8, s8;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            featT[(k0 + j) * kLdT + p] = c8[j];
-            featT[(kF + k0 + j) * kLdT + p] = s8[j];
+            c8[j] = static_cast<__bf16>(c);
+            s8[j] = static_cast<__bf16>(sn);
+            const float cn = fmaf(c, cd, -sn * sd);
+            sn = fmaf(sn, cd, c * sd);
+            c = cn;
         }
+        *reinterpret_cast<bf16x8*>(featT + f * kLdT + p0) = c8;
+        *reinterpret_cast<bf16x8*>(featT + (kF + f) * kLdT + p0) = s8;
     }
 }
 
@@ -250,7 +272,6 @@ struct NfFwdLds {
     alignas(16) __bf16 hA[kPc * kLdH];
     alignas(16) __bf16 hB[kPc * kLdH];
     alignas(16) __bf16 hT[2][kH * kLdT];      // feature-major staging of the activations being stored
-    alignas(16) unsigned onw[4 * kH];         // the chunk's ReLU mask words, stored once per chunk
 };
 
 // Stored activations of one chunk: h1..h4 feature-major, [4][128][32] BF16 (32 KB), chunk = ray * n_chunks + ch.
@@ -346,22 +367,6 @@ __device__ __forceinline__ void nf_head_partial2(const float (&h4)[2][2][4], con
     }
 }
 
-// ReLU masks of a stored layer for the adjoint: one 32-bit word per row of the chunk (bit p: point p is
-// positive), from two wave ballots per row (lane r + 16 q holds rows .. + 4 q + i of point r of each N tile).
-__device__ __forceinline__ void nf_store_on2(const float (&h)[2][2][4], unsigned* words) {
-    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const unsigned long long b0 = __ballot(h[rt][0][i] > 0.0f);
-            const unsigned long long b1 = __ballot(h[rt][1][i] > 0.0f);
-            if (r == i)
-                words[32 * wv + 16 * rt + 4 * q + i] = static_cast<unsigned>((b0 >> (16 * q)) & 0xFFFFull) |
-                                                       (static_cast<unsigned>((b1 >> (16 * q)) & 0xFFFFull) << 16);
-        }
-}
-
 // Copy a feature-major LDS block [128][kLdT] to its stored block, 256 threads x 2 x 16 bytes.
 __device__ __forceinline__ void nf_store_layer256(const __bf16* hT, __bf16* dst) {
 #pragma unroll
@@ -372,7 +377,7 @@ __device__ __forceinline__ void nf_store_layer256(const __bf16* hT, __bf16* dst)
 }
 
 __global__ __launch_bounds__(kNTF, 2) void nf_fwd_kernel(NfArgs a, float* __restrict__ w_out, __bf16* __restrict__ act,
-                                                      float* __restrict__ f_out, unsigned* __restrict__ on_out) {
+                                                      float* __restrict__ f_out) {
     __shared__ NfFwdLds sm;
     load_tables(a, sm.tab);
     bf16x8 w1[2][8], w2[2][4], w3[2][4], w4[2][4];
@@ -394,35 +399,27 @@ __global__ __launch_bounds__(kNTF, 2) void nf_fwd_kernel(NfArgs a, float* __rest
             const int s0 = ch * kPc;
             const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
             __bf16* dst = act ? act + chunk * kActChunk : nullptr;
-            unsigned* on = dst ? on_out + chunk * 4 * kH : nullptr;
             nf_features_p256(r, s0, sm.tab.B, sm.feat);
             __syncthreads();
             f32x4 acc[2][2];
             float h[2][2][4];
             nf_layer2<8>(w1, sm.feat, kLd1, acc);
             nf_activate2(acc, sm.tab.bias[0], sm.hA, dst ? sm.hT[0] : nullptr, h);
-            if (on) nf_store_on2(h, sm.onw + 0 * kH);
             __syncthreads();
             if (dst) nf_store_layer256(sm.hT[0], dst);
             nf_layer2<4>(w2, sm.hA, kLdH, acc);
             nf_activate2(acc, sm.tab.bias[1], sm.hB, dst ? sm.hT[1] : nullptr, h);
-            if (on) nf_store_on2(h, sm.onw + 1 * kH);
             __syncthreads();
             if (dst) nf_store_layer256(sm.hT[1], dst + kH * kPc);
             nf_layer2<4>(w3, sm.hB, kLdH, acc);
             nf_activate2(acc, sm.tab.bias[2], sm.hA, dst ? sm.hT[0] : nullptr, h);
-            if (on) nf_store_on2(h, sm.onw + 2 * kH);
             __syncthreads();
             if (dst) nf_store_layer256(sm.hT[0], dst + 2 * kH * kPc);
             nf_layer2<4>(w4, sm.hA, kLdH, acc);
             nf_activate2(acc, sm.tab.bias[3], sm.hB, dst ? sm.hT[1] : nullptr, h);
-            if (on) nf_store_on2(h, sm.onw + 3 * kH);
             nf_head_partial2(h, sm.tab.w5, sm.headp);
             __syncthreads();
             if (dst) nf_store_layer256(sm.hT[1], dst + 3 * kH * kPc);
-            static_assert(2 * kNTF == 4 * kH, "one pair of mask words per thread");
-            if (on)      // the 4 layers' mask words, one coalesced store (written to LDS before the last barrier)
-                *reinterpret_cast<uint2*>(on + 2 * threadIdx.x) = *reinterpret_cast<const uint2*>(sm.onw + 2 * threadIdx.x);
             if (threadIdx.x < kPc) {
                 const float f = nf_head_sum(sm.headp, threadIdx.x, sm.tab.b5);
                 if (f_out) f_out[chunk * kPc + threadIdx.x] = f;
@@ -535,7 +532,8 @@ __global__ __launch_bounds__(kNT) void nf_bwd_kernel(NfArgs a, const float* __re
         if (r.dl == 0.0f) continue;
         for (int ch = 0; ch < n_chunks; ++ch) {
             const int s0 = ch * kPc;
-            nf_features(a, r, s0, sm.tab.B, sm.feat, LO == 1 ? sm.featT : nullptr);
+            nf_features(a, r, s0, sm.tab.B, sm.feat);
+            if (LO == 1) nf_features_rot(r, s0, sm.tab.B, sm.featT);
             __syncthreads();
             f32x4 acc[2];
             float h[2][4];
@@ -637,12 +635,13 @@ __global__ __launch_bounds__(kNT) void nf_bwd_kernel(NfArgs a, const float* __re
 //      delta_1 (BF16, 8 KB per chunk) into the tail of the activation buffer;
 //   B (4 waves, 32 rows each, so that every B fragment read from LDS feeds two MFMAs): the layer-1 weight
 //      gradient delta_1 gamma^T from the stored delta_1 and recomputed features.
-// So the stored activations are read once, and layer 1's accumulators need no registers in A.  The ReLU
-// masks of a chunk come from the forward pass as one 32-bit word per feature (bit p: point p is positive),
-// so that a lane reads the masks of its four rows in one load.
+// So the stored activations are read once, and layer 1's accumulators need no registers in A.  Pass A
+// forms the ReLU masks of a chunk as one 32-bit word per feature (bit p: point p is positive) from the
+// activations it loads, so that a lane reads the masks of its four rows in one load.
 constexpr int kWavesS = 4;
 constexpr int kNTS = 64 * kWavesS;
 constexpr int kD1Chunk = kH * kPc;     // stored delta_1 of one chunk, feature-major [128][32]
+constexpr int kW1 = kH * kK1;          // entries of W1, the first block of the parameter vector
 
 
 // Value of lane l ^ 1 (l ^ 2) within groups of four lanes, by DPP quad permutes (no LDS traffic).
@@ -656,6 +655,13 @@ __device__ __forceinline__ float quad_sum(float v) {
     v += __int_as_float(static_cast<int>(quad_xor1(static_cast<unsigned>(__float_as_int(v)))));
     v += __int_as_float(static_cast<int>(quad_xor2(static_cast<unsigned>(__float_as_int(v)))));
     return v;
+}
+
+// Bit j: element j of v is positive (v holds ReLU outputs, so positive means a nonzero magnitude).
+__device__ __forceinline__ unsigned positive_bits8(const bf16x8& v) {
+    const uint4 d = __builtin_bit_cast(uint4, v);
+    const auto two = [](unsigned x) { return ((x & 0x7FFFu) ? 1u : 0u) | ((x & 0x7FFF0000u) ? 2u : 0u); };
+    return two(d.x) | (two(d.y) << 2) | (two(d.z) << 4) | (two(d.w) << 6);
 }
 
 struct NfBwdALds {
@@ -726,7 +732,7 @@ __device__ __forceinline__ void put_rows32(float* out, int off, int ld, const f3
 
 __global__ __launch_bounds__(kNT) void nf_bwd_a_kernel(NfArgs a, const __bf16* __restrict__ act,
                                                        const float* __restrict__ f_in,
-                                                       const unsigned* __restrict__ on_in, __bf16* __restrict__ d1,
+                                                       __bf16* __restrict__ d1,
                                                        const float* __restrict__ dL_dw,
                                                        const float* __restrict__ scale, float* __restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) unsigned char nf_dyn[];
@@ -765,28 +771,31 @@ __global__ __launch_bounds__(kNT) void nf_bwd_a_kernel(NfArgs a, const __bf16* _
         if (r.dl == 0.0f) continue;
         bf16x8 nxt[4];
         float fnxt = 0.0f;
-        unsigned onx;                          // mask word threadIdx.x of the chunk ([4][128])
         {
             const size_t chunk0 = static_cast<size_t>(ray) * n_chunks;
             const __bf16* src = act + chunk0 * kActChunk;
 #pragma unroll
             for (int L = 0; L < 4; ++L) nxt[L] = ld8(src + (L * kH + feature) * kPc + 8 * part);
             if (threadIdx.x < kPc) fnxt = f_in[chunk0 * kPc + threadIdx.x];
-            onx = on_in[chunk0 * 4 * kH + threadIdx.x];
         }
         for (int ch = 0; ch < n_chunks; ++ch) {
             const int s0 = ch * kPc;
             const size_t chunk = static_cast<size_t>(ray) * n_chunks + ch;
 #pragma unroll
-            for (int L = 0; L < 4; ++L) *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) = nxt[L];
-            (&sm.on[0][0])[threadIdx.x] = onx;
+            for (int L = 0; L < 4; ++L) {
+                *reinterpret_cast<bf16x8*>(sm.hT[L] + feature * kLdT + 8 * part) = nxt[L];
+                // the ReLU mask word of (L, feature): this lane's 8 points, then the quad's 32
+                unsigned m = positive_bits8(nxt[L]) << (8 * part);
+                m |= quad_xor1(m);
+                m |= quad_xor2(m);
+                if (part == L) sm.on[L][feature] = m;
+            }
             const float fcur = fnxt;
             if (ch + 1 < n_chunks) {
                 const __bf16* src = act + (chunk + 1) * kActChunk;
 #pragma unroll
                 for (int L = 0; L < 4; ++L) nxt[L] = ld8(src + (L * kH + feature) * kPc + 8 * part);
                 if (threadIdx.x < kPc) fnxt = f_in[(chunk + 1) * kPc + threadIdx.x];
-                onx = on_in[(chunk + 1) * 4 * kH + threadIdx.x];
             }
             if (threadIdx.x < kPc) {
                 float d = 0.0f;
@@ -873,31 +882,15 @@ __global__ __launch_bounds__(kNT) void nf_bwd_a_kernel(NfArgs a, const __bf16* _
     }
 }
 
-// Fourier features of a chunk, feature-major only, with 256 threads: thread t takes point t % 32 and
-// frequencies 16 (t / 32) .. + 15 (the same arithmetic as nf_features).
-__device__ __forceinline__ void nf_features_t256(const NfRay& r, int s0, const float* Bs, __bf16* featT) {
-    const int p = threadIdx.x & (kPc - 1);
-    const int k0 = (threadIdx.x >> 5) * 16;
-    const float t = fmaf(static_cast<float>(s0 + p) + 0.5f, r.dl, r.ta);
-    const float px = fmaf(t, r.ux, r.cx), py = fmaf(t, r.uy, r.cy);
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        float ph = fmaf(Bs[2 * (k0 + j)], px, Bs[2 * (k0 + j) + 1] * py);
-        ph -= rintf(ph);
-        featT[(k0 + j) * kLdT + p] = static_cast<__bf16>(__builtin_amdgcn_cosf(ph));
-        featT[(kF + k0 + j) * kLdT + p] = static_cast<__bf16>(__builtin_amdgcn_sinf(ph));
-    }
-}
-
 struct NfBwdBLds {
     float B[2 * kF];
     alignas(16) __bf16 featT[kK1 * kLdT];     // the chunk's features, feature-major
     alignas(16) __bf16 dT[kH * kLdT];         // the chunk's delta_1, feature-major
 };
 
-__global__ __launch_bounds__(kNTS) void nf_bwd_b_kernel(NfArgs a, const __bf16* __restrict__ d1,
-                                                        const float* __restrict__ dL_dw,
-                                                        const float* __restrict__ scale, float* __restrict__ partial) {
+__global__ __launch_bounds__(kNTS, 2) void nf_bwd_b_kernel(NfArgs a, const __bf16* __restrict__ d1,
+                                                           const float* __restrict__ dL_dw,
+                                                           const float* __restrict__ scale, float* __restrict__ w1part) {
     extern __shared__ __attribute__((aligned(16))) unsigned char nf_dyn[];
     NfBwdBLds& sm = *reinterpret_cast<NfBwdBLds*>(nf_dyn);
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
@@ -932,7 +925,7 @@ __global__ __launch_bounds__(kNTS) void nf_bwd_b_kernel(NfArgs a, const __bf16* 
 #pragma unroll
                 for (int h = 0; h < 2; ++h) nxt[h] = ld8(src + (feature + 64 * h) * kPc + 8 * part);
             }
-            nf_features_t256(r, ch * kPc, sm.B, sm.featT);
+            nf_features_rot(r, ch * kPc, sm.B, sm.featT);
             __syncthreads();
             bf16x8 da[2];
 #pragma unroll
@@ -945,22 +938,28 @@ __global__ __launch_bounds__(kNTS) void nf_bwd_b_kernel(NfArgs a, const __bf16* 
             }
         }
     }
-    put_rows32<16>(partial + static_cast<size_t>(blockIdx.x) * kNParams, kPW1, kK1, g1);
+    put_rows32<16>(w1part + static_cast<size_t>(blockIdx.x) * kW1, 0, kK1, g1);
 }
 
 // dL/dparams[j] = sum over workgroups of partial[b][j] in a fixed order, in two levels (kSlices contiguous
 // runs of partials, then the runs) so that many threads read the partials at once.
 constexpr int kSlices = 16;
 
+// The W1 entries come from w1part [n_w1][kW1] when it is given (the stored-activation form's pass B).
 __global__ __launch_bounds__(256) void nf_reduce1_kernel(const float* __restrict__ partial, int n_part,
+                                                        const float* __restrict__ w1part, int n_w1,
                                                         float* __restrict__ part2) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int slice = blockIdx.y;
     if (j >= kNParams) return;
-    const int per = (n_part + kSlices - 1) / kSlices;
-    const int b1 = min((slice + 1) * per, n_part);
+    const bool w1 = w1part && j < kW1;
+    const float* src = w1 ? w1part + j : partial + j;
+    const size_t pitch = w1 ? kW1 : kNParams;
+    const int n = w1 ? n_w1 : n_part;
+    const int per = (n + kSlices - 1) / kSlices;
+    const int b1 = min((slice + 1) * per, n);
     float s = 0.0f;
-    for (int b = slice * per; b < b1; ++b) s += partial[static_cast<size_t>(b) * kNParams + j];
+    for (int b = slice * per; b < b1; ++b) s += src[static_cast<size_t>(b) * pitch];
     part2[static_cast<size_t>(slice) * kNParams + j] = s;
 }
 
@@ -973,9 +972,10 @@ __global__ __launch_bounds__(256) void nf_reduce2_kernel(const float* __restrict
     out[j] = s;
 }
 
-int launch_nf_reduce(const float* partial, int n_part, float* out, hipStream_t st) {
+int launch_nf_reduce(const float* partial, int n_part, const float* w1part, int n_w1, float* out, hipStream_t st) {
     float* part2 = const_cast<float*>(partial) + static_cast<size_t>(n_part) * kNParams;
-    nf_reduce1_kernel<<<dim3(ceil_div(kNParams, 256), kSlices), 256, 0, st>>>(partial, n_part, part2);
+    nf_reduce1_kernel<<<dim3(ceil_div(kNParams, 256), kSlices), 256, 0, st>>>(partial, n_part, w1part, n_w1,
+                                                                              part2);
     if (int s = launch_status("pact_nf_sos_to_delays_adjoint")) return s;
     nf_reduce2_kernel<<<ceil_div(kNParams, 256), 256, 0, st>>>(part2, out);
     return launch_status("pact_nf_sos_to_delays_adjoint");
@@ -1060,26 +1060,26 @@ void set_lds_attr(K kernel, size_t lds) {
                               static_cast<int>(lds));
 }
 
-int launch_bwd_stored(const NfArgs& a, const __bf16* act, const float* f_in, const unsigned* on, __bf16* d1,
-                      const float* dL_dw, const float* scale, float* partial, int blocks, hipStream_t st) {
+// Pass A on `blocks` workgroups (rows of partial), pass B on 2 blocks (rows of w1part: two per CU fit).
+int launch_bwd_stored(const NfArgs& a, const __bf16* act, const float* f_in, __bf16* d1, const float* dL_dw,
+                      const float* scale, float* partial, float* w1part, int blocks, hipStream_t st) {
     static bool attr = false;
     if (!attr) {
         set_lds_attr(nf_bwd_a_kernel, sizeof(NfBwdALds));
         set_lds_attr(nf_bwd_b_kernel, sizeof(NfBwdBLds));
         attr = true;
     }
-    nf_bwd_a_kernel<<<blocks, kNT, sizeof(NfBwdALds), st>>>(a, act, f_in, on, d1, dL_dw, scale, partial);
+    nf_bwd_a_kernel<<<blocks, kNT, sizeof(NfBwdALds), st>>>(a, act, f_in, d1, dL_dw, scale, partial);
     if (int s = launch_status("pact_nf_sos_to_delays_adjoint")) return s;
-    nf_bwd_b_kernel<<<blocks, kNTS, sizeof(NfBwdBLds), st>>>(a, d1, dL_dw, scale, partial);
+    nf_bwd_b_kernel<<<2 * blocks, kNTS, sizeof(NfBwdBLds), st>>>(a, d1, dL_dw, scale, w1part);
     return launch_status("pact_nf_sos_to_delays_adjoint");
 }
 
-// Activation buffer: h1..h4 [chunks][4][128][32] BF16, f [chunks][32] FP32, the ReLU mask words of
-// h1..h4 [chunks][4][128] (bit p: point p positive), then the adjoint's delta_1 [chunks][128][32] BF16.
+// Activation buffer: h1..h4 [chunks][4][128][32] BF16, f [chunks][32] FP32, then the adjoint's delta_1
+// [chunks][128][32] BF16.
 struct NfActView {
     __bf16* h;
     float* f;
-    unsigned* on;
     __bf16* d1;
 };
 
@@ -1088,15 +1088,19 @@ NfActView nf_act_view(void* act, long long n_rays, int n_samples) {
     NfActView v;
     v.h = static_cast<__bf16*>(act);
     v.f = reinterpret_cast<float*>(v.h + chunks * kActChunk);
-    v.on = reinterpret_cast<unsigned*>(v.f + chunks * kPc);
-    v.d1 = reinterpret_cast<__bf16*>(v.on + chunks * 4 * kH);
+    v.d1 = reinterpret_cast<__bf16*>(v.f + chunks * kPc);
     return v;
+}
+
+// Adjoint workspace: one partial gradient per workgroup of pass A (or of the recomputing passes), 16 for the
+// second level of the sum, then pass B's W1 partials, two per CU.
+size_t nf_adjoint_ws_bytes(int cus) {
+    return (static_cast<size_t>(cus + kSlices) * kNParams + static_cast<size_t>(2 * cus) * kW1) * sizeof(float);
 }
 
 size_t nf_activation_bytes(long long n_rays, int n_samples) {
     const long long chunks = n_rays * ((n_samples + kPc - 1) / kPc);
-    return static_cast<size_t>(chunks) * (kActChunk * sizeof(__bf16) + kPc * sizeof(float) + 4 * kH * sizeof(unsigned) +
-                                          kD1Chunk * sizeof(__bf16));
+    return static_cast<size_t>(chunks) * (kActChunk * sizeof(__bf16) + kPc * sizeof(float) + kD1Chunk * sizeof(__bf16));
 }
 
 }  // namespace
@@ -1139,7 +1143,7 @@ extern "C" int pact_nf_sos_to_delays(const float* B, const float* params, const 
     PACT_CHECK_ARG(w, "pact_nf_sos_to_delays: null output");
     const NfArgs a = nf_args(B, params, packed, amp, mask_radius, v0, centres, N, *ring, n_samples);
     const long long n_rays = static_cast<long long>(N) * ring->n_elem;
-    NfActView v = {nullptr, nullptr, nullptr, nullptr};
+    NfActView v = {nullptr, nullptr, nullptr};
     if (act) {
         const size_t need = nf_activation_bytes(n_rays, n_samples);
         if (act_bytes < need) {
@@ -1149,13 +1153,13 @@ extern "C" int pact_nf_sos_to_delays(const float* B, const float* params, const 
         v = nf_act_view(act, n_rays, n_samples);
     }
     const int blocks = static_cast<int>(std::min<long long>(n_rays, 2LL * device_cu_count()));
-    nf_fwd_kernel<<<blocks, kNTF, 0, as_stream(stream)>>>(a, w, v.h, v.f, v.on);
+    nf_fwd_kernel<<<blocks, kNTF, 0, as_stream(stream)>>>(a, w, v.h, v.f);
     return launch_status("pact_nf_sos_to_delays");
 }
 
 extern "C" size_t pact_nf_sos_to_delays_adjoint_workspace_size(int n_freq, int width) {
     if (n_freq != pact::kF || width != pact::kH) return 0;
-    return static_cast<size_t>(pact::device_cu_count() + pact::kSlices) * pact::kNParams * sizeof(float);
+    return pact::nf_adjoint_ws_bytes(pact::device_cu_count());
 }
 
 extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params, const unsigned short* packed,
@@ -1171,7 +1175,7 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
         return s;
     PACT_CHECK_ARG(dL_dw && dL_dparams, "pact_nf_sos_to_delays_adjoint: null pointer");
     const int blocks = device_cu_count();
-    const size_t need = static_cast<size_t>(blocks + kSlices) * kNParams * sizeof(float);
+    const size_t need = nf_adjoint_ws_bytes(blocks);
     if (!ws || ws_bytes < need) {
         set_error("pact_nf_sos_to_delays_adjoint: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
         return PACT_EWORKSPACE;
@@ -1189,8 +1193,9 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
         }
         const NfActView v = nf_act_view(act, n_rays, n_samples);
         // from the stored activations: the head and layers 4..2 (writing delta_1), then layer 1
-        if (int s = launch_bwd_stored(a, v.h, v.f, v.on, v.d1, dL_dw, scale, partial, blocks, st)) return s;
-        return launch_nf_reduce(partial, blocks, dL_dparams, st);
+        float* w1part = partial + static_cast<size_t>(blocks + kSlices) * kNParams;
+        if (int s = launch_bwd_stored(a, v.h, v.f, v.d1, dL_dw, scale, partial, w1part, blocks, st)) return s;
+        return launch_nf_reduce(partial, blocks, w1part, 2 * blocks, dL_dparams, st);
     }
     // four passes, each recomputing the forward activations: layers 3-4 (and the head), layer 2, and the
     // two column halves of layer 1, so that each pass's gradient accumulators fit in registers
@@ -1198,5 +1203,5 @@ extern "C" int pact_nf_sos_to_delays_adjoint(const float* B, const float* params
     if (int s = launch_bwd<2, 2, 0, 0>(a, dL_dw, scale, partial, blocks, st)) return s;
     if (int s = launch_bwd<1, 1, 0, 8>(a, dL_dw, scale, partial, blocks, st)) return s;
     if (int s = launch_bwd<1, 1, 8, 8>(a, dL_dw, scale, partial, blocks, st)) return s;
-    return launch_nf_reduce(partial, blocks, dL_dparams, st);
+    return launch_nf_reduce(partial, blocks, nullptr, 0, dL_dparams, st);
 }

@@ -161,8 +161,8 @@ def test_nf_activation_buffer_too_small(P):
     pt = P.pact
     ring = pt.Ring(512, 110.0, 0.0)
     need = pt.load().pact_nf_activation_bytes(169, ring, 256)
-    # h1..h4, f, the mask words and the adjoint's layer-1 gradients: 32 KB + 128 + 2 KB + 8 KB per 32 samples
-    assert need == 169 * 512 * 8 * (32768 + 128 + 2048 + 8192)
+    # h1..h4, f and the adjoint's layer-1 gradients: 32 KB + 128 + 8 KB per 32 samples
+    assert need == 169 * 512 * 8 * (32768 + 128 + 8192)
     s, msg = _status(P, "pact_nf_sos_to_delays", FAKE, FAKE, FAKE, 128, 128, 0.15, 26.0, 1.5, FAKE, 169, ring, 256,
                      FAKE, FAKE, need - 1, None)
     assert s == -3 and "activation buffer" in msg
