@@ -43,7 +43,14 @@ def test_das_stack(lib, scan):
     assert err < TOL_DAS
 
 
-@pytest.mark.parametrize("scan", WORKLOADS, ids=lambda s: s.name)
+# patch sides for the transform paths: 32 = 4 4 2 and 24 = 4 2 3 (FFT), 45 = 3 3 5 (FFT, odd), 28 = 4 7 (DFT)
+PATCH_CASES = WORKLOADS + [
+    RAGGED.with_(name="ragged_p45", P=45, stride=22, fwhm=synth.configs.fwhm_for_patch(45, 0.25)),
+    RAGGED.with_(name="ragged_p28", P=28, stride=14, fwhm=synth.configs.fwhm_for_patch(28, 0.25)),
+]
+
+
+@pytest.mark.parametrize("scan", PATCH_CASES, ids=lambda s: s.name)
 def test_patch_fft_half_and_full(lib, scan):
     announce(f"patch_fft {scan.name}")
     rng = np.random.default_rng(2)
@@ -59,7 +66,7 @@ def test_patch_fft_half_and_full(lib, scan):
     assert e1 < TOL_SPECTRA and e2 < TOL_SPECTRA
 
 
-@pytest.mark.parametrize("P_", [24, 25, 80])
+@pytest.mark.parametrize("P_", [24, 25, 28, 45, 80, 96])
 def test_ifft2_real(lib, P_):
     announce(f"ifft2_real P={P_}")
     rng = np.random.default_rng(3)
