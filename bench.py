@@ -368,7 +368,7 @@ def precision_leg(P, sd, solver, scan, mask):
     L2 errors over every element (the loss: relative error)."""
     import numpy as np
     import torch
-    from oracle import loss as Oloss, patches as Opatch
+    from oracle import deconv as Odec, loss as Oloss, patches as Opatch, psf as Opsf
     from oracle.geometry import patch_centres
     F64 = torch.float64
     t0 = time.perf_counter()
@@ -387,13 +387,23 @@ def precision_leg(P, sd, solver, scan, mask):
                 px=scan.px, eps=scan.eps)
     ones = np.ones((scan.sos_n, scan.sos_n), dtype=bool)
     L, gv_o, gw_o, w_o = Oloss.loss_and_grad(sos.cpu().to(F64), ones, Y, geom, 0.0)
+    # the transfer functions H (Eq. TF) and the deconvolved spectra X (Eq. multi-deconv), which the step's
+    # fused loss never stores: the standalone entry points against the oracle's, each from its own w
+    d32 = torch.tensor(np.asarray(scan.delays), dtype=torch.float32, device="cuda")
+    H = P.pact.delays_to_psf(w, sd.centres, g, d32)
+    X = torch.empty(sd.centres.shape[0], scan.P, scan.P, dtype=torch.complex64, device="cuda")
+    P.pact.loss_and_grad(sd.Y, w, sd.centres, g, d32, scan.eps, want_grad=False, X=X)
+    torch.cuda.synchronize()
+    H_o = Opsf.transfer_functions(w_o, geom["centres"], scan.radius, scan.phi0, geom["delays"], scan.P, scan.px)
+    X_o = Odec.multichannel_deconv(torch.as_tensor(Y), H_o, scan.eps)
     rel = lambda a, b: (torch.linalg.vector_norm(a.cpu().to(b.dtype) - b) / torch.linalg.vector_norm(b)).item()
     free = torch.as_tensor(np.asarray(mask)).bool()
-    out = {"Y_half": rel(sd.Y, Opatch.half_spectrum(Y)), "w": rel(w, w_o),
+    out = {"Y_half": rel(sd.Y, Opatch.half_spectrum(Y)), "w": rel(w, w_o), "H": rel(H, H_o), "X": rel(X, X_o),
            "loss": abs(loss.item() - L.item()) / abs(L.item()), "dL_dw": rel(gw, gw_o),
            "dL_dsos": rel(gv.cpu()[free], gv_o[free]),
            "measure": "relative L2 over every element (loss: relative error; dL/dsos: over the free nodes, the "
-                      "ones the step updates), FP32 GPU against the FP64 oracle",
+                      "ones the step updates), FP32 GPU against the FP64 oracle; H and X from the standalone "
+                      "entry points (the step's loss forms neither)",
            "support_radius_mm": rho, "state": "the SOS after the timed jobs", "oracle_s": time.perf_counter() - t0}
     print("[bench] precision vs FP64 oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()
                                                            if isinstance(v, float) and k != "oracle_s"), flush=True)
