@@ -82,10 +82,10 @@ def traffic_bytes(stage):
 # copy kernel read as 256 MiB; rocprofv3 counter runs recorded under profiles/), keyed to the kernel source
 # it was taken on.
 TRAFFIC = {
-    "sos_to_delays": {"source": "rays.hip", "sha256_16": "ddee195ffe097f8e", "bytes": 1133448},
-    "loss_and_grad": {"source": "loss.hip", "sha256_16": "ea8f8d36bc036bb4", "bytes": 16832988},
-    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "ddee195ffe097f8e", "bytes": 33797880},
-    "adjoint_tv_adam": {"source": "rays.hip", "sha256_16": "ddee195ffe097f8e", "bytes": 34853730},
+    "sos_to_delays": {"source": "rays.hip", "sha256_16": "7d4719c27ab48eee", "bytes": 1127302},
+    "loss_and_grad": {"source": "loss.hip", "sha256_16": "0fa16bc95a50c044", "bytes": 16833422},
+    "sos_to_delays_adjoint": {"source": "rays.hip", "sha256_16": "7d4719c27ab48eee", "bytes": 33810707},
+    "adjoint_tv_adam": {"source": "rays.hip", "sha256_16": "7d4719c27ab48eee", "bytes": 34861434},
 }
 
 
