@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed for the CPU baseline")
     ap.add_argument("--nf-steps", type=int, default=3, help="neural-field optimisation steps timed (0: skip)")
-    ap.add_argument("--warm-scans", type=int, default=4,
+    ap.add_argument("--warm-scans", type=int, default=100,
                     help="held-out scans of the learned warm-start comparison (0: skip)")
     ap.add_argument("--batch-scans", type=int, default=32,
                     help="also time this many independent uneven scans solved together (0: skip)")
