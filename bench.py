@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # MI355X published FP32 vector peak (it counts packed FP32 instructions); the roofline fractions of the
 # ALU-bound stages are quoted against it.
 FP32_PUBLISHED_PEAK_TFLOPS = 157.3
-# The issue-rate bound of this build, reported beside it: packed FP32 is disabled, so one wave64 FP32 FMA
+# The issue-rate bound of these kernels, reported beside it: packed FP32 is disabled, so one wave64 FP32 FMA
 # per cycle per CU, 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.
 ALU_ISSUE_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 COPY_REF_BYTES = 256 << 20
@@ -171,7 +171,7 @@ PAPER_CONTEXT = {
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np

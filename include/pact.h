@@ -64,7 +64,7 @@ extern "C" {
 #define PACT_EINVAL (-1)        /* invalid argument (null pointer, bad size)      */
 #define PACT_EHIP (-2)          /* HIP runtime or launch error                     */
 #define PACT_EWORKSPACE (-3)    /* workspace missing or smaller than required      */
-#define PACT_EUNSUPPORTED (-4)  /* valid but outside this build's limits           */
+#define PACT_EUNSUPPORTED (-4)  /* valid but outside the library's limits          */
 
 /* Ring array: n_elem elements on a circle of radius `radius` (mm), element 0 at
  * angle phi0 (rad), counter-clockwise. */
