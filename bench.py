@@ -89,16 +89,15 @@ TRAFFIC = {
 }
 
 
-def active_samples(scan, support):
+def active_samples(scan, support, centres):
     """Ray samples (all patches and elements) that can touch a node inside the support disc: those within the
     support radius grown by a cell diagonal, at the midpoints of each ray's part inside the SOS box (all samples
-    without a support).  FP64, from the geometry alone."""
+    without a support).  FP64, from the geometry alone (centres: the scan's patch centres, [N][2])."""
     import numpy as np
-    from oracle.geometry import patch_centres
     total = scan.n_patches * scan.n_elem * scan.n_samples
     if not support > 0:
         return total
-    c = patch_centres(scan.ny, scan.nx, scan.px, scan.P, scan.stride).numpy()
+    c = np.asarray(centres, dtype=np.float64)
     phi = scan.phi0 + 2 * np.pi * np.arange(scan.n_elem) / scan.n_elem
     e = scan.radius * np.stack([np.cos(phi), np.sin(phi)], -1)
     h = 0.5 * (scan.sos_n + 1) * scan.sos_spacing
@@ -271,7 +270,7 @@ def main():
     N, M, Pp = scan.n_patches, scan.M, scan.P
     G2 = scan.sos_n * scan.sos_n
     # the ray samples the method needs: those that can touch a free node (the others add exactly zero)
-    samples = active_samples(scan, solver.support)
+    samples = active_samples(scan, solver.support, sd.centres.cpu().numpy())
     rays_io = N * scan.n_elem * 4
     n_virtual = Pp * (Pp // 2 + 1) + (Pp // 2 - 1 if Pp % 2 == 0 else 0)
     # per stage: (kernels, bound, algorithmic work per launch, unit of the work)
