@@ -30,7 +30,11 @@ def _geom(P, scan):
     return P.geometry_from(scan)
 
 
-@pytest.mark.parametrize("scan", WORKLOADS, ids=lambda s: s.name)
+# coarse pixels (0.5 mm): a 16 x 16 tile's distances to one element span about 280 samples
+DAS_CASES = WORKLOADS + [RAGGED.with_(name="ragged_coarse", ny=90, nx=80, px=0.5)]
+
+
+@pytest.mark.parametrize("scan", DAS_CASES, ids=lambda s: s.name)
 def test_das_stack(lib, scan):
     announce(f"das_stack {scan.name}")
     inp = synth.make_inputs(scan, seed=1)
