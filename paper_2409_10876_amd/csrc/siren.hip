@@ -22,14 +22,19 @@ __device__ __forceinline__ void node_xy(int idx, int Gy, int Gx, float spacing, 
     y = (static_cast<float>(a) - 0.5f * static_cast<float>(Gy - 1)) * spacing * inv_rho;
 }
 
-// Part of w2 . sin(omega0 (W1 (x, y) + b1)) over features k0, k0 + step, ... (parameters in LDS)
+// Part of w2 . sin(omega0 (W1 (x, y) + b1)) over features k0, k0 + step, ... (parameters in LDS).  The sine
+// comes from the hardware unit, which takes revolutions (reduced to [-1/2, 1/2]), as in the adjoint.
 __device__ __forceinline__ float siren_part(const float* p, int H, float omega0, float x, float y, int k0, int step) {
     const float* W1 = p;
     const float* b1 = p + 2 * H;
     const float* w2 = p + 3 * H;
+    const float rev_per_unit = omega0 * (1.0f / kTwoPi);
     float f = 0.0f;
-    for (int k = k0; k < H; k += step)
-        f = fmaf(w2[k], sinf(omega0 * fmaf(W1[2 * k], x, fmaf(W1[2 * k + 1], y, b1[k]))), f);
+    for (int k = k0; k < H; k += step) {
+        float rev = rev_per_unit * fmaf(W1[2 * k], x, fmaf(W1[2 * k + 1], y, b1[k]));
+        rev -= rintf(rev);
+        f = fmaf(w2[k], __builtin_amdgcn_sinf(rev), f);
+    }
     return f;
 }
 
