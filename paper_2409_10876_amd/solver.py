@@ -325,6 +325,7 @@ class SirenSolver:
         self.v = torch.zeros_like(self.params)
         self.t = torch.zeros(2, dtype=torch.int32, device=dev)
         self.sos = torch.empty(g.sos_ny, g.sos_nx, dtype=F32, device=dev)
+        self.staged = torch.empty(pact.staged_contrast_floats(g), dtype=F32, device=dev)
         N = scan.centres.shape[0]
         M = scan.d.numel()
         self.w = torch.empty(N, g.n_elem, dtype=F32, device=dev)
@@ -343,19 +344,21 @@ class SirenSolver:
         self.graph_steps = 0
 
     def sos_grid(self):
+        """The node SOS from the network, and its staged contrast (formed once for both ray kernels)."""
         pact.siren_sos(self.params, self.hidden, self.omega0, self.mask, self.g, self.rho, self.scan.v0,
                        out=self.sos)
+        pact.stage_contrast(self.sos, self.g, self.scan.v0, support=self.support, out=self.staged)
 
     def delays(self):
         pact.sos_to_delays(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, out=self.w,
-                           support=self.support)
+                           support=self.support, staged=self.staged)
 
     def loss_grad(self):
         self.scan.loss_and_grad(self.w, self.eps, loss=self.loss, dL_dw=self.gw, ws=self.ws_loss)
 
     def adjoint(self):
         pact.sos_to_delays_adjoint(self.sos, self.g, self.scan.v0, self.scan.centres, self.n_samples, self.gw,
-                                   out=self.grad_sos, ws=self.ws_adj, support=self.support)
+                                   out=self.grad_sos, ws=self.ws_adj, support=self.support, staged=self.staged)
         pact.siren_sos_adjoint(self.params, self.hidden, self.omega0, self.mask, self.g, self.rho, self.grad_sos,
                                out=self.grad, ws=self.ws_net)
 
