@@ -546,8 +546,9 @@ def siren_leg(P, sd, scan, inp, reps=100, graph_steps=50):
 def batch_leg(P, n_scans, steps=100, graph_steps=10):
     """Independent scans of uneven sizes (256^2 .. 768^2 px, 256 .. 1024 elements, 7 .. 15 delays, 64^2 or
     80^2 patches) solved together, three ways: per-scan step graphs replayed one scan after another, the same
-    graphs on one stream each, and one launch per stage over all scans (five launches per batched step,
-    captured in one graph).  Reports optimisation steps per second summed over the scans."""
+    graphs on one stream each, and one launch per stage over all scans (five launches per batched step, captured
+    in one graph; also over 2 and 4 groups of scans on their own streams).  Reports optimisation steps per second
+    summed over the scans."""
     import numpy as np
     import torch
     import synth
@@ -564,7 +565,8 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
     batch = P.BatchedSolver(solvers, graph_steps=graph_steps, autotune=True)
     print(f"[bench] batch: ray tilings autotuned per scan shape in {time.perf_counter() - t0:.1f} s", flush=True)
     # one launch per stage over all scans, and over each of 2 and 4 groups of scans on their own streams
-    grouped = {g: P.GroupedBatchSolver(solvers, graph_steps=graph_steps, groups=g) for g in (1, 2, 4)}
+    grouped = {("grouped" if g == 1 else f"grouped_{g}_streams"): P.GroupedBatchSolver(solvers, graph_steps=graph_steps,
+                                                                                       groups=g) for g in (1, 2, 4)}
     batch.run(graph_steps)
     batch.run_sequential(graph_steps)
     for gs in grouped.values():
@@ -572,7 +574,7 @@ def batch_leg(P, n_scans, steps=100, graph_steps=10):
     torch.cuda.synchronize()
     out = {}
     forms = [("sequential", batch.run_sequential), ("concurrent", batch.run)] + \
-        [("grouped" if g == 1 else f"grouped_{g}_streams", gs.run) for g, gs in grouped.items()]
+        [(name, gs.run) for name, gs in grouped.items()]
     for name, fn in forms:
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()

@@ -396,6 +396,20 @@ PACT_API int pact_batch_plan(const pact_batch_scan* scans, int n_scans, void* pl
                              size_t table_bytes, void* stream);
 PACT_API int pact_batch_step(const void* plan, int parity, int with_loss, void* stream);
 
+/* pact_batch_step_persistent is SWITCHED OFF: it returns PACT_EUNSUPPORTED and launches nothing (its kernel did
+ * not finish on the GPU for a batch of three small scans, and the cause is not established).  As designed, it
+ * enqueues the same step as ONE launch: a workgroup per CU takes tasks (one block of
+ * one stage of one scan) from a queue held in the table, in an order where every task comes after the tasks it
+ * needs, and starts a task once the stages it reads are complete for its scan (per-scan counters in the table).
+ * A scan's stage therefore starts as soon as its own previous stage ends, not when that stage ends for every
+ * scan; each block runs the same body on the same block number as in pact_batch_step, so the results are the
+ * same, bit for bit.  The kernel returns the counters to zero at its end: steps of one plan must not overlap
+ * (enqueue them on one stream, or in one graph).  PACT_EUNSUPPORTED when the scans' largest stage does not
+ * leave room in a CU's LDS for the kernel's own few bytes.  A wait that has not ended after about a second
+ * gives up (the kernel then ends with wrong results rather than hang); it does not occur while every task's
+ * inputs come from earlier tasks of the same queue, which the plan guarantees. */
+PACT_API int pact_batch_step_persistent(const void* plan, int parity, int with_loss, void* stream);
+
 /* ---- The paper's neural-field SOS: a sinusoidal network on the SOS-grid nodes (Sec. 3.3) ----
  *
  * v[a][b] = v0 + s (w2 . sin(omega0 (W1 (x_b, y_a) + b1)) + b2) + o on the free nodes (mask != 0),

@@ -20,7 +20,10 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpact.so")
 ARCH = os.environ.get("PACT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.hip", "das.hip", "fft.hip", "rays.hip", "psf.hip", "deconv.hip", "loss.hip", "optim.hip", "nf.hip", "stitch.hip", "siren.hip", "convnet.hip", "batch.hip"]
+# rays.hip and loss.hip are compiled inside batch.hip (one translation unit), whose persistent step kernel runs
+# the stage bodies of both
+SOURCES = ["abi.hip", "das.hip", "fft.hip", "psf.hip", "deconv.hip", "optim.hip", "nf.hip", "stitch.hip", "siren.hip",
+           "convnet.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -62,6 +62,7 @@ _SIGS = {
     "pact_batch_table_bytes": (_Z, [_I]),
     "pact_batch_plan": (_I, [_P, _I, _P, _Z, _P, _Z, _P]),
     "pact_batch_step": (_I, [_P, _I, _I, _P]),
+    "pact_batch_step_persistent": (_I, [_P, _I, _I, _P]),
     "pact_last_error": (ctypes.c_char_p, []),
     "pact_version": (_I, []),
     "pact_patch_count": (_I, [_PGRID, _PPATCH, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -731,4 +732,9 @@ def batch_plan(scans):
 def batch_step(plan, parity, with_loss=True):
     _check(load().pact_batch_step(ctypes.cast(plan, ctypes.c_void_p), int(parity), int(bool(with_loss)), _stream()),
            "pact_batch_step")
+
+
+def batch_step_persistent(plan, parity, with_loss=True):
+    _check(load().pact_batch_step_persistent(ctypes.cast(plan, ctypes.c_void_p), int(parity), int(bool(with_loss)),
+                                             _stream()), "pact_batch_step_persistent")
 

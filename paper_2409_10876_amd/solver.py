@@ -435,11 +435,15 @@ class GroupedBatchSolver:
     its own buffers (those of its PixelGridSolver) and the partition of work it has alone, so its states equal,
     bit for bit, those it reaches alone.  With groups > 1 the scans are dealt to that many groups of about
     equal work (largest first), each group with its own plan and graph replayed on its own stream, so that one
-    group's stages overlap another's.  Every scan must take the whole-grid or banded adjoint."""
+    group's stages overlap another's.  With persistent=True each group's step is one launch that takes the
+    stages' blocks from a queue (pact_batch_step_persistent).  Every scan must take the whole-grid or banded
+    adjoint."""
 
-    def __init__(self, solvers, graph_steps: int = 10, autotune: bool = False, groups: int = 1):
+    def __init__(self, solvers, graph_steps: int = 10, autotune: bool = False, groups: int = 1,
+                 persistent: bool = False):
         self.solvers = list(solvers)
         self.graph_steps = graph_steps
+        self._step_fn = pact.batch_step_persistent if persistent else pact.batch_step
         if any(s.ws_adj_bytes == 0 for s in self.solvers):
             raise ValueError("a scan takes the tiled adjoint, which the batched step does not run")
         # ray tilings timed per scan shape before the plan records them
@@ -495,7 +499,7 @@ class GroupedBatchSolver:
     def step(self, with_loss: bool = True):
         """One step of every scan, every group on the current stream."""
         for gr in self.groups:
-            pact.batch_step(gr["plan"], self.parity, with_loss)
+            self._step_fn(gr["plan"], self.parity, with_loss)
         self._flip()
 
     def capture(self, steps: int):
@@ -512,7 +516,7 @@ class GroupedBatchSolver:
             with torch.cuda.stream(st):
                 with torch.cuda.graph(g, stream=st):
                     for k in range(steps):
-                        pact.batch_step(gr["plan"], par, k == steps - 1)
+                        self._step_fn(gr["plan"], par, k == steps - 1)
                         par ^= 1
             torch.cuda.current_stream().wait_stream(st)
             gr["graph"] = g

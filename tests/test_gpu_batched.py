@@ -55,13 +55,20 @@ def test_batched_matches_solo(lib):
         assert torch.equal(a.sos, b.sos)
 
 
-@pytest.mark.parametrize("groups", [1, 2])
-def test_grouped_launches_match_solo(lib, groups):
+PERSISTENT_OFF = pytest.mark.skip(reason="the persistent step is switched off: its launch did not finish on the GPU (cause not established)")
+
+
+@pytest.mark.parametrize("groups,persistent", [(1, False), (2, False),
+                                               pytest.param(1, True, marks=PERSISTENT_OFF),
+                                               pytest.param(2, True, marks=PERSISTENT_OFF)],
+                         ids=["stages_1", "stages_2", "persistent_1", "persistent_2"])
+def test_grouped_launches_match_solo(lib, groups, persistent):
     """One launch per stage over all scans (pact_batch_step), or over each of two groups of scans on their own
-    streams, reaches each scan's solo state, bit for bit; the scalar loss of the last step too."""
-    announce(f"grouped batched step ({groups} groups) vs solo")
+    streams, or the whole step in one persistent launch per group (pact_batch_step_persistent), reaches each
+    scan's solo state, bit for bit; the scalar loss of the last step too."""
+    announce(f"grouped batched step ({groups} groups, persistent={persistent}) vs solo")
     scans = _scans()
-    grouped = lib.GroupedBatchSolver(_solvers(lib, scans), graph_steps=4, groups=groups)
+    grouped = lib.GroupedBatchSolver(_solvers(lib, scans), graph_steps=4, groups=groups, persistent=persistent)
     solo = _solvers(lib, scans)
     for s in solo:
         s.step()                                  # the grouped solver ran one eager step before capturing
