@@ -44,6 +44,7 @@ struct PersistArgs {
     const LossBatchDesc* loss;
     const int* seg_start;         // [n_seg + 1]: the first task of each segment
     const int* seg_code;          // [n_seg]: stage << 16 | scan
+    const int* loss_red;          // [n_scans]: byte offset of the loss body's reduction array in LDS
     int n_seg, n_scans, with_loss;
     int* ctr;                     // [n_scans * kStages] tasks done per scan and stage, then the queue head and
                                   // the count of workgroups that have left
@@ -118,8 +119,7 @@ __global__ __launch_bounds__(kPersistThreads) void batch_persist_kernel(PersistA
             switch (stage) {
                 case kSFwd: rays_fwd_body(R.fwd, b, R.blocks[0], lds); break;
                 case kSLoss: {
-                    const size_t red_off = (loss_lds_bytes(L.a.n_elem, L.a.nvbins) + 15) & ~static_cast<size_t>(15);
-                    float* red = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + red_off);
+                    float* red = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + A.loss_red[s]);
                     loss_proj_body(L.a, b, reinterpret_cast<unsigned long long*>(lds),
                                    *reinterpret_cast<float(*)[kBlock / 64]>(red));
                     break;
@@ -183,7 +183,7 @@ struct BatchPlan {
     int count[kLaunches];           // scans in each launch
     int total[kLaunches];           // blocks of each launch
     size_t lds[kLaunches];          // dynamic LDS of each launch
-    size_t off_seg_start, off_seg_code, off_ctr;   // the persistent form's queue segments and counters
+    size_t off_seg_start, off_seg_code, off_ctr, off_loss_red;   // the persistent form's queue and counters
     int n_seg;
     int persist_grid;               // workgroups of the persistent launch (0: not supported for these scans)
     size_t persist_lds;
@@ -194,7 +194,7 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct TableLayout {
     size_t off_ray[2], off_loss, off_starts[kLaunches], off_ids[kLaunches], off_seg_start, off_seg_code, off_ctr,
-        bytes;
+        off_loss_red, bytes;
 };
 
 TableLayout layout(int n) {
@@ -218,6 +218,8 @@ TableLayout layout(int n) {
     o = align256(o + static_cast<size_t>(n * kStages) * sizeof(int));
     L.off_ctr = o;
     o = align256(o + static_cast<size_t>(n * kStages + 2) * sizeof(int));
+    L.off_loss_red = o;
+    o = align256(o + static_cast<size_t>(n) * sizeof(int));
     L.bytes = o;
     return L;
 }
@@ -335,6 +337,8 @@ extern "C" int pact_batch_plan(const pact_batch_scan* scans, int n_scans, void* 
         order.insert(order.end(), members[kFwdSmall].begin(), members[kFwdSmall].end());
         int* seg_start = reinterpret_cast<int*>(host.data() + L.off_seg_start);
         int* seg_code = reinterpret_cast<int*>(host.data() + L.off_seg_code);
+        int* loss_red = reinterpret_cast<int*>(host.data() + L.off_loss_red);
+        for (int s = 0; s < n_scans; ++s) loss_red[s] = static_cast<int>((st[s].loss_lds + 15) & ~size_t{15});
         int q = 0;
         long long next = 0;
         size_t plds = 0;
@@ -357,6 +361,7 @@ extern "C" int pact_batch_plan(const pact_batch_scan* scans, int n_scans, void* 
         P.off_seg_start = L.off_seg_start;
         P.off_seg_code = L.off_seg_code;
         P.off_ctr = L.off_ctr;
+        P.off_loss_red = L.off_loss_red;
         P.n_seg = q;
         P.persist_lds = plds;
         P.persist_grid = 0;
@@ -434,6 +439,7 @@ extern "C" int pact_batch_step_persistent(const void* plan, int parity, int with
     A.loss = reinterpret_cast<const LossBatchDesc*>(P.table + P.off_loss);
     A.seg_start = reinterpret_cast<const int*>(P.table + P.off_seg_start);
     A.seg_code = reinterpret_cast<const int*>(P.table + P.off_seg_code);
+    A.loss_red = reinterpret_cast<const int*>(P.table + P.off_loss_red);
     A.n_seg = P.n_seg;
     A.n_scans = P.n;
     A.with_loss = with_loss != 0;
