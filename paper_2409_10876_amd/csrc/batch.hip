@@ -49,6 +49,7 @@ struct PersistArgs {
     int* ctr;                     // [n_scans * kStages] tasks done per scan and stage, then the queue head and
                                   // the count of workgroups that have left
     long long wait_ticks;         // kWaitMs in wall-clock ticks
+    int ctl_off;                  // float offset of the kernel's two control words, after every stage's LDS
 };
 
 // Polls counter c until it reaches need (true), or until wait_ticks of the wall clock have passed (false).
@@ -77,8 +78,10 @@ __device__ __forceinline__ void scan_loss_sum(const LossBatchDesc& D, float* red
 }
 
 __global__ __launch_bounds__(kPersistThreads) void batch_persist_kernel(PersistArgs A) {
+    // the stage bodies' LDS starts at 0, as in their own kernels (no static LDS here), and the two control words
+    // (the task taken; whether its inputs are complete) follow the largest of them
     extern __shared__ float lds[];
-    __shared__ int ctl[2];                       // the task taken; whether its inputs are complete
+    int* ctl = reinterpret_cast<int*>(lds + A.ctl_off);
     const int tid = threadIdx.x;
     const int total = A.seg_start[A.n_seg];
     int* head = A.ctr + A.n_scans * kStages;
@@ -187,6 +190,7 @@ struct BatchPlan {
     int n_seg;
     int persist_grid;               // workgroups of the persistent launch (0: not supported for these scans)
     size_t persist_lds;
+    int persist_ctl;                // float offset of the persistent kernel's control words in its LDS
     long long wait_ticks;           // the persistent kernel's bound on a wait, in wall-clock ticks
 };
 
@@ -363,6 +367,8 @@ extern "C" int pact_batch_plan(const pact_batch_scan* scans, int n_scans, void* 
         P.off_ctr = L.off_ctr;
         P.off_loss_red = L.off_loss_red;
         P.n_seg = q;
+        P.persist_ctl = static_cast<int>((plds + 15) / 16 * 4);   // floats, 16-byte aligned
+        plds = static_cast<size_t>(P.persist_ctl) * sizeof(float) + 16;
         P.persist_lds = plds;
         P.persist_grid = 0;
         hipFuncAttributes fa{};
@@ -445,6 +451,7 @@ extern "C" int pact_batch_step_persistent(const void* plan, int parity, int with
     A.with_loss = with_loss != 0;
     A.ctr = reinterpret_cast<int*>(const_cast<char*>(P.table) + P.off_ctr);
     A.wait_ticks = P.wait_ticks;
+    A.ctl_off = P.persist_ctl;
     batch_persist_kernel<<<P.persist_grid, kPersistThreads, P.persist_lds, as_stream(stream)>>>(A);
     return launch_status(what);
 }
