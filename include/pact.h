@@ -396,9 +396,10 @@ PACT_API int pact_batch_plan(const pact_batch_scan* scans, int n_scans, void* pl
                              size_t table_bytes, void* stream);
 PACT_API int pact_batch_step(const void* plan, int parity, int with_loss, void* stream);
 
-/* pact_batch_step_persistent is SWITCHED OFF: it returns PACT_EUNSUPPORTED and launches nothing (its kernel did
- * not finish on the GPU for a batch of three small scans, and the cause is not established).  As designed, it
- * enqueues the same step as ONE launch: a workgroup per CU takes tasks (one block of
+/* pact_batch_step_persistent is SWITCHED OFF: it returns PACT_EUNSUPPORTED and launches nothing (an earlier form
+ * of its kernel did not finish on the GPU: one-thread branches around its task queue let the compiler loop the
+ * other lanes over the same task; the rewritten kernel has not run on the GPU).  As designed, it enqueues the
+ * same step as ONE launch: a workgroup per CU takes tasks (one block of
  * one stage of one scan) from a queue held in the table, in an order where every task comes after the tasks it
  * needs, and starts a task once the stages it reads are complete for its scan (per-scan counters in the table).
  * A scan's stage therefore starts as soon as its own previous stage ends, not when that stage ends for every

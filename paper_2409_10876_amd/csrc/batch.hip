@@ -82,14 +82,20 @@ __global__ __launch_bounds__(kPersistThreads) void batch_persist_kernel(PersistA
     // (the task taken; whether its inputs are complete) follow the largest of them
     extern __shared__ float lds[];
     int* ctl = reinterpret_cast<int*>(lds + A.ctl_off);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // The queue and counter work is done by the whole first wave under wave-uniform branches (one lane's share
+    // of each atomic is 1, the others' 0), never under a one-thread branch: a one-thread branch at the loop's
+    // head and end let the compiler run the task body as an inner loop that the other lanes repeat while the
+    // one thread waits to rejoin them, so the next task was never taken.
+    const bool wave0 = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
     const int total = A.seg_start[A.n_seg];
     int* head = A.ctr + A.n_scans * kStages;
     for (;;) {
-        if (tid == 0) ctl[0] = atomicAdd(head, 1);
+        if (wave0) {
+            const int t = __hip_atomic_fetch_add(head, lane == 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ctl[0] = __builtin_amdgcn_readfirstlane(t);
+        }
         __syncthreads();
-        // read as a workgroup-uniform value, so that the exit test and every barrier below are in uniform control
-        // flow
         const int task = __builtin_amdgcn_readfirstlane(ctl[0]);
         if (task >= total) break;
         int lo = 0, hi = A.n_seg - 1;            // the task's segment: the last one starting at or before it
@@ -104,7 +110,7 @@ __global__ __launch_bounds__(kPersistThreads) void batch_persist_kernel(PersistA
         const RayBatchDesc& R = A.rays[s];
         const LossBatchDesc& L = A.loss[s];
         int* done = A.ctr + s * kStages;
-        if (tid == 0) {
+        if (wave0) {
             const long long wt = A.wait_ticks;
             bool ok = true;
             switch (stage) {
@@ -115,7 +121,7 @@ __global__ __launch_bounds__(kPersistThreads) void batch_persist_kernel(PersistA
                 default: break;
             }
             if (stage != kSFwd) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            ctl[1] = ok;
+            ctl[1] = __builtin_amdgcn_readfirstlane(ok ? 1 : 0);
         }
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(ctl[1])) {
@@ -145,10 +151,10 @@ __global__ __launch_bounds__(kPersistThreads) void batch_persist_kernel(PersistA
                 }
             }
         }
-        // every wave's stores are complete before one thread writes the L2 back and counts the task
+        // every wave's stores are complete before the first wave writes the L2 back and counts the task
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (tid == 0) __hip_atomic_fetch_add(done + stage, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (wave0) __hip_atomic_fetch_add(done + stage, lane == 0 ? 1 : 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     // the last workgroup to leave returns the counters to zero for the next step (no other workgroup reads them
     // any more)
@@ -433,11 +439,11 @@ extern "C" int pact_batch_step_persistent(const void* plan, int parity, int with
     std::memcpy(&P, plan, sizeof P);
     PACT_CHECK_ARG(P.magic == kPlanMagic && P.n > 0, "%s: not a plan made by pact_batch_plan", what);
     PACT_CHECK_ARG(parity == 0 || parity == 1, "%s: parity must be 0 or 1", what);
-    // Switched off: its launch did not finish on the GPU (a small batch of three scans ran past two minutes,
-    // before and after its waits were bounded in time), and the cause is not established; the kernel is kept
-    // for that work and is not launched.
-    PACT_CHECK_SUPPORTED(kPersistEnabled, "%s: the persistent step is switched off (its launch did not finish on "
-                         "the GPU; cause not established); use pact_batch_step", what);
+    // Switched off: an earlier form of the kernel did not finish on the GPU (one-thread branches around the task
+    // queue, which the compiler turned into an inner loop that the other lanes repeated on the same task); the
+    // rewritten kernel has not run on the GPU, so it is not launched.
+    PACT_CHECK_SUPPORTED(kPersistEnabled, "%s: the persistent step is switched off (an earlier form did not finish "
+                         "on the GPU; the rewritten kernel is untested there); use pact_batch_step", what);
     PACT_CHECK_SUPPORTED(P.persist_grid > 0, "%s: the scans' stages need %zu bytes of LDS, too many for one launch",
                          what, P.persist_lds);
     PersistArgs A;

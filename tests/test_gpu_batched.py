@@ -55,7 +55,7 @@ def test_batched_matches_solo(lib):
         assert torch.equal(a.sos, b.sos)
 
 
-PERSISTENT_OFF = pytest.mark.skip(reason="the persistent step is switched off: its launch did not finish on the GPU (cause not established)")
+PERSISTENT_OFF = pytest.mark.skip(reason="the persistent step is switched off: an earlier form did not finish on the GPU and the rewritten kernel is untested there")
 
 
 @pytest.mark.parametrize("groups,persistent", [(1, False), (2, False),
