@@ -204,4 +204,8 @@ def test_batch_argument_errors(P):
     # a buffer that pact_batch_plan did not fill is refused before anything is launched
     s = lib.pact_batch_step(plan, 0, 1, None)
     assert s == -1 and "plan" in lib.pact_last_error().decode()
+    s = lib.pact_batch_step_persistent(plan, 0, 1, None)
+    assert s == -1 and "plan" in lib.pact_last_error().decode()
+    s = lib.pact_batch_step_persistent(None, 0, 1, None)
+    assert s == -1 and "null" in lib.pact_last_error().decode()
 
