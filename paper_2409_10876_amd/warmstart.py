@@ -3,7 +3,8 @@
 The paper's method is self-supervised and needs no training data (Sec. 3.3).  This module adds a small
 convolutional network that maps a scan's delay-and-sum stack (Eq. DAS), averaged down to the SOS node
 grid, to a starting SOS for the plain optimisation of Eq. jr.  The plain optimisation from the uniform
-v0 stays the fallback and the judge of the result: the warm start only changes where it begins.
+v0 stays the fallback and the reference the result is compared with: the warm start only changes where it
+begins.
 
 * ``WarmStartNet``: the network (8 convolutions of 3 x 3, 64 channels, two 2 x 2 poolings, two
   nearest-neighbour doublings with additive skips), BF16 activations on MFMA with FP32 accumulation,
