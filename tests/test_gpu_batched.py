@@ -82,3 +82,27 @@ def test_grouped_launches_match_solo(lib, groups, persistent):
         assert torch.equal(a.sos, b.sos) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
         assert torch.equal(a.w, b.w) and torch.equal(a.gw, b.gw)
         assert abs(a.loss.item() - b.loss.item()) <= 1e-6 * abs(b.loss.item())   # TV's float atomics aside
+
+
+def test_persistent_step_refuses_a_real_plan(lib):
+    """The switched-off persistent step refuses a valid plan with PACT_EUNSUPPORTED before launching anything, and
+    the plan still drives the per-stage step, whose states then match solo runs bit for bit."""
+    announce("persistent batched step refuses a real plan")
+    P = lib
+    scans = _scans()[:2]
+    solvers = _solvers(P, scans)
+    desc = (P.pact.BatchScan * len(solvers))()
+    for q, s in enumerate(solvers):
+        desc[q] = P.GroupedBatchSolver._describe(s)
+    plan, table = P.pact.batch_plan(desc)
+    with pytest.raises(P.pact.PactError, match="status -4.*switched off"):
+        P.pact.batch_step_persistent(plan, 0, True)
+    solo = _solvers(P, scans)
+    P.pact.batch_step(plan, 0, True)
+    for s in solvers:
+        s._cur = 1
+    for s in solo:
+        s.step()
+    torch.cuda.synchronize()
+    for a, b in zip(solvers, solo):
+        assert torch.equal(a.sos, b.sos) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
