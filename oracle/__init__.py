@@ -1,8 +1,9 @@
 """FP64 CPU oracle of the joint SOS/image reconstruction's forward model.
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the reconstruction library imports,
-links or runs this package; only the tests, the smoke check and the CPU
-baseline leg of the benchmark do.  It shares no code with the HIP path:
+links or runs this package; only the tests, the smoke check and the
+measuring legs of the benchmark (its CPU baselines and its precision
+report) do, and none of them feeds a kernel.  It shares no code with the HIP path:
 it computes its own geometry, its own grids and its own sums, in float64
 (numpy for the delay-and-sum stack, torch float64 on the CPU elsewhere so
 that the gradient of the loss is obtained by reverse-mode differentiation,
